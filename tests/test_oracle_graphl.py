@@ -1,0 +1,63 @@
+"""Pins of the float64 graphL oracle (Section "graphL: optimization formulation")."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import graphl
+from paper_2311_00869_amd import synth
+
+
+@pytest.fixture(scope="module")
+def g200():
+    # the finite-difference graph: n = 200, m = 1,000
+    return synth.erdos_renyi_connected(200, 1000, 0.8, 1)
+
+
+def test_loss_at_signs_is_the_frustration_count(g200):
+    # Alg. alg-gradient notes the loss at +1/-1 states is the frustration count
+    rng = np.random.default_rng(0)
+    theta = np.where(rng.random((g200.n, 6)) < 0.5, 1, -1).astype(np.int8)
+    L = graphl.loss(g200, theta.astype(np.float64))
+    for r in range(6):
+        assert L[r] == oracle.count(g200, theta[:, r])
+    assert np.array_equal(graphl.frustration(g200, theta), L.astype(np.int64))
+
+
+def test_central_differences_are_exact(g200):
+    # no self-loops: L is affine in each single G_i, so a central difference
+    # equals the partial derivative up to float64 rounding, for any step h
+    G = synth.graphl_init(g200.n, 3, 5).astype(np.float64)
+    gr = graphl.grad(g200, G)
+    h = 2.0 ** -10
+    for i in [0, 1, 17, 99, 150, 199]:
+        Gp, Gm = G.copy(), G.copy()
+        Gp[i] += h
+        Gm[i] -= h
+        fd = (graphl.loss(g200, Gp) - graphl.loss(g200, Gm)) / (2 * h)
+        np.testing.assert_allclose(fd, gr[i], rtol=0, atol=1e-9)
+
+
+def test_descent_closed_form(g200):
+    # G_{k+1} = G_k + alpha/2 * A G_k, so G_T = (I + alpha A / 2)^T G_0
+    A = graphl.signed_adjacency(g200)
+    G0 = synth.graphl_init(g200.n, 4, 6)
+    alpha, T = 0.001, 200
+    M = np.linalg.matrix_power(np.eye(g200.n) + alpha * A / 2, T)
+    np.testing.assert_allclose(graphl.descent(g200, G0, T, alpha), M @ G0.astype(np.float64),
+                               rtol=1e-12, atol=1e-12)
+
+
+def test_gradient_symmetric_operator(g200):
+    # the Hessian of L is -A/2: <x, grad(y)> - <x, grad(0)> is symmetric in x, y
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((g200.n, 1))
+    y = rng.standard_normal((g200.n, 1))
+    a = float((x * graphl.grad(g200, y)).sum())
+    b = float((y * graphl.grad(g200, x)).sum())
+    assert abs(a - b) < 1e-9 * (abs(a) + 1)
+    assert np.all(graphl.grad(g200, np.zeros((g200.n, 1))) == 0)
+
+
+def test_rounding_threshold_at_zero():
+    G = np.array([[0.0], [-0.0], [1e-30], [-1e-30], [5.0]])
+    assert graphl.round_states(G)[:, 0].tolist() == [1, 1, 1, -1, 1]

@@ -1,0 +1,356 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Nothing here compares the oracle with itself: each test checks it against a
+published test vector, a hand-derived fixture of the paper's Figure
+fig-Balance, a closed form, brute-force enumeration, or an invariant of
+Theorem t:HararyCut / the fundamental-cycle corollary.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.csgraph as csg
+
+import oracle
+from oracle import brute
+from paper_2311_00869_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+M64 = 2**64 - 1
+
+
+# ------------------------------------------------------------ the two mixers
+
+def test_splitmix64_published_vectors():
+    # SplitMix64 reference outputs (Steele, Lea & Flood 2014; the reference C
+    # code distributed with xoshiro): stream seeded with 0 and with 1234567.
+    assert [oracle.tree_salt(0, t) for t in range(3)] == [
+        0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    assert [oracle.tree_salt(1234567, t) for t in range(5)] == [
+        6457827717110365317, 3203168211198807973, 9817491932198370423,
+        4593380528125082431, 16408922859458223821]
+
+
+def _murmur3_x86_32(data: bytes, seed: int) -> int:
+    """MurmurHash3_x86_32 body (Appleby) with the oracle's finalizer as last step."""
+    c1, c2 = 0xCC9E2D51, 0x1B873593
+    rotl = lambda x, r: ((x << r) | (x >> (32 - r))) & 0xFFFFFFFF
+    h = seed & 0xFFFFFFFF
+    nblocks = len(data) // 4
+    for i in range(nblocks):
+        k = int.from_bytes(data[4 * i:4 * i + 4], "little")
+        k = rotl((k * c1) & 0xFFFFFFFF, 15) * c2 & 0xFFFFFFFF
+        h = (rotl(h ^ k, 13) * 5 + 0xE6546B64) & 0xFFFFFFFF
+    tail = data[4 * nblocks:]
+    if tail:
+        k = int.from_bytes(tail, "little")
+        k = rotl((k * c1) & 0xFFFFFFFF, 15) * c2 & 0xFFFFFFFF
+        h ^= k
+    h ^= len(data)
+    return oracle.fmix32(h)
+
+
+def test_fmix32_published_vectors():
+    # MurmurHash3_x86_32 published test vectors.
+    assert _murmur3_x86_32(b"", 0) == 0
+    assert _murmur3_x86_32(b"", 1) == 0x514E28B7
+    assert _murmur3_x86_32(b"", 0xFFFFFFFF) == 0x81F16F39
+    assert _murmur3_x86_32(b"hello", 0) == 613153351
+    assert _murmur3_x86_32(b"The quick brown fox jumps over the lazy dog", 0) == 0x2E4FF723
+
+
+def test_vertex_key_layout():
+    salt = oracle.tree_salt(5, 17)
+    for u in [0, 1, 2, 1000, 2**31 - 1]:
+        k = oracle.vertex_key(salt, u)
+        assert k & (2**31 - 1) == u
+        assert k >> 31 < 2**20
+
+
+# ------------------------------------------------------------ Figure fig-Balance
+
+def _fig():
+    with open(os.path.join(GOLDEN, "figure_balance.json")) as f:
+        return json.load(f)
+
+
+def _tree_arrays(fig, tree):
+    """parent/level arrays of a named spanning tree of the figure, rooted at 0."""
+    adj = {}
+    for k in tree:
+        u, v = fig["edges"][k]
+        adj.setdefault(u, []).append(v)
+        adj.setdefault(v, []).append(u)
+    parent = np.full(4, -1, np.int32)
+    level = np.full(4, -1, np.int32)
+    level[0] = 0
+    todo = [0]
+    while todo:
+        x = todo.pop(0)
+        for y in adj.get(x, []):
+            if level[y] < 0:
+                level[y] = level[x] + 1
+                parent[y] = x
+                todo.append(y)
+    return level, parent
+
+
+def test_figure_balance_all_signings():
+    fig = _fig()
+    order = fig["edge_order"]
+    balanced = 0
+    for bits in range(32):
+        signs = [-1 if (bits >> i) & 1 else 1 for i in range(5)]
+        g = synth.figure_graph(signs)
+        sg = dict(zip(order, signs))
+        c1 = sg["a"] * sg["b"] * sg["e"]
+        c2 = sg["c"] * sg["d"] * sg["e"]
+        cls = f"{c1:+d},{c2:+d}"
+        want = fig["switches_by_cycle_signs"][cls]
+        got = [oracle.balance(g, *_tree_arrays(fig, t))[0] for t in fig["spanning_trees"]]
+        assert got == want, (signs, got, want)
+        fr = brute.frustration_index(g)
+        assert fr == fig["exact_index_by_cycle_signs"][cls]
+        balanced += fr == 0
+        # sampled BFS trees are among the 8 spanning trees: S in the row, min >= Fr
+        res = oracle.sweep(g, seed=3, t0=0, t1=64, checks=True, paper_strings=True)
+        assert set(res.switches.tolist()) <= set(want)
+        assert res.best[0] >= fr
+        assert int(res.cloud[:, 2].sum()) == 64
+    assert balanced == fig["balanced_signings"]
+
+
+# ------------------------------------------------------------ closed forms
+
+@pytest.mark.parametrize("n", [3, 4, 5, 6, 7, 8])
+def test_all_negative_complete_graph(n):
+    # all-negative signs: frustration index = max-cut complement, the number
+    # of edges minus the largest cut floor(n/2)*ceil(n/2); every BFS tree is a
+    # star, leaving the C(n-1, 2) leaf-leaf edges frustrated.
+    g = synth.complete_graph(n, -1)
+    assert brute.frustration_index(g) == math.comb(n, 2) - (n // 2) * ((n + 1) // 2)
+    K = 200
+    res = oracle.sweep(g, seed=11, t0=0, t1=K, checks=True, paper_strings=True)
+    assert np.all(res.switches == math.comb(n - 1, 2))
+    roots = set()
+    for t in range(K):
+        level, parent, _ = oracle.tree(g, 11, t)
+        roots.add(int(np.flatnonzero(level == 0)[0]))
+    assert len(res.cloud) == len(roots)
+    assert int(res.cloud[:, 2].sum()) == K
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_planted_balanced(seed):
+    # Theorem t:HararyCut: a graph whose signs follow a vertex bipartition is
+    # balanced, so every tree gives 0 switches and the same state.
+    g = synth.planted_er(300, 1500, 0.0, seed)
+    K = 50
+    res = oracle.sweep(g, seed=seed, t0=0, t1=K, checks=True)
+    assert np.all(res.switches == 0)
+    assert len(res.cloud) == 1 and int(res.cloud[0, 2]) == K
+    side = g.meta["side"].astype(np.int64)
+    state = np.where(side == side[0], 1, -1).astype(np.int8)
+    words = oracle.canonical_words(g, state)
+    assert (int(res.cloud[0, 0]), int(res.cloud[0, 1])) == oracle.hash128(words)
+    assert res.best == (0, 0)
+
+
+def test_planted_flips_bound():
+    g = synth.planted_er(400, 2400, 0.05, 4)
+    side = g.meta["side"]
+    state = np.where(side == side[0], 1, -1).astype(np.int8)
+    # the planted state frustrates exactly the flipped edges
+    assert oracle.count(g, state) == g.meta["flipped"]
+    res = oracle.sweep(g, seed=1, t0=0, t1=20, checks=True)
+    assert res.best[0] >= 0
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_trees_have_zero_frustration(seed):
+    g = synth.random_tree(60, seed)
+    res = oracle.sweep(g, seed=seed, t0=0, t1=30, checks=True, paper_strings=True)
+    assert np.all(res.switches == 0) and len(res.cloud) == 1
+
+
+@pytest.mark.parametrize("neg", [(), (0,), (0, 3), (1, 2, 5), (0, 1, 2, 3, 4, 5, 6)])
+def test_single_cycle(neg):
+    g = synth.cycle_graph(9, neg)
+    q = len(neg)
+    assert brute.frustration_index(g) == q % 2
+    res = oracle.sweep(g, seed=5, t0=0, t1=40, checks=True, paper_strings=True)
+    assert np.all(res.switches == q % 2)
+
+
+# ------------------------------------------------------------ brute force
+
+@pytest.mark.parametrize("seed", range(8))
+def test_bruteforce_lower_bound(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(6, 17))
+    m = int(rng.integers(n, min(3 * n, n * (n - 1) // 2)))
+    g = synth.random_small(n, m, seed, p_pos=float(rng.uniform(0.2, 0.8)),
+                           connected=bool(seed % 2))
+    fr = brute.frustration_index(g)
+    res = oracle.sweep(g, seed=seed, t0=0, t1=100, checks=True, paper_strings=True)
+    assert np.all(res.switches >= fr)
+    assert res.best[0] >= fr
+    # the best tree state really attains its count
+    assert res.best[0] == int(res.switches.min())
+
+
+def test_bruteforce_n20():
+    g = synth.random_small(20, 45, 99, p_pos=0.6, connected=True)
+    fr = brute.frustration_index(g)
+    res = oracle.sweep(g, seed=0, t0=0, t1=200, checks=True)
+    assert res.best[0] >= fr
+
+
+# ------------------------------------------------------------ trees and invariants
+
+def _scipy_dist(g, sources):
+    A = sp.csr_matrix((np.ones(g.nnz), g.col, g.row_ptr), shape=(g.n, g.n))
+    return csg.shortest_path(A, unweighted=True, indices=sources)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_tree_is_min_key_bfs_forest(seed):
+    g = synth.random_small(80, 120, seed, p_pos=0.7)  # disconnected
+    ncomp, comp = oracle.components(g)
+    _, labels = csg.connected_components(
+        sp.csr_matrix((np.ones(g.nnz), g.col, g.row_ptr), shape=(g.n, g.n)), directed=False)
+    assert ncomp == labels.max() + 1
+    for c in np.unique(comp):
+        assert c == np.flatnonzero(comp == c).min()
+    for t in range(5):
+        level, parent, state = oracle.tree(g, seed, t)
+        salt = oracle.tree_salt(seed, t)
+        keys = np.array([oracle.vertex_key(salt, u) for u in range(g.n)], dtype=np.uint64)
+        roots = np.flatnonzero(level == 0)
+        assert len(roots) == ncomp
+        for r in roots:
+            members = np.flatnonzero(comp == comp[r])
+            assert keys[members].min() == keys[r]
+        dist = _scipy_dist(g, roots).min(axis=0)
+        assert np.array_equal(dist.astype(np.int64), level.astype(np.int64))
+        for v in range(g.n):
+            if level[v] == 0:
+                assert parent[v] == -1 and state[v] == 1
+                continue
+            nb = g.col[g.row_ptr[v]:g.row_ptr[v + 1]]
+            cand = nb[level[nb] == level[v] - 1]
+            assert parent[v] == cand[np.argmin(keys[cand])]
+            e = g.row_ptr[v] + np.flatnonzero(nb == parent[v])[0]
+            assert state[v] == state[parent[v]] * g.sign[e]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_count_invariants(seed):
+    g = synth.random_small(50, 150, seed, p_pos=0.5)
+    ncomp, comp = oracle.components(g)
+    rng = np.random.default_rng(seed)
+    s = np.where(rng.random(g.n) < 0.5, 1, -1).astype(np.int8)
+    c = oracle.count(g, s)
+    assert oracle.count(g, -s) == c          # global flip
+    for anchor in np.unique(comp)[:3]:       # per-component flip
+        s2 = s.copy()
+        s2[comp == anchor] *= -1
+        assert oracle.count(g, s2) == c
+    # per-edge definition: sign * s_u * s_v == -1
+    u, v, sg = g.edges()
+    assert c == int(np.sum(sg.astype(np.int64) * s[u] * s[v] == -1))
+    # canonical words make flipped states equal
+    assert np.array_equal(oracle.canonical_words(g, s), oracle.canonical_words(g, -s))
+
+
+def test_cycle_walk_matches_state_for_every_tree():
+    g = synth.erdos_renyi_connected(200, 900, 0.6, 8)
+    for t in range(10):
+        level, parent, state = oracle.tree(g, 8, t)
+        s_walk, flip = oracle.balance(g, level, parent)
+        assert s_walk == oracle.count(g, state)
+        u = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+        frustrated = g.sign.astype(np.int64) * state[u] * state[g.col] < 0
+        assert np.array_equal(flip.astype(bool), frustrated)
+
+
+def test_hash_distinguishes_states():
+    rng = np.random.default_rng(0)
+    keys = set()
+    for _ in range(2000):
+        w = rng.integers(0, 2**63, size=4, dtype=np.int64).astype(np.uint64)
+        keys.add(oracle.hash128(w))
+    assert len(keys) == 2000
+    z = np.zeros(3, np.uint64)
+    one = z.copy(); one[2] = 1
+    assert oracle.hash128(z) != oracle.hash128(one)
+
+
+def test_sweep_split_equals_whole():
+    g = synth.erdos_renyi_connected(120, 400, 0.7, 3)
+    whole = oracle.sweep(g, 9, 0, 60)
+    a = oracle.sweep(g, 9, 0, 25)
+    b = oracle.sweep(g, 9, 25, 60)
+    merged = {}
+    for part in (a, b):
+        for hi, lo, f, s, t in part.cloud.tolist():
+            if (hi, lo) in merged:
+                F, S, T = merged[(hi, lo)]
+                assert S == s
+                merged[(hi, lo)] = (F + f, S, min(T, t))
+            else:
+                merged[(hi, lo)] = (f, s, t)
+    got = sorted((k[0], k[1], *v) for k, v in merged.items())
+    assert got == [tuple(r) for r in whole.cloud.tolist()]
+    assert np.array_equal(np.concatenate([a.trees, b.trees]), whole.trees)
+
+
+def test_isolated_and_empty():
+    g = synth.isolated_vertices(70)
+    res = oracle.sweep(g, 0, 0, 5)
+    assert np.all(res.switches == 0) and len(res.cloud) == 1
+    assert oracle.components(g)[0] == 70
+
+
+# ------------------------------------------------------------ input contract
+
+def _bad(kind):
+    g = synth.random_small(10, 20, 1, p_pos=0.5, connected=True)
+    rp, col, sg = g.row_ptr.copy(), g.col.copy(), g.sign.copy()
+    if kind == "sign":
+        sg[3] = 0
+    elif kind == "selfloop":
+        v = 2
+        col[rp[v]] = v
+        col[rp[v]:rp[v + 1]] = np.sort(col[rp[v]:rp[v + 1]])
+    elif kind == "dup":
+        v = 4
+        col[rp[v] + 1] = col[rp[v]]
+    elif kind == "unsorted":
+        v = 5
+        seg = col[rp[v]:rp[v + 1]].copy()
+        col[rp[v]:rp[v + 1]] = seg[::-1]
+    elif kind == "asym":
+        e = 7
+        sg[e] = -sg[e]
+    elif kind == "range":
+        col[0] = 99
+    elif kind == "rowptr":
+        rp[3] = rp[4] + 1
+    return synth.SignedCSR(10, rp, col, sg)
+
+
+@pytest.mark.parametrize("kind,code", [("sign", -5), ("selfloop", -3), ("dup", -4),
+                                       ("unsorted", -7), ("asym", -2), ("range", -1),
+                                       ("rowptr", -1)])
+def test_validate_rejects(kind, code):
+    assert oracle.validate(_bad(kind)) == code
+
+
+def test_validate_accepts_generated():
+    for g in [synth.config_small(0), synth.random_small(30, 60, 2), synth.figure_graph([1] * 5),
+              synth.isolated_vertices(5)]:
+        assert oracle.validate(g) == 0
