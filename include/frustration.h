@@ -1,0 +1,247 @@
+/*
+ * frustration.h - C ABI of the MI355X graphBpp sweep and graphL library
+ * (libfrustration.so).
+ *
+ * The operations follow Shebaro & Tesic, "Scaling Frustration Index and
+ * Corresponding Balanced State Discovery for Real Signed Graphs":
+ *   - graphBpp, Alg. alg-index: sample k spanning trees of a signed graph,
+ *     balance the graph on each tree (Alg. alg-balance), count the edge sign
+ *     switches s, key the balanced state, and keep the frustration cloud
+ *     B:(C, S) (Eq. eq-cloud); the approximate frustration index is
+ *     min_i S(i) (Eq. eq-obj);
+ *   - graphL, Eq. eq-loss_imbalance_new, its gradient and Alg. alg-gradient:
+ *     relaxed vertex signs Gamma, loss sum over edges (1 - e_ij G_i G_j)/2,
+ *     plain gradient descent, rounding at zero and an exact frustration count.
+ *
+ * Tree sampler (the paper's best, BFS, Section "Tree-Sampling techniques"),
+ * made reproducible: tree t of a sweep with seed s takes as salt output t of
+ * the SplitMix64 stream seeded with s; vertex u gets the key
+ * (h_t(u), u) with h_t(u) = fmix32(u * (salt_hi | 1) + salt_lo) >> 12
+ * (MurmurHash3 finalizer, 32-bit arithmetic).  The root of every connected
+ * component is its minimum-key vertex, and the parent of every other vertex
+ * is its minimum-key neighbour one BFS level closer to the root.  Vertex
+ * states: root +1, child = parent * sign(tree edge); by Theorem t:HararyCut
+ * this state frustrates exactly the edges Alg. alg-balance flips.  The cloud
+ * key of a state is a 128-bit hash of its canonical form (each component
+ * flipped so that its smallest vertex id is +1).
+ *
+ * Conventions
+ *   - Every function returns FI_OK (0) or a negative FI_E* code.
+ *   - Pointers named d_* are device pointers (HIP device memory of the
+ *     current device); h_* and out_* are host pointers.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls are asynchronous on it unless marked "blocks".
+ *   - The library never allocates device memory.  The caller allocates one
+ *     workspace per graph (size from fi_graph_workspace_size), keeps it alive
+ *     until fi_graph_destroy, and frees it afterwards.  Input CSR buffers are
+ *     read only during fi_graph_create (the workspace keeps what it needs).
+ *   - Errors found by kernels (a full cloud, a BFS deeper than 4094 levels,
+ *     a key collision) are sticky on the handle and returned by the next
+ *     blocking call (fi_graph_status, fi_min_frustration, fi_cloud_read).
+ *   - Results depend only on (graph, seed, tree indices), never on the
+ *     schedule, the stream or how a tree range is split into calls.
+ */
+#ifndef FRUSTRATION_H
+#define FRUSTRATION_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  FI_OK = 0,
+  FI_EINVAL = -1,      /* bad argument, row_ptr not 0..nnz non-decreasing, col out of range */
+  FI_EASYM = -2,       /* an entry u->v without v->u of the same sign ("inconsistencies") */
+  FI_ESELFLOOP = -3,   /* an entry v->v */
+  FI_EDUP = -4,        /* a repeated column in a row */
+  FI_ESIGN = -5,       /* a sign other than +1 / -1 */
+  FI_ERANGE = -6,      /* n or nnz >= 2^31, or a tree index >= 2^32 */
+  FI_EUNSORTED = -7,   /* a row whose columns are not increasing */
+  FI_ECAPACITY = -8,   /* more distinct balanced states than the cloud capacity */
+  FI_EDEVICE = -9,     /* a HIP runtime call failed */
+  FI_EDEPTH = -10,     /* a BFS tree deeper than 4094 levels */
+  FI_ECOLLISION = -11, /* two different states met under one 64-bit key half */
+  FI_EWORKSPACE = -12  /* workspace missing, too small or misaligned (256 B) */
+};
+
+/* Opaque handle: views of the caller's workspace plus host-side settings. */
+typedef struct fi_graph fi_graph;
+
+/* One frustration-cloud entry (Eq. eq-cloud): key of the balanced state B,
+ * its frequency C, its switch count S, and the first tree that produced it. */
+typedef struct {
+  uint64_t key_hi, key_lo;
+  uint64_t freq;
+  uint64_t switches;
+  uint64_t first_tree;
+} fi_cloud_entry;
+
+/* ---------------------------------------------------------------- graph */
+
+/* Bytes of device workspace for a graph with n vertices, nnz CSR entries
+ * (2 per undirected edge) and a cloud of up to cloud_capacity distinct
+ * states.  Pure host arithmetic. */
+int fi_graph_workspace_size(int32_t n, int64_t nnz, int64_t cloud_capacity, size_t* out_bytes);
+
+/* Upload and validate a signed graph (blocks).
+ * Input: symmetric CSR of a simple undirected signed graph - d_row_ptr
+ * int32[n+1] (0 .. nnz, non-decreasing), d_col int32[nnz] (strictly
+ * increasing within each row), d_sign int8[nnz] in {+1, -1}, each edge
+ * present in both directions with one sign.  The paper's input cleaning
+ * (Section "Implementation": duplicates, inconsistencies, self-loops,
+ * invalid signs) is not done here: such inputs are rejected, and when an
+ * input has several defects the first of FI_ERANGE, FI_EINVAL, FI_ESIGN,
+ * FI_ESELFLOOP, FI_EDUP, FI_EUNSORTED, FI_EASYM is returned.  Builds, inside d_workspace (>= fi_graph_workspace_size bytes,
+ * 256-byte aligned): the packed adjacency, the upper-triangle edge list,
+ * connected components with their anchors (smallest vertex id), and an
+ * empty cloud.  On success *out owns host memory only; release it with
+ * fi_graph_destroy. */
+int fi_graph_create(int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int32_t* d_col,
+                    const int8_t* d_sign, int64_t cloud_capacity, void* d_workspace,
+                    size_t ws_bytes, void* stream, fi_graph** out);
+
+/* Release the handle (host memory).  Does not touch the workspace. */
+void fi_graph_destroy(fi_graph* g);
+
+/* Number of connected components, and the number of isolated vertices. */
+int fi_graph_info(fi_graph* g, int32_t* out_components, int32_t* out_isolated);
+
+/* Blocks until the stream is idle; returns the sticky kernel error, if any. */
+int fi_graph_status(fi_graph* g, void* stream);
+
+/* ---------------------------------------------------------------- sweep */
+
+/* Alg. alg-index over trees t = 0 .. K-1: for each tree, build the BFS
+ * spanning forest, propagate states, count the frustrated edges (the
+ * switches s of Alg. alg-balance), hash the canonical state and
+ * insert-or-increment it in the cloud (new: C = 1, S = s; seen: C++).
+ * Accumulates into the current cloud; asynchronous. */
+int fi_sweep(fi_graph* g, int64_t K, uint64_t seed, void* stream);
+
+/* The same for trees t0 .. t1-1 (0 <= t0 <= t1 <= 2^32), so that a sweep can
+ * be split, resumed or sharded with identical results.  If d_tree_switches is
+ * not NULL it receives uint64[t1 - t0], the switch count of each tree. */
+int fi_sweep_range(fi_graph* g, int64_t t0, int64_t t1, uint64_t seed,
+                   uint64_t* d_tree_switches, void* stream);
+
+/* Eq. eq-obj: Fr = min_i S(i) over every tree inserted since the last reset,
+ * and the smallest tree index reaching it (blocks).  FI_EINVAL if empty. */
+int fi_min_frustration(fi_graph* g, uint64_t* out_switches, uint64_t* out_first_tree,
+                       void* stream);
+
+/* Number of distinct states in the cloud (blocks). */
+int fi_cloud_size(fi_graph* g, int64_t* out, void* stream);
+
+/* Copy the cloud to host memory, sorted by (key_hi, key_lo) (blocks).
+ * Writes min(size, cap) entries and sets *written to the cloud size.
+ * FI_ECOLLISION if two different states shared a key half or one key met
+ * two switch counts. */
+int fi_cloud_read(fi_graph* g, fi_cloud_entry* h_out, int64_t cap, int64_t* written,
+                  void* stream);
+
+/* Empty the cloud and the running minimum; clears the sticky error. */
+int fi_cloud_reset(fi_graph* g, void* stream);
+
+/* Re-insert saved entries (a checkpoint from fi_cloud_read) so that a sweep
+ * can resume: entries are merged as if their trees had been swept (freq
+ * added, first tree kept at the minimum).  h_entries is host memory. */
+int fi_cloud_load(fi_graph* g, const fi_cloud_entry* h_entries, int64_t count, void* stream);
+
+/* The canonical state of tree t: n bits as uint64[ceil(n/64)] (vertex v is
+ * bit v%64 of word v/64; set = -1), written to d_bits_out.  Also returns the
+ * tree's switch count in *d_switches_out if not NULL (device pointer). */
+int fi_tree_state(fi_graph* g, uint64_t seed, int64_t t, uint64_t* d_bits_out,
+                  uint64_t* d_switches_out, void* stream);
+
+/* Exact frustration count (the switch count of Alg. alg-index line "s =
+ * edge signs difference count"): for B states given as bitmaps d_bits
+ * uint64[B][ceil(n/64)] (set bit = vertex state -1), d_counts[b] = number of
+ * undirected edges (u, v) with sign(u,v) * s_u * s_v = -1. */
+int fi_count(fi_graph* g, const uint64_t* d_bits, int32_t B, uint64_t* d_counts, void* stream);
+
+/* ---------------------------------------------------------------- graphL */
+
+/* Eq. eq-loss_imbalance_new for R restarts at once: d_gamma float32[n][R]
+ * (restart r is column r), d_loss float64[R] with
+ * L_r = sum over undirected edges (1 - e_ij G_ir G_jr) / 2.
+ * Each edge term is formed in float32 and summed in float64 in a fixed order
+ * (deterministic).  1 <= R <= 64. */
+int fi_graphl_forward(fi_graph* g, const float* d_gamma, int32_t R, double* d_loss, void* stream);
+
+/* Gradient of sum_r w_r L_r: d_grad_gamma[i][r] = -1/2 * w_r * sum over
+ * neighbours j of e_ij G_jr, with w = d_grad_loss float64[R] (NULL = all 1).
+ * One gather per CSR row, no atomics. */
+int fi_graphl_backward(fi_graph* g, const float* d_gamma, int32_t R, const double* d_grad_loss,
+                       float* d_grad_gamma, void* stream);
+
+/* One step of Alg. alg-gradient's update loop for all restarts:
+ * d_gamma_out = d_gamma_in - alpha * dL/dGamma (buffers must not overlap). */
+int fi_graphl_step(fi_graph* g, const float* d_gamma_in, int32_t R, float alpha,
+                   float* d_gamma_out, void* stream);
+
+/* Alg. alg-gradient's final loop: theta = +1 where Gamma >= 0 else -1, then
+ * the exact frustration count of every restart: d_counts uint64[R].
+ * d_bits_out (uint64[R][ceil(n/64)], set = -1) receives the rounded states
+ * if not NULL. */
+int fi_round_count(fi_graph* g, const float* d_gamma, int32_t R, uint64_t* d_counts,
+                   uint64_t* d_bits_out, void* stream);
+
+/* ---------------------------------------------------------------- batches */
+
+/* Many independent graphs swept in one launch (Alg. alg-index per graph).
+ * The graphs are concatenated: graph i has vertices
+ * h_vertex_offsets[i] .. h_vertex_offsets[i+1]-1 and CSR entries
+ * h_nnz_offsets[i] .. h_nnz_offsets[i+1]-1; d_row_ptr int32[total_n + G]
+ * holds each graph's own row_ptr (local, starting at 0) back to back, and
+ * d_col holds local column ids.  Each graph must satisfy the
+ * fi_graph_create contract on its own.  Only the minimum and per-graph
+ * statistics are kept (no cloud). */
+int fi_batch_workspace_size(int32_t G, const int64_t* h_vertex_offsets, const int64_t* h_nnz_offsets,
+                            size_t* out_bytes);
+int fi_batch_create(int32_t G, const int64_t* h_vertex_offsets, const int64_t* h_nnz_offsets,
+                    const int32_t* d_row_ptr, const int32_t* d_col, const int8_t* d_sign,
+                    void* d_workspace, size_t ws_bytes, void* stream, fi_graph** out);
+
+/* Trees t = 0 .. trees_per_graph-1 of every graph (all graphs use `seed`).
+ * d_min_per_graph uint64[G][2]: (minimum switches, first tree reaching it),
+ * d_distinct_per_graph (may be NULL) uint64[G]: number of distinct states
+ * among the graph's trees.  Asynchronous. */
+int fi_batch_sweep(fi_graph* b, int64_t trees_per_graph, uint64_t seed, uint64_t* d_min_per_graph,
+                   uint64_t* d_distinct_per_graph, void* stream);
+
+/* ---------------------------------------------------------------- schedule */
+
+/* How a sweep is laid on the GPU.  Every schedule gives bit-identical
+ * results; fi_set_schedule only changes speed.  path: 0 = automatic,
+ * 1 = one workgroup per tree with the tree state in LDS (n <= 12,000),
+ * 2 = one workgroup per tree with the tree state in workspace memory
+ * (n <= 1,000,000), 3 = the whole grid per tree (persistent cooperative
+ * kernel, any n).  block: threads per workgroup (256, 512 or 1024);
+ * grid: workgroups (0 = fill the GPU); heavy: degree above which a
+ * frontier vertex is expanded by several workgroups (path 3). */
+typedef struct {
+  int32_t path;
+  int32_t block;
+  int32_t grid;
+  int32_t heavy;
+} fi_schedule;
+
+int fi_set_schedule(fi_graph* g, const fi_schedule* s);
+int fi_get_schedule(fi_graph* g, fi_schedule* out);
+
+/* Kernel timing with HIP events recorded on the launch stream around every
+ * launch of the sweep kernel (0) and the count kernel (1).  Enable, run,
+ * then read: fi_prof_read blocks and returns the summed milliseconds and the
+ * number of launches since the last enable. */
+int fi_prof_enable(fi_graph* g, int on);
+int fi_prof_read(fi_graph* g, int kernel, double* out_ms, int64_t* out_launches);
+
+const char* fi_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FRUSTRATION_H */

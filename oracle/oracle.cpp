@@ -356,10 +356,11 @@ int orc_validate(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* 
         for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e)
             if (col[e] == v) return ORC_ESELFLOOP;
     for (int32_t v = 0; v < n; ++v)
-        for (int64_t e = row_ptr[v] + 1; e < row_ptr[v + 1]; ++e) {
+        for (int64_t e = row_ptr[v] + 1; e < row_ptr[v + 1]; ++e)
             if (col[e] == col[e - 1]) return ORC_EDUP;
+    for (int32_t v = 0; v < n; ++v)
+        for (int64_t e = row_ptr[v] + 1; e < row_ptr[v + 1]; ++e)
             if (col[e] < col[e - 1]) return ORC_EUNSORTED;
-        }
     Graph g{n, row_ptr, col, sign};
     for (int32_t u = 0; u < n; ++u)
         for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e)

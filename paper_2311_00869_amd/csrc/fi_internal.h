@@ -1,0 +1,219 @@
+// Internal declarations of libfrustration: device helpers, the workspace
+// layout and the host-side handle.  Everything here is the HIP path's own;
+// nothing is shared with the CPU oracle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "frustration.h"
+
+struct fi_graph;
+
+namespace fi {
+
+// ----------------------------------------------------------------- mixers
+// SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): a Weyl sequence with
+// increment 0x9E3779B97F4A7C15 read through a 64-bit finalizer.  `mix64(x)`
+// is the value returned when the generator's state before the call is x.
+constexpr uint64_t kWeyl = 0x9E3779B97F4A7C15ull;
+
+__host__ __device__ __forceinline__ uint64_t mix64(uint64_t x) {
+  x += kWeyl;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+// MurmurHash3's 32-bit finalizer (Appleby, public domain).
+__host__ __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85EBCA6Bu;
+  h ^= h >> 13;
+  h *= 0xC2B2AE35u;
+  h ^= h >> 16;
+  return h;
+}
+
+// Tree t of a sweep seeded with s: salt = output t of SplitMix64 seeded s.
+__host__ __device__ __forceinline__ uint64_t tree_salt(uint64_t seed, uint64_t t) {
+  return mix64(seed + t * kWeyl);
+}
+
+// Per-tree vertex hash: 20 high bits of fmix32(u * (salt_hi | 1) + salt_lo).
+struct KeyMix {
+  uint32_t mul, add;
+};
+__host__ __device__ __forceinline__ KeyMix key_mix(uint64_t salt) {
+  return KeyMix{(uint32_t)(salt >> 32) | 1u, (uint32_t)salt};
+}
+__device__ __forceinline__ uint32_t vhash20(KeyMix k, uint32_t u) {
+  return fmix32(u * k.mul + k.add) >> 12;
+}
+
+// ----------------------------------------------------------------- tree words
+// One 64-bit word per vertex carries the BFS level (12 bits), the parent's
+// hash (20 bits) and id (31 bits) and the vertex's state bit (1 = state -1):
+//   level << 52 | hash << 32 | parent << 1 | bit.
+// Unsigned order is (level, parent key), so an atomic minimum keeps the
+// earliest level and, within it, the minimum-key parent; words of earlier
+// levels are never overwritten.  All ones = not reached yet.
+constexpr uint64_t kUnvisited = ~0ull;
+constexpr uint32_t kMaxLevel = 4094;
+
+__device__ __forceinline__ uint64_t tree_word(uint32_t level, uint32_t h20, uint32_t u,
+                                              uint32_t bit) {
+  return ((uint64_t)level << 52) | ((uint64_t)h20 << 32) | ((uint64_t)u << 1) | bit;
+}
+__device__ __forceinline__ uint32_t word_vertex(uint64_t w) {
+  return (uint32_t)(w >> 1) & 0x7FFFFFFFu;
+}
+// Candidate word used to pick a component's root: same order as tree_word at
+// level 0 (hash, then id).
+__device__ __forceinline__ uint64_t root_candidate(uint32_t h20, uint32_t u) {
+  return ((uint64_t)h20 << 32) | ((uint64_t)u << 1);
+}
+
+// Packed adjacency entry: neighbour id in the low 31 bits, bit 31 set for a
+// negative edge.
+constexpr uint32_t kVertexMask = 0x7FFFFFFFu;
+
+// ----------------------------------------------------------------- state keys
+// 128-bit key of a canonical state, as two independent sums mod 2^64 of
+// mix64(mix64(i + K) ^ W_i) over the state's 64-bit words W_i.
+constexpr uint64_t kKeyHi = 0x243F6A8885A308D3ull;  // pi, hex digits 1-16
+constexpr uint64_t kKeyLo = 0x13198A2E03707344ull;  // pi, hex digits 17-32
+
+__device__ __forceinline__ void key_terms(uint64_t i, uint64_t w, uint64_t& hi, uint64_t& lo) {
+  hi += mix64(mix64(i + kKeyHi) ^ w);
+  lo += mix64(mix64(i + kKeyLo) ^ w);
+}
+
+// ----------------------------------------------------------------- cloud
+// Open addressing on key_lo (linear probing).  Every field is updated with a
+// commutative atomic, so the table contents never depend on insertion order;
+// readout checks that each slot saw one key_hi and one switch count.
+struct CloudSlot {
+  uint64_t tag;        // key_lo, or kEmpty
+  uint64_t khi_min, khi_max;
+  uint64_t s_min, s_max;
+  uint64_t freq;
+  uint64_t first;      // smallest tree index
+  uint64_t pad;
+};
+constexpr uint64_t kEmpty = ~0ull;
+
+// ----------------------------------------------------------------- control
+// uint64 words of the per-graph control block.
+enum : int {
+  C_ERR = 0,        // sticky error bits (E_*)
+  C_BEST = 1,       // min over trees of (switches << 32 | tree)
+  C_COUNT = 2,      // occupied cloud slots
+  C_TREES = 3,      // trees inserted
+  C_NCOMP = 4,      // components (create)
+  C_NISO = 5,       // isolated vertices (create)
+  C_NANCH = 6,      // anchors of non-trivial components (create)
+  C_FLAGS = 7,      // validation flags (create)
+  C_BAR = 16,       // grid barrier: arrivals (own 128-byte line)
+  C_GEN = 32,       // grid barrier: generation (own line)
+  C_ACC = 48,       // tree accumulators: switches, key_hi, key_lo
+  C_RING = 64,      // per-level frontier counters, 4 slots x 4 words
+  C_UNIT = 96,      // per-block work-unit ticket broadcast (unused on host)
+  C_WORDS = 128
+};
+enum : uint64_t { E_CAPACITY = 1, E_DEPTH = 2, E_COLLISION = 4 };
+
+// validation flags set by the create kernels
+enum : uint32_t {
+  V_ROWPTR = 1, V_RANGE = 2, V_SIGN = 4, V_SELF = 8, V_DUP = 16, V_UNSORTED = 32, V_ASYM = 64
+};
+
+// ----------------------------------------------------------------- device view
+struct DevGraph {
+  int32_t n;
+  int32_t nwords;       // ceil(n / 64)
+  int64_t nnz;
+  int64_t m;            // undirected edges
+  const int32_t* row_ptr;   // [n+1]
+  const uint32_t* adj;      // [nnz] packed neighbour | neg << 31
+  const uint2* edges;       // [m] (u, v | neg << 31), u < v
+  const int32_t* comp;      // [n] anchor (smallest id) of the component
+  const int32_t* word_comp; // [nwords] anchor shared by the word's non-isolated
+                            // vertices, -1 if mixed, -2 if none
+  const uint64_t* word_mask;// [nwords] non-isolated vertices of the word
+  const int32_t* anchors;   // [C] anchors of components with an edge
+  CloudSlot* cloud;
+  uint64_t cloud_mask;      // table size - 1
+  uint64_t cloud_cap;       // user capacity (distinct states)
+  uint64_t* ctl;            // [C_WORDS]
+};
+
+// Per-call sweep arguments.
+struct SweepArgs {
+  uint64_t seed;
+  uint64_t t0, t1;
+  uint64_t* tree_switches;  // [t1 - t0] or null
+  uint64_t* bits_out;       // canonical words of the single tree, or null
+  int insert;               // 0: compute only, leave the cloud alone
+  // scratch for the tree state
+  uint64_t* pw;             // path 2: [slots][stride]; path 3: [n]
+  int32_t* q;               // path 2: [slots][stride]; path 3: frontier lists
+  size_t slot_stride;       // elements per slot (path 2)
+  // path 3 extras
+  int32_t* ql[2];
+  int2* qh[2];
+  uint64_t* vis;
+  uint64_t* st;
+  uint64_t* rootkey;        // [n], indexed by anchor, kept at kUnvisited
+  int32_t heavy;            // degree above which a vertex is split into units
+  int32_t nanch;
+};
+
+// ----------------------------------------------------------------- layout
+struct Layout {
+  size_t row_ptr, adj, edges, comp, word_comp, word_mask, anchors, tmp, cloud, ctl;
+  size_t rootkey, pw, q0, q1, qh0, qh1, vis, st, gl;
+  size_t slots;        // path-2 tree scratch
+  size_t nslots, slot_stride;
+  size_t total;
+};
+
+Layout make_layout(int32_t n, int64_t nnz, int64_t cloud_capacity, uint64_t table_size);
+uint64_t table_size_for(int64_t cloud_capacity);
+
+constexpr int kGraphLMaxR = 64;
+constexpr int kGraphLBlocks = 1024;
+
+// profiling events around one launch (no-ops unless profiling is on)
+int prof_begin(fi_graph* g, hipStream_t s, void** token);
+void prof_end(fi_graph* g, hipStream_t s, void* token, int kernel);
+
+// launchers implemented in the .hip files
+hipError_t launch_sweep(fi_graph* g, const SweepArgs& a, hipStream_t s);
+hipError_t launch_count(const DevGraph& dg, const uint64_t* bits, int32_t B, uint64_t* counts,
+                        hipStream_t s);
+
+}  // namespace fi
+
+// ----------------------------------------------------------------- host handle
+struct fi_graph {
+  fi::DevGraph dg;
+  fi::Layout L;
+  char* ws;
+  size_t ws_bytes;
+  int64_t cloud_capacity;
+  uint64_t table_size;
+  int32_t ncomp, nisolated, nanch;
+  fi_schedule sched;
+  int cu_count;
+  int max_shared;
+  // profiling
+  bool prof;
+  double prof_ms[2];
+  int64_t prof_n[2];
+  void* prof_events;  // std::vector of pending (start, stop, kernel)
+  // batch mode
+  bool is_batch;
+  void* batch;        // fi::BatchInfo*
+};

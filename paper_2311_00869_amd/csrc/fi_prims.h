@@ -1,0 +1,182 @@
+// Wavefront (64 lanes) and workgroup primitives shared by the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fi_internal.h"
+
+namespace fi {
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// Number of set bits of `mask` in lanes below this one.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) x += __shfl_xor(x, d);
+  return x;
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) {
+    uint64_t y = __shfl_xor(x, d);
+    x = y < x ? y : x;
+  }
+  return x;
+}
+
+__device__ __forceinline__ int wave_min_i32(int x) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) x = min(x, __shfl_xor(x, d));
+  return x;
+}
+
+__device__ __forceinline__ int wave_max_i32(int x) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) x = max(x, __shfl_xor(x, d));
+  return x;
+}
+
+// Wave-aggregated append: lanes with `pred` write `val` to consecutive slots
+// of `list`, reserved with one atomicAdd on `counter` per wave.
+__device__ __forceinline__ void wave_append(bool pred, int32_t val, int32_t* list,
+                                            uint32_t* counter) {
+  uint64_t mask = __ballot(pred);
+  if (mask == 0) return;
+  int leader = __ffsll((unsigned long long)mask) - 1;
+  uint32_t base = 0;
+  if (lane_id() == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
+  base = __shfl(base, leader);
+  if (pred) list[base + lanes_below(mask)] = val;
+}
+
+// Exclusive prefix sum over the workgroup.  `s_tmp` needs NT/64 + 1 ints of
+// LDS.  Returns this thread's exclusive prefix; `total` gets the block sum.
+// Ends with a barrier; callers may reuse s_tmp only after another barrier.
+template <int NT>
+__device__ __forceinline__ int block_exclusive_scan(int x, int& total, int* s_tmp) {
+  constexpr int NW = NT / 64;
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  int inc = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int y = __shfl_up(inc, d);
+    if (lane >= d) inc += y;
+  }
+  if (lane == 63) s_tmp[w] = inc;
+  __syncthreads();
+  if (w == 0) {
+    int v = lane < NW ? s_tmp[lane] : 0;
+    int iv = v;
+#pragma unroll
+    for (int d = 1; d < NW; d <<= 1) {
+      int y = __shfl_up(iv, d);
+      if (lane >= d) iv += y;
+    }
+    if (lane < NW) s_tmp[lane] = iv - v;
+    if (lane == NW - 1) s_tmp[NW] = iv;
+  }
+  __syncthreads();
+  total = s_tmp[NW];
+  return inc - x + s_tmp[w];
+}
+
+// Sum over the workgroup, valid in thread 0.  `s_tmp` needs NT/64 words.
+template <int NT>
+__device__ __forceinline__ uint64_t block_sum_u64(uint64_t x, uint64_t* s_tmp) {
+  x = wave_sum_u64(x);
+  if (lane_id() == 0) s_tmp[threadIdx.x >> 6] = x;
+  __syncthreads();
+  uint64_t r = 0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) r += s_tmp[i];
+  }
+  __syncthreads();
+  return r;
+}
+
+// Largest k in [0, len) with a[k] <= x, for a non-decreasing a with a[0] <= x.
+__device__ __forceinline__ int upper_index(const int* a, int len, int x) {
+  int lo = 0, hi = len;  // answer in [lo, hi)
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (a[mid] <= x) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ uint64_t load_agent(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t load_agent_i32(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid-wide barrier for a cooperative launch (all workgroups co-resident).
+// Arrival counter and generation live in separate cache lines of the
+// control block; the generation is read before arriving so the release by
+// the last workgroup cannot be missed.  Agent-scope fences on both sides make
+// every store before the barrier visible to every load after it.
+__device__ __forceinline__ void grid_barrier(uint64_t* ctl, uint32_t nblocks) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t* bar = ctl + C_BAR;
+    uint64_t* gen = ctl + C_GEN;
+    uint64_t g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    uint64_t arrived = __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == nblocks - 1) {
+      __hip_atomic_store(bar, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(gen, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g)
+        __builtin_amdgcn_s_sleep(1);
+    }
+    __threadfence();
+  }
+  __syncthreads();
+}
+
+// Insert one tree's result into the cloud (single thread).  New key: the
+// first claimer of a slot sets its tag; every inserter then folds its fields
+// in with commutative atomics.
+__device__ __forceinline__ void cloud_insert(const DevGraph& G, uint64_t khi, uint64_t klo,
+                                             uint64_t S, uint64_t t) {
+  if (klo == kEmpty) {  // reserved tag value
+    atomicOr((unsigned long long*)(G.ctl + C_ERR), (unsigned long long)E_COLLISION);
+    return;
+  }
+  uint64_t idx = klo & G.cloud_mask;
+  for (uint64_t probe = 0; probe <= G.cloud_mask; ++probe) {
+    CloudSlot* s = G.cloud + idx;
+    uint64_t old = atomicCAS((unsigned long long*)&s->tag, (unsigned long long)kEmpty,
+                             (unsigned long long)klo);
+    if (old == kEmpty || old == klo) {
+      if (old == kEmpty) {
+        uint64_t c = atomicAdd((unsigned long long*)(G.ctl + C_COUNT), 1ull);
+        if (c + 1 > G.cloud_cap)
+          atomicOr((unsigned long long*)(G.ctl + C_ERR), (unsigned long long)E_CAPACITY);
+      }
+      atomicMin((unsigned long long*)&s->khi_min, (unsigned long long)khi);
+      atomicMax((unsigned long long*)&s->khi_max, (unsigned long long)khi);
+      atomicMin((unsigned long long*)&s->s_min, (unsigned long long)S);
+      atomicMax((unsigned long long*)&s->s_max, (unsigned long long)S);
+      atomicAdd((unsigned long long*)&s->freq, 1ull);
+      atomicMin((unsigned long long*)&s->first, (unsigned long long)t);
+      atomicAdd((unsigned long long*)(G.ctl + C_TREES), 1ull);
+      atomicMin((unsigned long long*)(G.ctl + C_BEST), (unsigned long long)((S << 32) | t));
+      return;
+    }
+    idx = (idx + 1) & G.cloud_mask;
+  }
+  atomicOr((unsigned long long*)(G.ctl + C_ERR), (unsigned long long)E_CAPACITY);
+}
+
+}  // namespace fi

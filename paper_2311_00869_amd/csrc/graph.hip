@@ -1,0 +1,747 @@
+// Graph upload, validation, connected components, the cloud table and its
+// readout, the exact frustration counter over given states, schedules,
+// profiling and error strings.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "fi_internal.h"
+#include "fi_prims.h"
+
+namespace fi {
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+inline int grid_for(int64_t work, int block, int cap = 65536) {
+  int64_t g = (work + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+// ------------------------------------------------------------ validation
+// Row of CSR entry e: the largest u < n with row_ptr[u] <= e.
+__device__ __forceinline__ int32_t row_of(const int32_t* rp, int32_t n, int64_t e) {
+  int32_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    int32_t mid = lo + ((hi - lo) >> 1);
+    if ((int64_t)rp[mid] <= e) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void k_check_rowptr(const int32_t* rp, int32_t n, int64_t nnz, uint64_t* ctl) {
+  uint32_t bad = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (rp[i + 1] < rp[i]) bad = 1;
+    if (i == 0 && (rp[0] != 0 || (int64_t)rp[n] != nnz)) bad = 1;
+  }
+  if (n == 0 && blockIdx.x == 0 && threadIdx.x == 0 && (rp[0] != 0 || nnz != 0)) bad = 1;
+  if (bad) atomicOr((unsigned long long*)(ctl + C_FLAGS), (unsigned long long)V_ROWPTR);
+}
+
+__global__ void k_check_entries(const int32_t* rp, const int32_t* col, const int8_t* sign,
+                                int32_t n, int64_t nnz, uint64_t* ctl) {
+  uint32_t f = 0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int32_t u = row_of(rp, n, e);
+    int32_t v = col[e];
+    int s = sign[e];
+    if (v < 0 || v >= n) { f |= V_RANGE; continue; }
+    if (s != 1 && s != -1) f |= V_SIGN;
+    if (v == u) f |= V_SELF;
+    if (e + 1 < (int64_t)rp[u + 1]) {
+      int32_t c2 = col[e + 1];
+      if (c2 == v) f |= V_DUP;
+      else if (c2 < v) f |= V_UNSORTED;
+    }
+    // the reverse entry v -> u, by binary search in v's (sorted) row
+    int64_t lo = rp[v], hi = rp[v + 1];
+    while (lo < hi) {
+      int64_t mid = (lo + hi) >> 1;
+      if (col[mid] < u) lo = mid + 1; else hi = mid;
+    }
+    if (lo >= rp[v + 1] || col[lo] != u || sign[lo] != s) f |= V_ASYM;
+  }
+  if (f) atomicOr((unsigned long long*)(ctl + C_FLAGS), (unsigned long long)f);
+}
+
+// ------------------------------------------------------------ packing
+// Per row: first entry with column > u, and the number of such entries.
+__global__ void k_row_upper(const int32_t* rp, const int32_t* col, int32_t n, int32_t* upper_start,
+                            int32_t* upper_cnt) {
+  for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n;
+       u += (int64_t)gridDim.x * blockDim.x) {
+    int32_t lo = rp[u], hi = rp[u + 1];
+    while (lo < hi) {
+      int32_t mid = lo + ((hi - lo) >> 1);
+      if (col[mid] <= (int32_t)u) lo = mid + 1; else hi = mid;
+    }
+    upper_start[u] = lo;
+    upper_cnt[u] = rp[u + 1] - lo;
+  }
+}
+
+// Exclusive scan, three passes of 1024-element tiles.
+constexpr int kScanBlock = 256;
+constexpr int kScanTile = 1024;
+
+__global__ void __launch_bounds__(kScanBlock) k_scan_tiles(int32_t* a, int64_t len, int32_t* tile_sums) {
+  __shared__ int s_tmp[kScanBlock / 64 + 1];
+  int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 4;
+  int v[4];
+  int sum = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[k] = base + k < len ? a[base + k] : 0;
+    sum += v[k];
+  }
+  int total;
+  int pre = block_exclusive_scan<kScanBlock>(sum, total, s_tmp);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (base + k < len) a[base + k] = pre;
+    pre += v[k];
+  }
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_scan_sums(int32_t* sums, int64_t ntiles, int32_t* total_out) {
+  __shared__ int s_tmp[kScanBlock / 64 + 1];
+  int carry = 0;
+  for (int64_t c = 0; c < ntiles; c += kScanBlock) {
+    int64_t i = c + threadIdx.x;
+    int x = i < ntiles ? sums[i] : 0;
+    int total;
+    int pre = block_exclusive_scan<kScanBlock>(x, total, s_tmp);
+    if (i < ntiles) sums[i] = pre + carry;
+    carry += total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total_out = carry;
+}
+
+__global__ void k_scan_add(int32_t* a, int64_t len, const int32_t* tile_sums) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len;
+       i += (int64_t)gridDim.x * blockDim.x)
+    a[i] += tile_sums[i / kScanTile];
+}
+
+__global__ void k_pack(const int32_t* rp, const int32_t* col, const int8_t* sign, int32_t n,
+                       int64_t nnz, const int32_t* upper_start, const int32_t* edge_off,
+                       uint32_t* adj, uint2* edges) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int32_t u = row_of(rp, n, e);
+    uint32_t v = (uint32_t)col[e];
+    uint32_t neg = sign[e] < 0 ? 1u : 0u;
+    uint32_t a = v | (neg << 31);
+    adj[e] = a;
+    if ((int32_t)v > u) edges[edge_off[u] + (e - upper_start[u])] = make_uint2((uint32_t)u, a);
+  }
+}
+
+__global__ void k_copy_i32(const int32_t* src, int32_t* dst, int64_t len) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+// ------------------------------------------------------------ components
+// Lock-free union-find: every edge hooks the larger of its two roots under the
+// smaller, so each component's final root is its smallest vertex id.  Parent
+// reads use agent-scope atomic loads so a retry always sees fresh pointers.
+__device__ __forceinline__ int32_t uf_find(int32_t* parent, int32_t x) {
+  int32_t p = load_agent_i32(parent + x);
+  while (p != x) {
+    x = p;
+    p = load_agent_i32(parent + x);
+  }
+  return x;
+}
+
+__global__ void k_uf_init(int32_t* parent, int32_t n) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x)
+    parent[v] = (int32_t)v;
+}
+
+__global__ void k_uf_hook(const uint2* edges, int64_t m, int32_t* parent) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int32_t u = (int32_t)edges[e].x;
+    int32_t v = (int32_t)(edges[e].y & kVertexMask);
+    while (true) {
+      int32_t ru = uf_find(parent, u), rv = uf_find(parent, v);
+      if (ru == rv) break;
+      int32_t lo = min(ru, rv), hi = max(ru, rv);
+      int32_t old = atomicCAS(parent + hi, hi, lo);
+      if (old == hi) break;
+    }
+  }
+}
+
+__global__ void k_uf_compress(int32_t* parent, int32_t n) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x)
+    parent[v] = uf_find(parent, (int32_t)v);
+}
+
+// One wave per 64-vertex word: which vertices have edges, and the anchor they
+// share (-1 if several, -2 if none).  Also lists anchors of components with an
+// edge and counts components and isolated vertices.
+__global__ void k_word_info(const int32_t* rp, const int32_t* comp, int32_t n, int32_t nwords,
+                            int32_t* word_comp, uint64_t* word_mask, int32_t* anchors,
+                            uint64_t* ctl) {
+  const int lane = lane_id();
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  uint32_t ncomp = 0, niso = 0;
+  for (int64_t i = wave; i < nwords; i += nwaves) {
+    int64_t v = i * 64 + lane;
+    bool valid = v < n;
+    bool has_edge = valid && rp[v + 1] > rp[v];
+    int32_t c = has_edge ? comp[v] : INT32_MAX;
+    int32_t cmin = wave_min_i32(c);
+    int32_t cmax = wave_max_i32(has_edge ? c : -1);
+    uint64_t mask = __ballot(has_edge);
+    if (lane == 0) {
+      word_mask[i] = mask;
+      word_comp[i] = mask == 0 ? -2 : (cmin == cmax ? cmin : -1);
+    }
+    bool is_anchor = has_edge && comp[v] == (int32_t)v;
+    if (valid && comp[v] == (int32_t)v) ncomp++;
+    if (valid && !has_edge) niso++;
+    wave_append(is_anchor, (int32_t)v, anchors, (uint32_t*)(ctl + C_NANCH));
+  }
+  uint64_t a = wave_sum_u64(ncomp), b = wave_sum_u64(niso);
+  if (lane == 0) {
+    if (a) atomicAdd((unsigned long long*)(ctl + C_NCOMP), (unsigned long long)a);
+    if (b) atomicAdd((unsigned long long*)(ctl + C_NISO), (unsigned long long)b);
+  }
+}
+
+__global__ void k_fill_u64(uint64_t* p, int64_t len, uint64_t val) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = val;
+}
+
+__global__ void k_cloud_reset(CloudSlot* t, int64_t size, uint64_t* ctl) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < size;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    CloudSlot s;
+    s.tag = kEmpty;
+    s.khi_min = ~0ull; s.khi_max = 0;
+    s.s_min = ~0ull; s.s_max = 0;
+    s.freq = 0; s.first = ~0ull; s.pad = 0;
+    t[i] = s;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl[C_ERR] = 0;
+    ctl[C_BEST] = ~0ull;
+    ctl[C_COUNT] = 0;
+    ctl[C_TREES] = 0;
+  }
+}
+
+// Merge saved cloud entries (5 words each) as if their trees had been swept.
+__global__ void k_cloud_load(DevGraph G, const uint64_t* e, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t khi = e[5 * i], klo = e[5 * i + 1], freq = e[5 * i + 2], S = e[5 * i + 3],
+             first = e[5 * i + 4];
+    if (klo == kEmpty) {
+      atomicOr((unsigned long long*)(G.ctl + C_ERR), (unsigned long long)E_COLLISION);
+      continue;
+    }
+    uint64_t idx = klo & G.cloud_mask;
+    bool done = false;
+    for (uint64_t probe = 0; probe <= G.cloud_mask && !done; ++probe) {
+      CloudSlot* s = G.cloud + idx;
+      uint64_t old = atomicCAS((unsigned long long*)&s->tag, (unsigned long long)kEmpty,
+                               (unsigned long long)klo);
+      if (old == kEmpty || old == klo) {
+        if (old == kEmpty) {
+          uint64_t c = atomicAdd((unsigned long long*)(G.ctl + C_COUNT), 1ull);
+          if (c + 1 > G.cloud_cap)
+            atomicOr((unsigned long long*)(G.ctl + C_ERR), (unsigned long long)E_CAPACITY);
+        }
+        atomicMin((unsigned long long*)&s->khi_min, (unsigned long long)khi);
+        atomicMax((unsigned long long*)&s->khi_max, (unsigned long long)khi);
+        atomicMin((unsigned long long*)&s->s_min, (unsigned long long)S);
+        atomicMax((unsigned long long*)&s->s_max, (unsigned long long)S);
+        atomicAdd((unsigned long long*)&s->freq, (unsigned long long)freq);
+        atomicMin((unsigned long long*)&s->first, (unsigned long long)first);
+        atomicAdd((unsigned long long*)(G.ctl + C_TREES), (unsigned long long)freq);
+        atomicMin((unsigned long long*)(G.ctl + C_BEST), (unsigned long long)((S << 32) | first));
+        done = true;
+      }
+      idx = (idx + 1) & G.cloud_mask;
+    }
+    if (!done) atomicOr((unsigned long long*)(G.ctl + C_ERR), (unsigned long long)E_CAPACITY);
+  }
+}
+
+// ------------------------------------------------------------ exact count
+// Frustrated edges of B states: the y-th row of blocks counts state y.
+constexpr int kCountBlock = 256;
+__global__ void __launch_bounds__(kCountBlock) k_count(const uint2* edges, int64_t m,
+                                                     const uint64_t* bits, int32_t nwords,
+                                                     uint64_t* counts) {
+  __shared__ uint64_t s_tmp[kCountBlock / 64];
+  const uint64_t* b = bits + (size_t)blockIdx.y * nwords;
+  uint64_t c = 0;
+  for (int64_t e = blockIdx.x * (int64_t)kCountBlock + threadIdx.x; e < m;
+       e += (int64_t)gridDim.x * kCountBlock) {
+    uint2 uv = edges[e];
+    uint32_t v = uv.y & kVertexMask;
+    uint32_t bu = (uint32_t)(b[uv.x >> 6] >> (uv.x & 63)) & 1u;
+    uint32_t bv = (uint32_t)(b[v >> 6] >> (v & 63)) & 1u;
+    c += (uv.y >> 31) ^ bu ^ bv;
+  }
+  uint64_t tot = block_sum_u64<kCountBlock>(c, s_tmp);
+  if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long*)(counts + blockIdx.y), (unsigned long long)tot);
+}
+
+int err_from_bits(uint64_t bits) {
+  if (bits & E_DEPTH) return FI_EDEPTH;
+  if (bits & E_COLLISION) return FI_ECOLLISION;
+  if (bits & E_CAPACITY) return FI_ECAPACITY;
+  return FI_OK;
+}
+
+struct ProfEvent {
+  hipEvent_t a, b;
+  int kernel;
+};
+
+}  // namespace
+
+uint64_t table_size_for(int64_t cloud_capacity) {
+  uint64_t want = (uint64_t)std::max<int64_t>(cloud_capacity, 1) * 2;
+  uint64_t s = 64;
+  while (s < want) s <<= 1;
+  return s;
+}
+
+Layout make_layout(int32_t n, int64_t nnz, int64_t cloud_capacity, uint64_t table_size) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + std::max<size_t>(bytes, 1));
+    return o;
+  };
+  const size_t nn = (size_t)n, m = (size_t)nnz / 2, nw = ((size_t)n + 63) / 64;
+  L.row_ptr = take(4 * (nn + 1));
+  L.adj = take(4 * (size_t)nnz);
+  L.edges = take(8 * m);
+  L.comp = take(4 * nn);
+  L.word_comp = take(4 * nw);
+  L.word_mask = take(8 * nw);
+  L.anchors = take(4 * nn);
+  L.tmp = take(4 * (nn / kScanTile + 2));
+  L.cloud = take(sizeof(CloudSlot) * table_size);
+  L.ctl = take(8 * C_WORDS);
+  L.rootkey = take(8 * nn);
+  // tree words; also stages rounded graphL states (R <= 64 bitmaps)
+  L.pw = take(std::max<size_t>(8 * nn, 8 * (size_t)kGraphLMaxR * nw));
+  L.q0 = take(4 * (nn + 64));
+  L.q1 = take(4 * (nn + 64));
+  L.qh0 = take(8 * (nn + 64));
+  L.qh1 = take(8 * (nn + 64));
+  L.vis = take(8 * nw);
+  L.st = take(8 * nw);
+  L.gl = take(8 * (size_t)kGraphLBlocks * kGraphLMaxR);
+  // per-workgroup tree scratch (a tree word and a queue entry per vertex)
+  L.slot_stride = align_up(12 * nn);
+  L.nslots = 0;
+  if (n > 0 && n <= 1000000) {
+    size_t budget = (size_t)8 << 30;
+    L.nslots = std::min<size_t>(2048, std::max<size_t>(1, budget / L.slot_stride));
+  }
+  L.slots = take(L.slot_stride * L.nslots);
+  L.total = off;
+  return L;
+}
+
+}  // namespace fi
+
+using namespace fi;
+
+// ============================================================ C ABI
+
+extern "C" {
+
+const char* fi_strerror(int code) {
+  switch (code) {
+    case FI_OK: return "ok";
+    case FI_EINVAL: return "invalid argument or malformed CSR";
+    case FI_EASYM: return "CSR is not symmetric (missing reverse entry or sign mismatch)";
+    case FI_ESELFLOOP: return "self-loop";
+    case FI_EDUP: return "duplicate edge";
+    case FI_ESIGN: return "sign not +1/-1";
+    case FI_ERANGE: return "size or tree index out of range";
+    case FI_EUNSORTED: return "row columns not increasing";
+    case FI_ECAPACITY: return "frustration cloud capacity exceeded";
+    case FI_EDEVICE: return "HIP runtime error";
+    case FI_EDEPTH: return "BFS tree deeper than 4094 levels";
+    case FI_ECOLLISION: return "state key collision";
+    case FI_EWORKSPACE: return "workspace missing, too small or misaligned";
+    default: return "unknown error";
+  }
+}
+
+int fi_graph_workspace_size(int32_t n, int64_t nnz, int64_t cloud_capacity, size_t* out_bytes) {
+  if (!out_bytes || n < 0 || nnz < 0 || cloud_capacity < 0) return FI_EINVAL;
+  if (nnz >= ((int64_t)1 << 31)) return FI_ERANGE;
+  *out_bytes = make_layout(n, nnz, cloud_capacity, table_size_for(cloud_capacity)).total;
+  return FI_OK;
+}
+
+#define FI_HIP(call)                              \
+  do {                                            \
+    if ((call) != hipSuccess) return FI_EDEVICE;  \
+  } while (0)
+
+int fi_graph_create(int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int32_t* d_col,
+                    const int8_t* d_sign, int64_t cloud_capacity, void* d_workspace,
+                    size_t ws_bytes, void* stream, fi_graph** out) {
+  if (!out) return FI_EINVAL;
+  *out = nullptr;
+  if (n < 0 || nnz < 0 || cloud_capacity < 0) return FI_EINVAL;
+  if (nnz >= ((int64_t)1 << 31)) return FI_ERANGE;
+  if (!d_row_ptr || (nnz > 0 && (!d_col || !d_sign))) return FI_EINVAL;
+  if (nnz % 2) return FI_EASYM;
+  const uint64_t tsize = table_size_for(cloud_capacity);
+  Layout L = make_layout(n, nnz, cloud_capacity, tsize);
+  if (!d_workspace || ws_bytes < L.total || ((uintptr_t)d_workspace % kAlign)) return FI_EWORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = (char*)d_workspace;
+
+  fi_graph* g = new (std::nothrow) fi_graph();
+  if (!g) return FI_EINVAL;
+  g->L = L;
+  g->ws = ws;
+  g->ws_bytes = ws_bytes;
+  g->cloud_capacity = cloud_capacity;
+  g->table_size = tsize;
+  int dev = 0;
+  FI_HIP(hipGetDevice(&dev));
+  FI_HIP(hipDeviceGetAttribute(&g->cu_count, hipDeviceAttributeMultiprocessorCount, dev));
+  FI_HIP(hipDeviceGetAttribute(&g->max_shared, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  g->sched = fi_schedule{0, 256, 0, 512};
+
+  DevGraph& G = g->dg;
+  G.n = n;
+  G.nwords = (n + 63) / 64;
+  G.nnz = nnz;
+  G.m = nnz / 2;
+  G.row_ptr = (const int32_t*)(ws + L.row_ptr);
+  G.adj = (const uint32_t*)(ws + L.adj);
+  G.edges = (const uint2*)(ws + L.edges);
+  G.comp = (const int32_t*)(ws + L.comp);
+  G.word_comp = (const int32_t*)(ws + L.word_comp);
+  G.word_mask = (const uint64_t*)(ws + L.word_mask);
+  G.anchors = (const int32_t*)(ws + L.anchors);
+  G.cloud = (CloudSlot*)(ws + L.cloud);
+  G.cloud_mask = tsize - 1;
+  G.cloud_cap = (uint64_t)cloud_capacity;
+  G.ctl = (uint64_t*)(ws + L.ctl);
+
+  const int B = 256;
+  uint64_t* ctl = G.ctl;
+  auto fail = [&](int code) {
+    delete g;
+    return code;
+  };
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(B), 0, s, ctl, (int64_t)C_WORDS, 0ull);
+  hipLaunchKernelGGL(k_check_rowptr, dim3(grid_for(n, B)), dim3(B), 0, s, d_row_ptr, n, nnz, ctl);
+  uint64_t flags = 0;
+  if (hipMemcpyAsync(&flags, ctl + C_FLAGS, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(FI_EDEVICE);
+  if (flags & V_ROWPTR) return fail(FI_EINVAL);
+  if (nnz > 0)
+    hipLaunchKernelGGL(k_check_entries, dim3(grid_for(nnz, B, 16384)), dim3(B), 0, s, d_row_ptr,
+                       d_col, d_sign, n, nnz, ctl);
+  if (hipMemcpyAsync(&flags, ctl + C_FLAGS, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(FI_EDEVICE);
+  if (flags & V_RANGE) return fail(FI_EINVAL);
+  if (flags & V_SIGN) return fail(FI_ESIGN);
+  if (flags & V_SELF) return fail(FI_ESELFLOOP);
+  if (flags & V_DUP) return fail(FI_EDUP);
+  if (flags & V_UNSORTED) return fail(FI_EUNSORTED);
+  if (flags & V_ASYM) return fail(FI_EASYM);
+
+  // packed adjacency and the upper-triangle edge list
+  int32_t* upper_start = (int32_t*)(ws + L.q0);
+  int32_t* edge_off = (int32_t*)(ws + L.q1);
+  int32_t* tile_sums = (int32_t*)(ws + L.tmp);
+  hipLaunchKernelGGL(k_copy_i32, dim3(grid_for(n + 1, B)), dim3(B), 0, s, d_row_ptr,
+                     (int32_t*)G.row_ptr, (int64_t)n + 1);
+  if (n > 0) {
+    hipLaunchKernelGGL(k_row_upper, dim3(grid_for(n, B)), dim3(B), 0, s, d_row_ptr, d_col, n,
+                       upper_start, edge_off);
+    int64_t ntiles = ((int64_t)n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(kScanBlock), 0, s, edge_off,
+                       (int64_t)n, tile_sums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, s, tile_sums, ntiles,
+                       tile_sums + ntiles);
+    hipLaunchKernelGGL(k_scan_add, dim3(grid_for(n, B)), dim3(B), 0, s, edge_off, (int64_t)n,
+                       tile_sums);
+  }
+  if (nnz > 0)
+    hipLaunchKernelGGL(k_pack, dim3(grid_for(nnz, B, 16384)), dim3(B), 0, s, d_row_ptr, d_col,
+                       d_sign, n, nnz, upper_start, edge_off, (uint32_t*)G.adj, (uint2*)G.edges);
+  // components
+  if (n > 0) {
+    int32_t* comp = (int32_t*)G.comp;
+    hipLaunchKernelGGL(k_uf_init, dim3(grid_for(n, B)), dim3(B), 0, s, comp, n);
+    if (G.m > 0)
+      hipLaunchKernelGGL(k_uf_hook, dim3(grid_for(G.m, B, 16384)), dim3(B), 0, s, G.edges, G.m, comp);
+    hipLaunchKernelGGL(k_uf_compress, dim3(grid_for(n, B)), dim3(B), 0, s, comp, n);
+    hipLaunchKernelGGL(k_word_info, dim3(grid_for((int64_t)G.nwords * 64, B)), dim3(B), 0, s,
+                       G.row_ptr, G.comp, n, G.nwords, (int32_t*)G.word_comp,
+                       (uint64_t*)G.word_mask, (int32_t*)G.anchors, ctl);
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, B)), dim3(B), 0, s,
+                       (uint64_t*)(ws + L.rootkey), (int64_t)n, kUnvisited);
+  }
+  hipLaunchKernelGGL(k_cloud_reset, dim3(grid_for((int64_t)tsize, B)), dim3(B), 0, s, G.cloud,
+                     (int64_t)tsize, ctl);
+  uint64_t info[3] = {0, 0, 0};
+  if (hipMemcpyAsync(info, ctl + C_NCOMP, 24, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(FI_EDEVICE);
+  if (hipGetLastError() != hipSuccess) return fail(FI_EDEVICE);
+  g->ncomp = (int32_t)info[0];
+  g->nisolated = (int32_t)info[1];
+  g->nanch = (int32_t)info[2];
+  g->prof = false;
+  g->prof_ms[0] = g->prof_ms[1] = 0;
+  g->prof_n[0] = g->prof_n[1] = 0;
+  g->prof_events = new std::vector<ProfEvent>();
+  g->is_batch = false;
+  g->batch = nullptr;
+  *out = g;
+  return FI_OK;
+}
+
+void fi_graph_destroy(fi_graph* g) {
+  if (!g) return;
+  auto* ev = (std::vector<ProfEvent>*)g->prof_events;
+  if (ev) {
+    for (auto& e : *ev) {
+      (void)hipEventDestroy(e.a);
+      (void)hipEventDestroy(e.b);
+    }
+    delete ev;
+  }
+  if (g->batch) std::free(g->batch);
+  delete g;
+}
+
+int fi_graph_info(fi_graph* g, int32_t* out_components, int32_t* out_isolated) {
+  if (!g) return FI_EINVAL;
+  if (out_components) *out_components = g->ncomp;
+  if (out_isolated) *out_isolated = g->nisolated;
+  return FI_OK;
+}
+
+int fi_graph_status(fi_graph* g, void* stream) {
+  if (!g) return FI_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  uint64_t bits = 0;
+  FI_HIP(hipMemcpyAsync(&bits, g->dg.ctl + C_ERR, 8, hipMemcpyDeviceToHost, s));
+  FI_HIP(hipStreamSynchronize(s));
+  return err_from_bits(bits);
+}
+
+int fi_min_frustration(fi_graph* g, uint64_t* out_switches, uint64_t* out_first_tree,
+                       void* stream) {
+  if (!g) return FI_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  uint64_t w[4];
+  FI_HIP(hipMemcpyAsync(w, g->dg.ctl, 32, hipMemcpyDeviceToHost, s));
+  FI_HIP(hipStreamSynchronize(s));
+  int e = err_from_bits(w[C_ERR]);
+  if (e) return e;
+  if (w[C_TREES] == 0) return FI_EINVAL;
+  if (out_switches) *out_switches = w[C_BEST] >> 32;
+  if (out_first_tree) *out_first_tree = w[C_BEST] & 0xFFFFFFFFull;
+  return FI_OK;
+}
+
+int fi_cloud_size(fi_graph* g, int64_t* out, void* stream) {
+  if (!g || !out || g->is_batch) return FI_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  uint64_t c = 0;
+  FI_HIP(hipMemcpyAsync(&c, g->dg.ctl + C_COUNT, 8, hipMemcpyDeviceToHost, s));
+  FI_HIP(hipStreamSynchronize(s));
+  *out = (int64_t)c;
+  return FI_OK;
+}
+
+int fi_cloud_read(fi_graph* g, fi_cloud_entry* h_out, int64_t cap, int64_t* written, void* stream) {
+  if (!g || g->is_batch || cap < 0 || (cap > 0 && !h_out)) return FI_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<CloudSlot> table(g->table_size);
+  uint64_t bits = 0;
+  FI_HIP(hipMemcpyAsync(table.data(), g->dg.cloud, sizeof(CloudSlot) * g->table_size,
+                        hipMemcpyDeviceToHost, s));
+  FI_HIP(hipMemcpyAsync(&bits, g->dg.ctl + C_ERR, 8, hipMemcpyDeviceToHost, s));
+  FI_HIP(hipStreamSynchronize(s));
+  int e = err_from_bits(bits);
+  if (e) return e;
+  std::vector<fi_cloud_entry> rows;
+  for (const CloudSlot& c : table) {
+    if (c.tag == kEmpty) continue;
+    if (c.khi_min != c.khi_max || c.s_min != c.s_max) return FI_ECOLLISION;
+    rows.push_back(fi_cloud_entry{c.khi_min, c.tag, c.freq, c.s_min, c.first});
+  }
+  std::sort(rows.begin(), rows.end(), [](const fi_cloud_entry& a, const fi_cloud_entry& b) {
+    return a.key_hi != b.key_hi ? a.key_hi < b.key_hi : a.key_lo < b.key_lo;
+  });
+  int64_t k = std::min<int64_t>(cap, (int64_t)rows.size());
+  if (k > 0) std::memcpy(h_out, rows.data(), sizeof(fi_cloud_entry) * k);
+  if (written) *written = (int64_t)rows.size();
+  return FI_OK;
+}
+
+int fi_cloud_reset(fi_graph* g, void* stream) {
+  if (!g || g->is_batch) return FI_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_cloud_reset, dim3(grid_for((int64_t)g->table_size, 256)), dim3(256), 0, s,
+                     g->dg.cloud, (int64_t)g->table_size, g->dg.ctl);
+  return hipGetLastError() == hipSuccess ? FI_OK : FI_EDEVICE;
+}
+
+int fi_cloud_load(fi_graph* g, const fi_cloud_entry* h_entries, int64_t count, void* stream) {
+  if (!g || g->is_batch || count < 0 || (count > 0 && !h_entries)) return FI_EINVAL;
+  if (count == 0) return FI_OK;
+  hipStream_t s = (hipStream_t)stream;
+  // stage through the tree-word scratch, in chunks that fit it
+  uint64_t* stage = (uint64_t*)(g->ws + g->L.pw);
+  int64_t per = std::max<int64_t>(1, (int64_t)g->dg.n / 5);
+  std::vector<uint64_t> buf;
+  for (int64_t c0 = 0; c0 < count; c0 += per) {
+    int64_t k = std::min(per, count - c0);
+    buf.resize(5 * k);
+    for (int64_t i = 0; i < k; ++i) {
+      const fi_cloud_entry& e = h_entries[c0 + i];
+      buf[5 * i] = e.key_hi; buf[5 * i + 1] = e.key_lo; buf[5 * i + 2] = e.freq;
+      buf[5 * i + 3] = e.switches; buf[5 * i + 4] = e.first_tree;
+    }
+    FI_HIP(hipMemcpyAsync(stage, buf.data(), 8 * buf.size(), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_cloud_load, dim3(grid_for(k, 256)), dim3(256), 0, s, g->dg, stage, k);
+    FI_HIP(hipStreamSynchronize(s));
+  }
+  return hipGetLastError() == hipSuccess ? FI_OK : FI_EDEVICE;
+}
+
+int fi_count(fi_graph* g, const uint64_t* d_bits, int32_t B, uint64_t* d_counts, void* stream) {
+  if (!g || g->is_batch || B < 0 || (B > 0 && (!d_bits || !d_counts))) return FI_EINVAL;
+  if (B == 0) return FI_OK;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, d_counts, (int64_t)B, 0ull);
+  hipError_t e = launch_count(g->dg, d_bits, B, d_counts, s);
+  return e == hipSuccess ? FI_OK : FI_EDEVICE;
+}
+
+int fi_set_schedule(fi_graph* g, const fi_schedule* sc) {
+  if (!g || !sc) return FI_EINVAL;
+  if (sc->path < 0 || sc->path > 3) return FI_EINVAL;
+  if (sc->block != 256 && sc->block != 512 && sc->block != 1024) return FI_EINVAL;
+  if (sc->grid < 0 || sc->heavy < 32) return FI_EINVAL;
+  if (sc->path == 1 && (size_t)g->dg.n * 12 + 32768 > (size_t)g->max_shared) return FI_EINVAL;
+  if (sc->path == 2 && g->L.nslots == 0) return FI_EINVAL;
+  g->sched = *sc;
+  return FI_OK;
+}
+
+int fi_get_schedule(fi_graph* g, fi_schedule* out) {
+  if (!g || !out) return FI_EINVAL;
+  *out = g->sched;
+  return FI_OK;
+}
+
+int fi_prof_enable(fi_graph* g, int on) {
+  if (!g) return FI_EINVAL;
+  auto* ev = (std::vector<ProfEvent>*)g->prof_events;
+  for (auto& e : *ev) {
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  ev->clear();
+  g->prof = on != 0;
+  g->prof_ms[0] = g->prof_ms[1] = 0;
+  g->prof_n[0] = g->prof_n[1] = 0;
+  return FI_OK;
+}
+
+int fi_prof_read(fi_graph* g, int kernel, double* out_ms, int64_t* out_launches) {
+  if (!g || kernel < 0 || kernel > 1) return FI_EINVAL;
+  auto* ev = (std::vector<ProfEvent>*)g->prof_events;
+  for (auto& e : *ev) {
+    FI_HIP(hipEventSynchronize(e.b));
+    float ms = 0;
+    FI_HIP(hipEventElapsedTime(&ms, e.a, e.b));
+    g->prof_ms[e.kernel] += ms;
+    g->prof_n[e.kernel] += 1;
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  ev->clear();
+  if (out_ms) *out_ms = g->prof_ms[kernel];
+  if (out_launches) *out_launches = g->prof_n[kernel];
+  return FI_OK;
+}
+
+}  // extern "C"
+
+namespace fi {
+
+// Events around one launch, when profiling is on.
+int prof_begin(fi_graph* g, hipStream_t s, void** token) {
+  *token = nullptr;
+  if (!g->prof) return 0;
+  auto* pe = new ProfEvent();
+  if (hipEventCreate(&pe->a) != hipSuccess || hipEventCreate(&pe->b) != hipSuccess) {
+    delete pe;
+    return -1;
+  }
+  (void)hipEventRecord(pe->a, s);
+  *token = pe;
+  return 0;
+}
+
+void prof_end(fi_graph* g, hipStream_t s, void* token, int kernel) {
+  if (!token) return;
+  auto* pe = (ProfEvent*)token;
+  pe->kernel = kernel;
+  (void)hipEventRecord(pe->b, s);
+  ((std::vector<ProfEvent>*)g->prof_events)->push_back(*pe);
+  delete pe;
+}
+
+hipError_t launch_count(const DevGraph& dg, const uint64_t* bits, int32_t B, uint64_t* counts,
+                        hipStream_t s) {
+  if (dg.m == 0) return hipSuccess;
+  int gx = grid_for(dg.m, kCountBlock, 2048);
+  hipLaunchKernelGGL(k_count, dim3(gx, B), dim3(kCountBlock), 0, s, dg.edges, dg.m, bits,
+                     dg.nwords, counts);
+  return hipGetLastError();
+}
+
+}  // namespace fi

@@ -1,0 +1,333 @@
+"""Python binding of libfrustration (ctypes): argument marshalling only.
+
+Every step of the sweep and of graphL runs in the HIP kernels of the library;
+PyTorch only provides device memory (the workspace and the I/O tensors) and
+the stream.  There is no CPU fallback: if the library is missing or no GPU is
+present, construction fails with an error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfrustration.so")
+
+ERRORS = {
+    0: "FI_OK", -1: "FI_EINVAL", -2: "FI_EASYM", -3: "FI_ESELFLOOP", -4: "FI_EDUP",
+    -5: "FI_ESIGN", -6: "FI_ERANGE", -7: "FI_EUNSORTED", -8: "FI_ECAPACITY",
+    -9: "FI_EDEVICE", -10: "FI_EDEPTH", -11: "FI_ECOLLISION", -12: "FI_EWORKSPACE",
+}
+SYMBOLS = (
+    "fi_graph_workspace_size", "fi_graph_create", "fi_graph_destroy", "fi_graph_info",
+    "fi_graph_status", "fi_sweep", "fi_sweep_range", "fi_min_frustration", "fi_cloud_size",
+    "fi_cloud_read", "fi_cloud_reset", "fi_cloud_load", "fi_tree_state", "fi_count",
+    "fi_graphl_forward", "fi_graphl_backward", "fi_graphl_step", "fi_round_count",
+    "fi_batch_workspace_size", "fi_batch_create", "fi_batch_sweep", "fi_set_schedule",
+    "fi_get_schedule", "fi_prof_enable", "fi_prof_read", "fi_strerror",
+)
+
+
+class FrustrationError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {ERRORS.get(code, code)}")
+
+
+class CloudEntry(ctypes.Structure):
+    _fields_ = [("key_hi", ctypes.c_uint64), ("key_lo", ctypes.c_uint64),
+                ("freq", ctypes.c_uint64), ("switches", ctypes.c_uint64),
+                ("first_tree", ctypes.c_uint64)]
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("heavy", ctypes.c_int32)]
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libfrustration.so and declare its C signatures (no GPU needed)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with __graft_entry__.build() "
+                              "or python paper_2311_00869_amd/_build.py")
+        L = ctypes.CDLL(path)
+        c = ctypes
+        vp, i32, i64, u64, sz = c.c_void_p, c.c_int32, c.c_int64, c.c_uint64, c.c_size_t
+        P = c.POINTER
+        sig = {
+            "fi_graph_workspace_size": ([i32, i64, i64, P(sz)], c.c_int),
+            "fi_graph_create": ([i32, i64, vp, vp, vp, i64, vp, sz, vp, P(vp)], c.c_int),
+            "fi_graph_destroy": ([vp], None),
+            "fi_graph_info": ([vp, P(i32), P(i32)], c.c_int),
+            "fi_graph_status": ([vp, vp], c.c_int),
+            "fi_sweep": ([vp, i64, u64, vp], c.c_int),
+            "fi_sweep_range": ([vp, i64, i64, u64, vp, vp], c.c_int),
+            "fi_min_frustration": ([vp, P(u64), P(u64), vp], c.c_int),
+            "fi_cloud_size": ([vp, P(i64), vp], c.c_int),
+            "fi_cloud_read": ([vp, vp, i64, P(i64), vp], c.c_int),
+            "fi_cloud_reset": ([vp, vp], c.c_int),
+            "fi_cloud_load": ([vp, vp, i64, vp], c.c_int),
+            "fi_tree_state": ([vp, u64, i64, vp, vp, vp], c.c_int),
+            "fi_count": ([vp, vp, i32, vp, vp], c.c_int),
+            "fi_graphl_forward": ([vp, vp, i32, vp, vp], c.c_int),
+            "fi_graphl_backward": ([vp, vp, i32, vp, vp, vp], c.c_int),
+            "fi_graphl_step": ([vp, vp, i32, c.c_float, vp, vp], c.c_int),
+            "fi_round_count": ([vp, vp, i32, vp, vp, vp], c.c_int),
+            "fi_batch_workspace_size": ([i32, vp, vp, P(sz)], c.c_int),
+            "fi_batch_create": ([i32, vp, vp, vp, vp, vp, vp, sz, vp, P(vp)], c.c_int),
+            "fi_batch_sweep": ([vp, i64, u64, vp, vp, vp], c.c_int),
+            "fi_set_schedule": ([vp, P(Schedule)], c.c_int),
+            "fi_get_schedule": ([vp, P(Schedule)], c.c_int),
+            "fi_prof_enable": ([vp, c.c_int], c.c_int),
+            "fi_prof_read": ([vp, c.c_int, P(c.c_double), P(i64)], c.c_int),
+            "fi_strerror": ([c.c_int], c.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+        return L
+
+
+def _check(rc: int, where: str):
+    if rc != 0:
+        raise FrustrationError(rc, where)
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        raise RuntimeError("libfrustration needs a ROCm GPU; none is visible")
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev(x, dtype, device):
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=dtype).contiguous()
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device=device, dtype=dtype).contiguous()
+
+
+def nwords(n: int) -> int:
+    return (n + 63) // 64
+
+
+def words_to_numpy(t) -> np.ndarray:
+    """int64 device words -> numpy uint64."""
+    return t.detach().cpu().numpy().view(np.uint64)
+
+
+class Graph:
+    """A signed graph resident on the GPU with its frustration cloud.
+
+    row_ptr / col / sign: symmetric sorted CSR (numpy or torch).  The
+    workspace is one torch uint8 tensor owned by this object.
+    """
+
+    def __init__(self, row_ptr, col, sign, cloud_capacity: int = 4096, device="cuda",
+                 stream=None):
+        _require_gpu()
+        self.lib = load_library()
+        self.device = torch.device(device)
+        rp = _dev(row_ptr, torch.int32, self.device)
+        cl = _dev(col, torch.int32, self.device)
+        sg = _dev(sign, torch.int8, self.device)
+        self.n = int(rp.numel() - 1)
+        self.nnz = int(cl.numel())
+        self.m = self.nnz // 2
+        self.nwords = nwords(self.n)
+        self.cloud_capacity = int(cloud_capacity)
+        size = ctypes.c_size_t(0)
+        _check(self.lib.fi_graph_workspace_size(self.n, self.nnz, self.cloud_capacity,
+                                                ctypes.byref(size)), "workspace_size")
+        self.ws_bytes = int(size.value)
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = self.lib.fi_graph_create(self.n, self.nnz, _ptr(rp), _ptr(cl), _ptr(sg),
+                                          self.cloud_capacity, ctypes.c_void_p(self._ws_ptr),
+                                          self.ws_bytes, _stream_ptr(stream), ctypes.byref(h))
+        _check(rc, "graph_create")
+        self.handle = h
+        del rp, cl, sg
+
+    # ---------------------------------------------------------------- lifetime
+    def close(self):
+        if getattr(self, "handle", None):
+            torch.cuda.synchronize(self.device)
+            self.lib.fi_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        c, i = ctypes.c_int32(), ctypes.c_int32()
+        _check(self.lib.fi_graph_info(self.handle, ctypes.byref(c), ctypes.byref(i)), "info")
+        return int(c.value), int(i.value)
+
+    def status(self, stream=None):
+        _check(self.lib.fi_graph_status(self.handle, _stream_ptr(stream)), "status")
+
+    # ---------------------------------------------------------------- sweep
+    def sweep(self, K: int, seed: int, stream=None):
+        _check(self.lib.fi_sweep(self.handle, int(K), seed & (2**64 - 1), _stream_ptr(stream)), "sweep")
+
+    def sweep_range(self, t0: int, t1: int, seed: int, tree_switches: bool = False, stream=None):
+        out = torch.empty(max(t1 - t0, 1), dtype=torch.int64, device=self.device) if tree_switches else None
+        _check(self.lib.fi_sweep_range(self.handle, int(t0), int(t1), seed & (2**64 - 1), _ptr(out),
+                                       _stream_ptr(stream)), "sweep_range")
+        return None if out is None else out[: t1 - t0]
+
+    def min_frustration(self, stream=None):
+        s, t = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(self.lib.fi_min_frustration(self.handle, ctypes.byref(s), ctypes.byref(t),
+                                           _stream_ptr(stream)), "min_frustration")
+        return int(s.value), int(t.value)
+
+    def cloud_size(self, stream=None) -> int:
+        k = ctypes.c_int64()
+        _check(self.lib.fi_cloud_size(self.handle, ctypes.byref(k), _stream_ptr(stream)), "cloud_size")
+        return int(k.value)
+
+    def cloud(self, stream=None) -> np.ndarray:
+        """uint64 [E, 5]: key_hi, key_lo, freq, switches, first_tree (sorted by key)."""
+        size = self.cloud_size(stream)
+        buf = (CloudEntry * max(size, 1))()
+        written = ctypes.c_int64()
+        _check(self.lib.fi_cloud_read(self.handle, buf, size, ctypes.byref(written),
+                                      _stream_ptr(stream)), "cloud_read")
+        arr = np.ctypeslib.as_array(buf).view(np.uint64).reshape(-1, 5)[:size].copy()
+        return arr
+
+    def cloud_reset(self, stream=None):
+        _check(self.lib.fi_cloud_reset(self.handle, _stream_ptr(stream)), "cloud_reset")
+
+    def cloud_load(self, entries, stream=None):
+        e = np.ascontiguousarray(entries, dtype=np.uint64).reshape(-1, 5)
+        _check(self.lib.fi_cloud_load(self.handle, e.ctypes.data_as(ctypes.c_void_p), e.shape[0],
+                                      _stream_ptr(stream)), "cloud_load")
+
+    def tree_state(self, seed: int, t: int, stream=None):
+        """(canonical words as numpy uint64 [nwords], switches) of tree t."""
+        bits = torch.zeros(max(self.nwords, 1), dtype=torch.int64, device=self.device)
+        sw = torch.zeros(1, dtype=torch.int64, device=self.device)
+        _check(self.lib.fi_tree_state(self.handle, seed & (2**64 - 1), int(t), _ptr(bits), _ptr(sw),
+                                      _stream_ptr(stream)), "tree_state")
+        return words_to_numpy(bits)[: self.nwords], int(sw.item())
+
+    def count(self, bits, stream=None):
+        """Exact frustration counts of B states given as int64 words [B, nwords]."""
+        b = bits.to(device=self.device, dtype=torch.int64).contiguous().reshape(-1, self.nwords)
+        out = torch.zeros(b.shape[0], dtype=torch.int64, device=self.device)
+        _check(self.lib.fi_count(self.handle, _ptr(b), b.shape[0], _ptr(out), _stream_ptr(stream)), "count")
+        return out
+
+    # ---------------------------------------------------------------- graphL
+    def graphl_forward(self, gamma, stream=None):
+        g = gamma.contiguous()
+        R = g.shape[1]
+        loss = torch.empty(R, dtype=torch.float64, device=self.device)
+        _check(self.lib.fi_graphl_forward(self.handle, _ptr(g), R, _ptr(loss), _stream_ptr(stream)),
+               "graphl_forward")
+        return loss
+
+    def graphl_backward(self, gamma, grad_loss=None, stream=None):
+        g = gamma.contiguous()
+        R = g.shape[1]
+        w = None if grad_loss is None else grad_loss.to(dtype=torch.float64).contiguous()
+        out = torch.empty_like(g)
+        _check(self.lib.fi_graphl_backward(self.handle, _ptr(g), R, _ptr(w), _ptr(out),
+                                           _stream_ptr(stream)), "graphl_backward")
+        return out
+
+    def graphl_step(self, gamma, alpha: float, out=None, stream=None):
+        g = gamma.contiguous()
+        R = g.shape[1]
+        if out is None:
+            out = torch.empty_like(g)
+        _check(self.lib.fi_graphl_step(self.handle, _ptr(g), R, float(alpha), _ptr(out),
+                                       _stream_ptr(stream)), "graphl_step")
+        return out
+
+    def round_count(self, gamma, return_bits: bool = False, stream=None):
+        g = gamma.contiguous()
+        R = g.shape[1]
+        counts = torch.empty(R, dtype=torch.int64, device=self.device)
+        bits = torch.empty((R, max(self.nwords, 1)), dtype=torch.int64, device=self.device) if return_bits else None
+        _check(self.lib.fi_round_count(self.handle, _ptr(g), R, _ptr(counts), _ptr(bits),
+                                       _stream_ptr(stream)), "round_count")
+        return (counts, bits) if return_bits else counts
+
+    # ---------------------------------------------------------------- tuning / timing
+    def set_schedule(self, path=0, block=256, grid=0, heavy=512):
+        s = Schedule(path, block, grid, heavy)
+        _check(self.lib.fi_set_schedule(self.handle, ctypes.byref(s)), "set_schedule")
+
+    def get_schedule(self):
+        s = Schedule()
+        _check(self.lib.fi_get_schedule(self.handle, ctypes.byref(s)), "get_schedule")
+        return dict(path=s.path, block=s.block, grid=s.grid, heavy=s.heavy)
+
+    def prof_enable(self, on=True):
+        _check(self.lib.fi_prof_enable(self.handle, 1 if on else 0), "prof_enable")
+
+    def prof_read(self, kernel=0):
+        ms, k = ctypes.c_double(), ctypes.c_int64()
+        _check(self.lib.fi_prof_read(self.handle, kernel, ctypes.byref(ms), ctypes.byref(k)), "prof_read")
+        return float(ms.value), int(k.value)
+
+
+class GraphLLoss(torch.autograd.Function):
+    """L_r = sum over edges (1 - e_ij G_ir G_jr) / 2 (Eq. eq-loss_imbalance_new) for
+    every restart column r; forward and backward are the library's kernels."""
+
+    @staticmethod
+    def forward(ctx, gamma, graph):
+        ctx.graph = graph
+        ctx.save_for_backward(gamma)
+        return graph.graphl_forward(gamma)
+
+    @staticmethod
+    def backward(ctx, grad_loss):
+        (gamma,) = ctx.saved_tensors
+        return ctx.graph.graphl_backward(gamma, grad_loss), None
+
+
+def graphl_loss(graph: Graph, gamma):
+    return GraphLLoss.apply(gamma, graph)
+
+
+def graphl_descent(graph: Graph, gamma0, steps: int, alpha: float = 0.001):
+    """Alg. alg-gradient's update loop with the fused step kernel (ping-pong
+    buffers); returns the final Gamma."""
+    a = gamma0.contiguous().clone()
+    b = torch.empty_like(a)
+    for _ in range(steps):
+        graph.graphl_step(a, alpha, out=b)
+        a, b = b, a
+    return a

@@ -1,0 +1,58 @@
+"""Host-only checks of the C-ABI library: it loads, exports every function
+include/frustration.h declares, and its pure host calls behave (no GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2311_00869_amd import frustration as fr
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "frustration.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fi_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = fr.load_library()
+    names = _declared()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(fr.SYMBOLS)
+
+
+def test_strerror_and_workspace_arithmetic():
+    lib = fr.load_library()
+    assert lib.fi_strerror(0) == b"ok"
+    assert b"symmetric" in lib.fi_strerror(-2)
+    size = ctypes.c_size_t()
+    assert lib.fi_graph_workspace_size(1000, 10000, 1000, ctypes.byref(size)) == 0
+    small = size.value
+    assert lib.fi_graph_workspace_size(2000, 20000, 1000, ctypes.byref(size)) == 0
+    assert size.value > small > 1000 * 12
+    assert lib.fi_graph_workspace_size(-1, 0, 0, ctypes.byref(size)) == -1
+    assert lib.fi_graph_workspace_size(10, 2**31, 0, ctypes.byref(size)) == -6
+
+
+def test_create_rejects_bad_arguments_without_touching_the_device():
+    lib = fr.load_library()
+    out = ctypes.c_void_p()
+    # null output pointer, negative sizes and a missing workspace fail before any HIP call
+    assert lib.fi_graph_create(4, 8, None, None, None, 16, None, 0, None, None) == -1
+    assert lib.fi_graph_create(-1, 0, None, None, None, 16, None, 0, None, ctypes.byref(out)) == -1
+    assert lib.fi_graph_create(4, 2**31, None, None, None, 16, None, 0, None, ctypes.byref(out)) == -6
+
+
+def test_product_path_has_no_oracle_import():
+    pkg = os.path.join(os.path.dirname(os.path.dirname(__file__)), "paper_2311_00869_amd")
+    for root, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h")):
+                text = open(os.path.join(root, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "liboracle" not in text, f

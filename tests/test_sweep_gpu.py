@@ -1,0 +1,208 @@
+"""Parity of the HIP sweep with the CPU oracle (bit-exact): per-tree switch
+counts, canonical states, the cloud, the minimum, input validation, and
+invariance to schedule, splitting and repetition."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2311_00869_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+fr = pytest.importorskip("paper_2311_00869_amd.frustration")
+
+SCHEDULES = [
+    dict(path=1, block=256), dict(path=1, block=512), dict(path=1, block=1024),
+    dict(path=2, block=256), dict(path=2, block=1024),
+    dict(path=3, block=256), dict(path=3, block=512, heavy=32), dict(path=3, block=1024, heavy=64),
+]
+
+
+def _graph(g, cap=4096):
+    return fr.Graph(g.row_ptr, g.col, g.sign, cloud_capacity=cap)
+
+
+def _cases():
+    return {
+        "small1000": synth.config_small(0),
+        "disconnected": synth.random_small(300, 280, 3, p_pos=0.6),
+        "isolated": synth.chung_lu(2000, 3000, 2.1, 5, p_pos=0.7),
+        "fig_neg": synth.figure_graph([-1, 1, -1, 1, -1]),
+        "k7neg": synth.complete_graph(7, -1),
+        "cycle": synth.cycle_graph(33, (0, 5, 9)),
+        "tree": synth.random_tree(200, 1),
+        "empty": synth.isolated_vertices(65),
+    }
+
+
+def _sched_ok(g, s):
+    if s["path"] == 1 and g.n * 12 + 32768 > 160 * 1024:
+        return False
+    return True
+
+
+@pytest.mark.parametrize("name", list(_cases().keys()))
+def test_tree_switches_and_cloud_match_oracle(name):
+    g = _cases()[name]
+    K, seed = 96, 12345
+    ref = oracle.sweep(g, seed, 0, K, checks=True)
+    G = _graph(g)
+    for s in SCHEDULES:
+        if not _sched_ok(g, s):
+            continue
+        G.set_schedule(**s)
+        G.cloud_reset()
+        sw = G.sweep_range(0, K, seed, tree_switches=True)
+        got = sw.cpu().numpy().astype(np.uint64)
+        assert np.array_equal(got, ref.trees[:, 0]), (name, s)
+        cloud = G.cloud()
+        assert np.array_equal(cloud, ref.cloud), (name, s)
+        assert G.min_frustration() == ref.best, (name, s)
+    G.close()
+
+
+@pytest.mark.parametrize("name", ["small1000", "disconnected", "isolated", "cycle"])
+def test_canonical_states_match_oracle(name):
+    g = _cases()[name]
+    G = _graph(g)
+    seed = 77
+    for t in [0, 1, 5, 31]:
+        _, _, st = oracle.tree(g, seed, t)
+        want = oracle.canonical_words(g, st)
+        for s in SCHEDULES[::3]:
+            if not _sched_ok(g, s):
+                continue
+            G.set_schedule(**s)
+            words, sw = G.tree_state(seed, t)
+            assert np.array_equal(words, want), (name, t, s)
+            assert sw == oracle.count(g, st)
+    # tree_state leaves the cloud alone
+    assert G.cloud_size() == 0
+    G.close()
+
+
+def test_split_sweep_and_repeat_are_identical():
+    g = synth.erdos_renyi_connected(3000, 12000, 0.75, 9)
+    G = _graph(g, cap=2048)
+    G.sweep(300, 4)
+    whole = G.cloud()
+    best = G.min_frustration()
+    G.cloud_reset()
+    for a, b in [(0, 17), (17, 200), (200, 300)]:
+        G.sweep_range(a, b, 4)
+    assert np.array_equal(G.cloud(), whole)
+    assert G.min_frustration() == best
+    G.cloud_reset()
+    G.set_schedule(path=3, block=256)
+    G.sweep(300, 4)
+    assert np.array_equal(G.cloud(), whole)
+    ref = oracle.sweep(g, 4, 0, 300, checks=False)
+    assert np.array_equal(whole, ref.cloud)
+    G.close()
+
+
+def test_cloud_checkpoint_resume():
+    g = synth.config_small(2)
+    G = _graph(g, cap=1024)
+    G.sweep_range(0, 150, 8)
+    saved = G.cloud()
+    G.cloud_reset()
+    G.cloud_load(saved)
+    G.sweep_range(150, 400, 8)
+    resumed = G.cloud()
+    ref = oracle.sweep(g, 8, 0, 400, checks=False)
+    assert np.array_equal(resumed, ref.cloud)
+    assert G.min_frustration() == ref.best
+    G.close()
+
+
+def test_capacity_error_is_reported():
+    g = synth.config_small(0)
+    G = _graph(g, cap=4)
+    G.sweep(200, 1)
+    with pytest.raises(fr.FrustrationError) as e:
+        G.status()
+    assert e.value.code == -8
+    G.cloud_reset()
+    G.status()
+    G.close()
+
+
+def test_exact_count_matches_oracle():
+    g = synth.chung_lu(5000, 40000, 2.3, 3, p_pos=0.8)
+    G = _graph(g)
+    rng = np.random.default_rng(0)
+    B = 7
+    states = np.where(rng.random((B, g.n)) < 0.5, 1, -1).astype(np.int8)
+    words = np.zeros((B, G.nwords), np.uint64)
+    for b in range(B):
+        idx = np.flatnonzero(states[b] < 0)
+        np.bitwise_or.at(words[b], idx // 64, np.left_shift(np.uint64(1), (idx % 64).astype(np.uint64)))
+    got = G.count(torch.from_numpy(words.view(np.int64))).cpu().numpy()
+    want = [oracle.count(g, states[b]) for b in range(B)]
+    assert got.tolist() == want
+    G.close()
+
+
+def test_planted_counter_pin():
+    # the planted split frustrates exactly the flipped edges
+    g = synth.chung_lu(20000, 100000, 2.1, 6, planted_flip=0.05)
+    G = _graph(g)
+    side = g.meta["side"]
+    idx = np.flatnonzero(side == 1)
+    w = np.zeros(G.nwords, np.uint64)
+    np.bitwise_or.at(w, idx // 64, np.left_shift(np.uint64(1), (idx % 64).astype(np.uint64)))
+    got = int(G.count(torch.from_numpy(w.view(np.int64))).item())
+    assert got == g.meta["flipped"]
+    G.close()
+
+
+def _bad(kind):
+    g = synth.random_small(10, 20, 1, p_pos=0.5, connected=True)
+    rp, col, sg = g.row_ptr.copy(), g.col.copy(), g.sign.copy()
+    if kind == "sign":
+        sg[3] = 0
+    elif kind == "selfloop":
+        v = 2
+        col[rp[v]] = v
+        col[rp[v]:rp[v + 1]] = np.sort(col[rp[v]:rp[v + 1]])
+    elif kind == "dup":
+        v = 4
+        col[rp[v] + 1] = col[rp[v]]
+    elif kind == "unsorted":
+        v = 5
+        col[rp[v]:rp[v + 1]] = col[rp[v]:rp[v + 1]][::-1].copy()
+    elif kind == "asym":
+        sg[7] = -sg[7]
+    elif kind == "range":
+        col[0] = 99
+    elif kind == "rowptr":
+        rp[3] = rp[4] + 1
+    return synth.SignedCSR(10, rp, col, sg)
+
+
+@pytest.mark.parametrize("kind", ["sign", "selfloop", "dup", "unsorted", "asym", "range", "rowptr"])
+def test_validation_matches_oracle(kind):
+    g = _bad(kind)
+    want = oracle.validate(g)
+    assert want != 0
+    with pytest.raises(fr.FrustrationError) as e:
+        _graph(g)
+    assert e.value.code == want
+
+
+def test_powerlaw_multi_tile_all_paths():
+    # several tiles, ragged tails, hubs above the heavy threshold
+    g = synth.chung_lu(60000, 300000, 2.1, 11, p_pos=0.8)
+    K, seed = 24, 99
+    ref = oracle.sweep(g, seed, 0, K, checks=False)
+    G = _graph(g, cap=256)
+    for s in [dict(path=2, block=256), dict(path=2, block=1024), dict(path=3, block=256, heavy=64),
+              dict(path=3, block=512, heavy=512), dict(path=3, block=1024, heavy=4096)]:
+        G.set_schedule(**s)
+        G.cloud_reset()
+        sw = G.sweep_range(0, K, seed, tree_switches=True).cpu().numpy().astype(np.uint64)
+        assert np.array_equal(sw, ref.trees[:, 0]), s
+        assert np.array_equal(G.cloud(), ref.cloud), s
+    G.close()
