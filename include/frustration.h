@@ -218,15 +218,17 @@ int fi_batch_sweep(fi_graph* b, int64_t trees_per_graph, uint64_t seed, uint64_t
  * results; fi_set_schedule only changes speed.  path: 0 = automatic,
  * 1 = one workgroup per tree with the tree state in LDS (n <= 12,000),
  * 2 = one workgroup per tree with the tree state in workspace memory
- * (n <= 1,000,000), 3 = the whole grid per tree (persistent cooperative
- * kernel, any n).  block: threads per workgroup (256, 512 or 1024);
- * grid: workgroups (0 = fill the GPU); heavy: degree above which a
- * frontier vertex is expanded by several workgroups (path 3). */
+ * (n <= 1,000,000), 3 = the whole grid on a few trees at a time
+ * (persistent cooperative kernel, any n).  block: threads per workgroup
+ * (256, 512 or 1024); grid: workgroups (0 = default); heavy: degree above
+ * which a top-down frontier vertex is expanded by several workgroups
+ * (path 3, >= 32); batch: trees in flight on path 3 (1 .. 8). */
 typedef struct {
   int32_t path;
   int32_t block;
   int32_t grid;
   int32_t heavy;
+  int32_t batch;
 } fi_schedule;
 
 int fi_set_schedule(fi_graph* g, const fi_schedule* s);

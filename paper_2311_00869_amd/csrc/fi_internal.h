@@ -139,9 +139,10 @@ struct DevGraph {
   const uint32_t* adj;      // [nnz] packed neighbour | neg << 31
   const uint2* edges;       // [m] (u, v | neg << 31), u < v
   const int32_t* comp;      // [n] anchor (smallest id) of the component
-  const int32_t* word_comp; // [nwords] anchor shared by the word's non-isolated
-                            // vertices, -1 if mixed, -2 if none
-  const uint64_t* word_mask;// [nwords] non-isolated vertices of the word
+  const int32_t* word_comp; // [nwords] smallest anchor among the word's vertices
+                            // with an edge ("main" component), -2 if none
+  const uint64_t* word_mask;// [nwords] vertices of the word with an edge
+  const uint64_t* word_main;// [nwords] those of them in the main component
   const int32_t* anchors;   // [C] anchors of components with an edge
   CloudSlot* cloud;
   uint64_t cloud_mask;      // table size - 1
@@ -156,25 +157,26 @@ struct SweepArgs {
   uint64_t* tree_switches;  // [t1 - t0] or null
   uint64_t* bits_out;       // canonical words of the single tree, or null
   int insert;               // 0: compute only, leave the cloud alone
-  // scratch for the tree state
-  uint64_t* pw;             // path 2: [slots][stride]; path 3: [n]
-  int32_t* q;               // path 2: [slots][stride]; path 3: frontier lists
-  size_t slot_stride;       // elements per slot (path 2)
-  // path 3 extras
-  int32_t* ql[2];
-  int2* qh[2];
-  uint64_t* vis;
-  uint64_t* st;
-  uint64_t* rootkey;        // [n], indexed by anchor, kept at kUnvisited
-  int32_t heavy;            // degree above which a vertex is split into units
-  int32_t nanch;
+  // one-workgroup-per-tree scratch in workspace memory: [slots][slot_stride bytes]
+  uint64_t* pw;
+  size_t slot_stride;
 };
 
 // ----------------------------------------------------------------- layout
+constexpr int kGridSlots = 8;  // trees in flight on the whole-grid path (max)
+constexpr int kGridCtlWords = 128;          // control words per tree slot
+constexpr int kGridBarWords = 32 + 16 * 512;  // barrier words per tree slot
+
 struct Layout {
-  size_t row_ptr, adj, edges, comp, word_comp, word_mask, anchors, tmp, cloud, ctl;
-  size_t rootkey, pw, q0, q1, qh0, qh1, vis, st, gl;
-  size_t slots;        // path-2 tree scratch
+  size_t row_ptr, adj, edges, comp, word_comp, word_mask, word_main, anchors, tmp, cloud, ctl;
+  size_t scratch;      // create temporaries, cloud staging, rounded graphL states
+  size_t gl;           // graphL loss partials
+  // whole-grid path: kGridSlots trees in flight
+  size_t gpw, gql, gqh, gfb, gvis, gsb, grootkey, gctl, gbar;
+  size_t hcap;         // heavy-list entries per list
+  size_t gpstride;     // per-slot vertex stride (n rounded up to 32)
+  size_t gwstride;     // per-slot bitmap stride (words rounded up to 32)
+  size_t slots;        // one-workgroup-per-tree scratch in workspace memory
   size_t nslots, slot_stride;
   size_t total;
 };
@@ -191,6 +193,7 @@ void prof_end(fi_graph* g, hipStream_t s, void* token, int kernel);
 
 // launchers implemented in the .hip files
 hipError_t launch_sweep(fi_graph* g, const SweepArgs& a, hipStream_t s);
+hipError_t launch_grid(fi_graph* g, const SweepArgs& a, hipStream_t s);
 hipError_t launch_count(const DevGraph& dg, const uint64_t* bits, int32_t B, uint64_t* counts,
                         hipStream_t s);
 

@@ -196,12 +196,13 @@ __global__ void k_uf_compress(int32_t* parent, int32_t n) {
     parent[v] = uf_find(parent, (int32_t)v);
 }
 
-// One wave per 64-vertex word: which vertices have edges, and the anchor they
-// share (-1 if several, -2 if none).  Also lists anchors of components with an
-// edge and counts components and isolated vertices.
+// One wave per 64-vertex word: which vertices have edges, the smallest anchor
+// among them (the word's "main" component, -2 if none) and which of them
+// belong to it.  Also lists anchors of components with an edge and counts
+// components and isolated vertices.
 __global__ void k_word_info(const int32_t* rp, const int32_t* comp, int32_t n, int32_t nwords,
-                            int32_t* word_comp, uint64_t* word_mask, int32_t* anchors,
-                            uint64_t* ctl) {
+                            int32_t* word_comp, uint64_t* word_mask, uint64_t* word_main,
+                            int32_t* anchors, uint64_t* ctl) {
   const int lane = lane_id();
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -212,11 +213,12 @@ __global__ void k_word_info(const int32_t* rp, const int32_t* comp, int32_t n, i
     bool has_edge = valid && rp[v + 1] > rp[v];
     int32_t c = has_edge ? comp[v] : INT32_MAX;
     int32_t cmin = wave_min_i32(c);
-    int32_t cmax = wave_max_i32(has_edge ? c : -1);
     uint64_t mask = __ballot(has_edge);
+    uint64_t main = __ballot(has_edge && c == cmin);
     if (lane == 0) {
       word_mask[i] = mask;
-      word_comp[i] = mask == 0 ? -2 : (cmin == cmax ? cmin : -1);
+      word_main[i] = main;
+      word_comp[i] = mask == 0 ? -2 : cmin;
     }
     bool is_anchor = has_edge && comp[v] == (int32_t)v;
     if (valid && comp[v] == (int32_t)v) ncomp++;
@@ -349,20 +351,28 @@ Layout make_layout(int32_t n, int64_t nnz, int64_t cloud_capacity, uint64_t tabl
   L.comp = take(4 * nn);
   L.word_comp = take(4 * nw);
   L.word_mask = take(8 * nw);
+  L.word_main = take(8 * nw);
   L.anchors = take(4 * nn);
   L.tmp = take(4 * (nn / kScanTile + 2));
   L.cloud = take(sizeof(CloudSlot) * table_size);
   L.ctl = take(8 * C_WORDS);
-  L.rootkey = take(8 * nn);
-  // tree words; also stages rounded graphL states (R <= 64 bitmaps)
-  L.pw = take(std::max<size_t>(8 * nn, 8 * (size_t)kGraphLMaxR * nw));
-  L.q0 = take(4 * (nn + 64));
-  L.q1 = take(4 * (nn + 64));
-  L.qh0 = take(8 * (nn + 64));
-  L.qh1 = take(8 * (nn + 64));
-  L.vis = take(8 * nw);
-  L.st = take(8 * nw);
+  // two int32 arrays of n + 64 at create; cloud staging; R <= 64 rounded states
+  L.scratch = take(std::max<size_t>(8 * (nn + 64), 8 * (size_t)kGraphLMaxR * nw));
   L.gl = take(8 * (size_t)kGraphLBlocks * kGraphLMaxR);
+  // whole-grid path
+  const size_t S = kGridSlots;
+  L.hcap = (size_t)nnz / 32 + 1;
+  L.gpstride = (nn + 31) / 32 * 32;
+  L.gwstride = (nw + 31) / 32 * 32;
+  L.gpw = take(8 * S * L.gpstride);
+  L.gql = take(4 * S * 2 * (nn + 64));
+  L.gqh = take(8 * S * 2 * (L.hcap + 64));
+  L.gfb = take(8 * 3 * S * L.gwstride); // three frontier bitmaps per slot
+  L.gvis = take(8 * S * L.gwstride);    // visited, per slot
+  L.gsb = take(8 * S * L.gwstride);     // state bits, per slot
+  L.grootkey = take(8 * S * L.gpstride);
+  L.gctl = take(8 * S * kGridCtlWords);
+  L.gbar = take(8 * S * kGridBarWords);
   // per-workgroup tree scratch (a tree word and a queue entry per vertex)
   L.slot_stride = align_up(12 * nn);
   L.nslots = 0;
@@ -440,7 +450,7 @@ int fi_graph_create(int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int3
   FI_HIP(hipGetDevice(&dev));
   FI_HIP(hipDeviceGetAttribute(&g->cu_count, hipDeviceAttributeMultiprocessorCount, dev));
   FI_HIP(hipDeviceGetAttribute(&g->max_shared, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-  g->sched = fi_schedule{0, 256, 0, 512};
+  g->sched = fi_schedule{0, 256, 0, 512, 4};
 
   DevGraph& G = g->dg;
   G.n = n;
@@ -453,6 +463,7 @@ int fi_graph_create(int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int3
   G.comp = (const int32_t*)(ws + L.comp);
   G.word_comp = (const int32_t*)(ws + L.word_comp);
   G.word_mask = (const uint64_t*)(ws + L.word_mask);
+  G.word_main = (const uint64_t*)(ws + L.word_main);
   G.anchors = (const int32_t*)(ws + L.anchors);
   G.cloud = (CloudSlot*)(ws + L.cloud);
   G.cloud_mask = tsize - 1;
@@ -486,8 +497,8 @@ int fi_graph_create(int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int3
   if (flags & V_ASYM) return fail(FI_EASYM);
 
   // packed adjacency and the upper-triangle edge list
-  int32_t* upper_start = (int32_t*)(ws + L.q0);
-  int32_t* edge_off = (int32_t*)(ws + L.q1);
+  int32_t* upper_start = (int32_t*)(ws + L.scratch);
+  int32_t* edge_off = upper_start + (n + 64);
   int32_t* tile_sums = (int32_t*)(ws + L.tmp);
   hipLaunchKernelGGL(k_copy_i32, dim3(grid_for(n + 1, B)), dim3(B), 0, s, d_row_ptr,
                      (int32_t*)G.row_ptr, (int64_t)n + 1);
@@ -514,10 +525,15 @@ int fi_graph_create(int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int3
     hipLaunchKernelGGL(k_uf_compress, dim3(grid_for(n, B)), dim3(B), 0, s, comp, n);
     hipLaunchKernelGGL(k_word_info, dim3(grid_for((int64_t)G.nwords * 64, B)), dim3(B), 0, s,
                        G.row_ptr, G.comp, n, G.nwords, (int32_t*)G.word_comp,
-                       (uint64_t*)G.word_mask, (int32_t*)G.anchors, ctl);
-    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, B)), dim3(B), 0, s,
-                       (uint64_t*)(ws + L.rootkey), (int64_t)n, kUnvisited);
+                       (uint64_t*)G.word_mask, (uint64_t*)G.word_main, (int32_t*)G.anchors, ctl);
+    const int64_t nroot = (int64_t)L.gpstride * kGridSlots;
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(nroot, B)), dim3(B), 0, s,
+                       (uint64_t*)(ws + L.grootkey), nroot, kUnvisited);
   }
+  hipLaunchKernelGGL(k_fill_u64, dim3(64), dim3(B), 0, s, (uint64_t*)(ws + L.gbar),
+                     (int64_t)kGridSlots * kGridBarWords, 0ull);
+  hipLaunchKernelGGL(k_fill_u64, dim3(4), dim3(B), 0, s, (uint64_t*)(ws + L.gctl),
+                     (int64_t)kGridSlots * kGridCtlWords, 0ull);
   hipLaunchKernelGGL(k_cloud_reset, dim3(grid_for((int64_t)tsize, B)), dim3(B), 0, s, G.cloud,
                      (int64_t)tsize, ctl);
   uint64_t info[3] = {0, 0, 0};
@@ -632,7 +648,7 @@ int fi_cloud_load(fi_graph* g, const fi_cloud_entry* h_entries, int64_t count, v
   if (count == 0) return FI_OK;
   hipStream_t s = (hipStream_t)stream;
   // stage through the tree-word scratch, in chunks that fit it
-  uint64_t* stage = (uint64_t*)(g->ws + g->L.pw);
+  uint64_t* stage = (uint64_t*)(g->ws + g->L.scratch);
   int64_t per = std::max<int64_t>(1, (int64_t)g->dg.n / 5);
   std::vector<uint64_t> buf;
   for (int64_t c0 = 0; c0 < count; c0 += per) {
@@ -663,7 +679,8 @@ int fi_set_schedule(fi_graph* g, const fi_schedule* sc) {
   if (!g || !sc) return FI_EINVAL;
   if (sc->path < 0 || sc->path > 3) return FI_EINVAL;
   if (sc->block != 256 && sc->block != 512 && sc->block != 1024) return FI_EINVAL;
-  if (sc->grid < 0 || sc->heavy < 32) return FI_EINVAL;
+  if (sc->grid < 0 || sc->heavy < 32 || sc->batch < 1 || sc->batch > kGridSlots) return FI_EINVAL;
+  if (sc->grid > 16 * 4096) return FI_EINVAL;
   if (sc->path == 1 && (size_t)g->dg.n * 12 + 32768 > (size_t)g->max_shared) return FI_EINVAL;
   if (sc->path == 2 && g->L.nslots == 0) return FI_EINVAL;
   g->sched = *sc;

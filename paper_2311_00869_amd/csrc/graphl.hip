@@ -171,7 +171,7 @@ int fi_round_count(fi_graph* g, const float* d_gamma, int32_t R, uint64_t* d_cou
   if (!d_gamma) return FI_EINVAL;
   // rounded states go to the caller's buffer, or to the tree-word scratch
   // (R * ceil(n/64) words <= 8n bytes for R <= 64)
-  uint64_t* bits = d_bits_out ? d_bits_out : (uint64_t*)(g->ws + g->L.pw);
+  uint64_t* bits = d_bits_out ? d_bits_out : (uint64_t*)(g->ws + g->L.scratch);
   const int64_t waves = (int64_t)g->dg.nwords * R;
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((waves * 64 + 255) / 256, 65536));
   hipLaunchKernelGGL(k_gl_round, dim3(grid), dim3(256), 0, s, d_gamma, g->dg.n, g->dg.nwords,

@@ -46,7 +46,7 @@ class CloudEntry(ctypes.Structure):
 
 class Schedule(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("grid", ctypes.c_int32), ("heavy", ctypes.c_int32)]
+                ("grid", ctypes.c_int32), ("heavy", ctypes.c_int32), ("batch", ctypes.c_int32)]
 
 
 _lock = threading.Lock()
@@ -284,14 +284,14 @@ class Graph:
         return (counts, bits) if return_bits else counts
 
     # ---------------------------------------------------------------- tuning / timing
-    def set_schedule(self, path=0, block=256, grid=0, heavy=512):
-        s = Schedule(path, block, grid, heavy)
+    def set_schedule(self, path=0, block=256, grid=0, heavy=512, batch=4):
+        s = Schedule(path, block, grid, heavy, batch)
         _check(self.lib.fi_set_schedule(self.handle, ctypes.byref(s)), "set_schedule")
 
     def get_schedule(self):
         s = Schedule()
         _check(self.lib.fi_get_schedule(self.handle, ctypes.byref(s)), "get_schedule")
-        return dict(path=s.path, block=s.block, grid=s.grid, heavy=s.heavy)
+        return dict(path=s.path, block=s.block, grid=s.grid, heavy=s.heavy, batch=s.batch)
 
     def prof_enable(self, on=True):
         _check(self.lib.fi_prof_enable(self.handle, 1 if on else 0), "prof_enable")

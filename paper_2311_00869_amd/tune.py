@@ -1,0 +1,84 @@
+"""Schedule choice for the sweep: a default by graph size, and an autotuner
+that times candidate schedules on a few trees and keeps the fastest.
+Schedules never change results (every path computes the same trees), so
+tuning only trades speed.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+
+LDS_BYTES = 160 * 1024
+
+
+def candidates(n: int, nnz: int):
+    out = []
+    if 12 * n + 32768 <= LDS_BYTES:
+        for b in (256, 512, 1024):
+            out.append(dict(path=1, block=b, grid=0, heavy=512, batch=1))
+    if n <= 1_000_000:
+        for b in (256, 512, 1024):
+            out.append(dict(path=2, block=b, grid=0, heavy=512, batch=1))
+    for b in (256, 512, 1024):
+        for batch in (1, 4, 8):
+            out.append(dict(path=3, block=b, grid=0, heavy=512, batch=batch))
+    return out
+
+
+def _key(n, nnz):
+    return f"{n}:{nnz}"
+
+
+def default_schedule(n: int, nnz: int):
+    cache = _load()
+    if _key(n, nnz) in cache:
+        return dict(cache[_key(n, nnz)])
+    if 12 * n + 32768 <= LDS_BYTES:
+        return dict(path=1, block=512, grid=0, heavy=512, batch=1)
+    if n <= 200_000:
+        return dict(path=2, block=1024, grid=0, heavy=512, batch=1)
+    return dict(path=3, block=1024, grid=0, heavy=512, batch=8)
+
+
+def _load():
+    if os.path.exists(CACHE):
+        with open(CACHE) as f:
+            return json.load(f)
+    return {}
+
+
+def autotune(graph, trees: int = 16, seed: int = 12345, save: bool = True, verbose=False):
+    """Time each candidate schedule on `trees` trees; keep the fastest."""
+    import torch
+
+    best = None
+    results = []
+    for s in candidates(graph.n, graph.nnz):
+        try:
+            graph.set_schedule(**s)
+        except Exception:
+            continue
+        graph.cloud_reset()
+        graph.sweep_range(0, min(trees, 2), seed)
+        torch.cuda.synchronize()
+        graph.cloud_reset()
+        t0 = time.perf_counter()
+        graph.sweep_range(0, trees, seed)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        results.append((el, s))
+        if verbose:
+            print(f"# tune {s}: {trees / el:.1f} trees/s", flush=True)
+        if best is None or el < best[0]:
+            best = (el, s)
+    graph.cloud_reset()
+    graph.set_schedule(**best[1])
+    if save:
+        cache = _load()
+        cache[_key(graph.n, graph.nnz)] = best[1]
+        with open(CACHE, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+    return best[1], results
