@@ -37,7 +37,7 @@ def algorithmic_bytes_per_tree(n: int, nnz: int) -> int:
 
 def kernel_source_sha() -> str:
     h = hashlib.sha256()
-    for f in ("sweep.hip", "fi_prims.h", "fi_internal.h"):
+    for f in ("sweep.hip", "sweep_grid.hip", "fi_prims.h", "fi_internal.h"):
         with open(os.path.join(ROOT, "paper_2311_00869_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -67,10 +67,11 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--heavy", type=int, default=0)
+    ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graphl", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--cpu-trees", type=int, default=1)
+    ap.add_argument("--cpu-trees", type=int, default=2)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -103,7 +104,7 @@ def main():
     T = args.trees
     G = fr.Graph(g.row_ptr, g.col, g.sign, cloud_capacity=T)
     sched = tune.default_schedule(G.n, G.nnz)
-    for k in ("path", "block", "grid", "heavy"):
+    for k in ("path", "block", "grid", "heavy", "batch"):
         v = getattr(args, k)
         if v:
             sched[k] = v

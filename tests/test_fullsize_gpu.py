@@ -1,0 +1,67 @@
+"""Full-size parity: the 16M-vertex / 64M-edge graph in the launch
+configuration the benchmark times, and the 1M-vertex planted power-law graph,
+against per-tree results the CPU oracle wrote ahead of time
+(tests/golden/make_fullsize_golden.py)."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2311_00869_amd import synth, tune
+
+pytestmark = pytest.mark.gpu
+
+fr = pytest.importorskip("paper_2311_00869_amd.frustration")
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, f"fullsize_{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    with open(path) as f:
+        return json.load(f)
+
+
+def _check(G, gold, schedule):
+    G.set_schedule(**schedule)
+    G.cloud_reset()
+    t0, t1, seed = gold["t0"], gold["t1"], gold["seed"]
+    sw = G.sweep_range(t0, t1, seed, tree_switches=True).cpu().numpy().astype(np.uint64)
+    want = np.array(gold["trees"], dtype=np.uint64)
+    assert np.array_equal(sw, want[:, 0]), (schedule, sw, want[:, 0])
+    assert np.array_equal(G.cloud(), np.array(gold["cloud"], dtype=np.uint64)), schedule
+    assert list(G.min_frustration()) == gold["best"], schedule
+
+
+def test_large_graph_bench_configuration():
+    gold = _golden("large")
+    g = synth.config_large(0)
+    assert (g.n, g.nnz) == (gold["n"], gold["nnz"])
+    G = fr.Graph(g.row_ptr, g.col, g.sign, cloud_capacity=64)
+    _check(G, gold, tune.default_schedule(G.n, G.nnz))
+    _check(G, gold, dict(path=3, block=512, heavy=256, batch=1))
+    # every tree's frustrated edges, recounted by the exact counter from its state
+    words, s0 = G.tree_state(gold["seed"], gold["t0"])
+    got = int(G.count(torch.from_numpy(words.view(np.int64))).item())
+    assert got == s0 == gold["trees"][0][0]
+    G.close()
+
+
+def test_planted_powerlaw_all_paths():
+    gold = _golden("planted")
+    g = synth.config_planted_powerlaw(0)
+    assert (g.n, g.nnz) == (gold["n"], gold["nnz"])
+    G = fr.Graph(g.row_ptr, g.col, g.sign, cloud_capacity=256)
+    for sched in [tune.default_schedule(G.n, G.nnz), dict(path=2, block=1024),
+                  dict(path=3, block=1024, batch=8), dict(path=3, block=256, batch=3, heavy=64)]:
+        _check(G, gold, sched)
+    # the planted split frustrates exactly the flipped edges
+    side = g.meta["side"]
+    idx = np.flatnonzero(side == 1)
+    w = np.zeros(G.nwords, np.uint64)
+    np.bitwise_or.at(w, idx // 64, np.left_shift(np.uint64(1), (idx % 64).astype(np.uint64)))
+    assert int(G.count(torch.from_numpy(w.view(np.int64))).item()) == gold["planted_flipped"]
+    G.close()
