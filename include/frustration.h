@@ -191,24 +191,39 @@ int fi_round_count(fi_graph* g, const float* d_gamma, int32_t R, uint64_t* d_cou
 
 /* ---------------------------------------------------------------- batches */
 
-/* Many independent graphs swept in one launch (Alg. alg-index per graph).
+/* Many independent graphs swept together (Alg. alg-index per graph), for
+ * batches of small and medium graphs of uneven size.
  * The graphs are concatenated: graph i has vertices
- * h_vertex_offsets[i] .. h_vertex_offsets[i+1]-1 and CSR entries
- * h_nnz_offsets[i] .. h_nnz_offsets[i+1]-1; d_row_ptr int32[total_n + G]
- * holds each graph's own row_ptr (local, starting at 0) back to back, and
- * d_col holds local column ids.  Each graph must satisfy the
- * fi_graph_create contract on its own.  Only the minimum and per-graph
- * statistics are kept (no cloud). */
+ * h_vertex_offsets[i] .. h_vertex_offsets[i+1]-1 (G+1 host int64 offsets
+ * starting at 0) and CSR entries h_nnz_offsets[i] .. h_nnz_offsets[i+1]-1;
+ * d_row_ptr int32[total_n + G] holds each graph's own row_ptr (starting at 0)
+ * back to back, and d_col holds graph-local column ids.  Each graph must
+ * satisfy the fi_graph_create contract on its own, have at most 1,000,000
+ * vertices, and is swept with its own vertex ids, exactly as if it had been
+ * uploaded alone.  Every graph keeps its own cloud of up to
+ * cloud_capacity_per_graph states.  The workspace (fi_batch_workspace_size
+ * bytes, 256-byte aligned, owned by the caller) must outlive the handle; the
+ * input arrays may be freed once fi_batch_create returns.  Errors: FI_EINVAL
+ * for bad offsets, sizes or row_ptr, the fi_graph_create codes for a graph
+ * that breaks the contract, FI_EWORKSPACE for a short workspace.  The handle
+ * serves fi_batch_sweep, fi_graph_status, fi_set_schedule (block and grid
+ * only), fi_get_schedule, fi_prof_enable / fi_prof_read and
+ * fi_graph_destroy; the single-graph calls return FI_EINVAL on it. */
 int fi_batch_workspace_size(int32_t G, const int64_t* h_vertex_offsets, const int64_t* h_nnz_offsets,
-                            size_t* out_bytes);
+                            int64_t cloud_capacity_per_graph, size_t* out_bytes);
 int fi_batch_create(int32_t G, const int64_t* h_vertex_offsets, const int64_t* h_nnz_offsets,
                     const int32_t* d_row_ptr, const int32_t* d_col, const int8_t* d_sign,
-                    void* d_workspace, size_t ws_bytes, void* stream, fi_graph** out);
+                    int64_t cloud_capacity_per_graph, void* d_workspace, size_t ws_bytes,
+                    void* stream, fi_graph** out);
 
-/* Trees t = 0 .. trees_per_graph-1 of every graph (all graphs use `seed`).
- * d_min_per_graph uint64[G][2]: (minimum switches, first tree reaching it),
- * d_distinct_per_graph (may be NULL) uint64[G]: number of distinct states
- * among the graph's trees.  Asynchronous. */
+/* Trees t = 0 .. trees_per_graph-1 of every graph (all graphs use `seed`):
+ * one launch per size class, work items (graph, tree) ordered largest graph
+ * first and drawn by persistent workgroups.  Each call starts from empty
+ * clouds.  Outputs, device memory: d_min_per_graph uint64[G][2] =
+ * (minimum switches, first tree reaching it), d_distinct_per_graph (may be
+ * NULL) uint64[G] = distinct balanced states among the graph's trees.
+ * Launches kernels only (no host synchronisation, memset or allocation), so
+ * it may be recorded into a HIP graph on `stream`. */
 int fi_batch_sweep(fi_graph* b, int64_t trees_per_graph, uint64_t seed, uint64_t* d_min_per_graph,
                    uint64_t* d_distinct_per_graph, void* stream);
 

@@ -1,31 +1,652 @@
-// Many independent graphs in one launch (placeholder entry points until the
-// batched sweep lands).
+// Many independent graphs of uneven size swept together (Alg. alg-index per
+// graph).  The graphs are validated, packed and split into components in one
+// pass each over the concatenated arrays (every element finds its graph by a
+// binary search over the offsets); each keeps its own vertex ids, its own
+// small cloud and its own minimum.  Sweeping hands out work items
+// (graph, tree), largest graph first, to persistent workgroups that each run
+// one whole tree (the same routine as the single-graph sweep): graphs small
+// enough keep their tree state in LDS, the others in a workspace slice.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <new>
+#include <numeric>
+#include <vector>
+
 #include "fi_internal.h"
+#include "fi_prims.h"
+#include "fi_wg.h"
+
+namespace fi {
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+constexpr int kCtlPerGraph = 32;       // err, best, distinct count, trees; own 256-byte line
+constexpr int32_t kMaxBatchN = 1000000;
+constexpr int kLdsMaxN = 6144;         // graphs up to this size keep their tree in LDS
+// item tickets of the two size classes, each on its own 128-byte line of the
+// batch control block
+constexpr int kTicket0 = C_UNIT;
+constexpr int kTicket1 = C_UNIT + 16;
+
+inline int grid_for(int64_t work, int block, int cap = 65536) {
+  int64_t g = (work + block - 1) / block;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+}
+
+struct BatchGraph {
+  int32_t n, nwords;
+  int64_t nnz, m;
+  int64_t vo, no, me, ro;  // first vertex, CSR entry, edge, row_ptr slot
+};
+
+struct BatchLayout {
+  size_t meta, offs, row_ptr, adj, edges, comp, ustart, eoff, tiles, gctl, clouds, ctl, small, large,
+      slots;
+  size_t slot_stride, nslots;
+  size_t total;
+};
+
+struct BatchInfo {
+  int32_t G;
+  int64_t n_total, nnz_total, m_total;
+  int64_t cap;
+  uint64_t tsize;
+  int32_t n_max_small, n_max_large;
+  int32_t n_small, n_large;
+  int per_cu[3][2];  // [block 256/512/1024][in LDS, in workspace]
+  BatchLayout L;
+};
+
+BatchLayout batch_layout(int32_t G, int64_t n_total, int64_t nnz_total, int32_t n_max_large,
+                         uint64_t tsize) {
+  BatchLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + std::max<size_t>(bytes, 1));
+    return o;
+  };
+  const size_t g = (size_t)G, n = (size_t)n_total, nnz = (size_t)nnz_total, m = nnz / 2;
+  L.meta = take(sizeof(BatchGraph) * g);
+  L.offs = take(8 * 4 * (g + 1));  // vo, no, me, ro
+  L.row_ptr = take(4 * (n + g));
+  L.adj = take(4 * nnz);
+  L.edges = take(8 * m);
+  L.comp = take(4 * n);
+  L.ustart = take(4 * (n + 64));
+  L.eoff = take(4 * (n + 64));
+  L.tiles = take(4 * (n / 1024 + 2));
+  L.gctl = take(8 * kCtlPerGraph * g);
+  L.clouds = take(sizeof(CloudSlot) * tsize * g);
+  L.ctl = take(8 * C_WORDS);
+  L.small = take(4 * g);
+  L.large = take(4 * g);
+  L.slot_stride = align_up(12 * (size_t)std::max(n_max_large, 1));
+  L.nslots = n_max_large > 0
+                 ? std::min<size_t>(2048, std::max<size_t>(64, ((size_t)8 << 30) / L.slot_stride))
+                 : 0;
+  L.slots = take(L.slot_stride * L.nslots);
+  L.total = off;
+  return L;
+}
+
+// Largest i in [0, len) with off[i] <= x.
+__device__ __forceinline__ int32_t which(const int64_t* off, int32_t len, int64_t x) {
+  int32_t lo = 0, hi = len;
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (off[mid] <= x) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int32_t row_in(const int32_t* rp, int32_t n, int64_t e) {
+  int32_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int32_t mid = lo + ((hi - lo) >> 1);
+    if ((int64_t)rp[mid] <= e) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// row_ptr entries: starts at 0, ends at the graph's nnz, never decreases
+__global__ void k_b_rowptr(const int32_t* rp, const BatchGraph* meta, const int64_t* ro, int32_t G,
+                           int64_t total, uint64_t* ctl) {
+  bool bad = false;
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < total;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t g = which(ro, G, r);
+    const BatchGraph b = meta[g];
+    const int64_t local = r - b.ro;
+    const int32_t x = rp[r];
+    if (local == 0 && x != 0) bad = true;
+    if (local == b.n && (int64_t)x != b.nnz) bad = true;
+    if (local > 0 && x < rp[r - 1]) bad = true;
+  }
+  if (bad) atomicOr((unsigned long long*)(ctl + C_FLAGS), (unsigned long long)V_ROWPTR);
+}
+
+__global__ void k_b_entries(const int32_t* rp, const int32_t* col, const int8_t* sign,
+                            const BatchGraph* meta, const int64_t* no, int32_t G, int64_t total,
+                            uint64_t* ctl) {
+  uint32_t f = 0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t g = which(no, G, e);
+    const BatchGraph b = meta[g];
+    const int32_t* rpg = rp + b.ro;
+    const int32_t* cg = col + b.no;
+    const int8_t* sg = sign + b.no;
+    const int64_t le = e - b.no;
+    const int32_t u = row_in(rpg, b.n, le);
+    const int32_t v = cg[le];
+    const int s = sg[le];
+    if (v < 0 || v >= b.n) { f |= V_RANGE; continue; }
+    if (s != 1 && s != -1) f |= V_SIGN;
+    if (v == u) f |= V_SELF;
+    if (le + 1 < (int64_t)rpg[u + 1]) {
+      const int32_t c2 = cg[le + 1];
+      if (c2 == v) f |= V_DUP;
+      else if (c2 < v) f |= V_UNSORTED;
+    }
+    int64_t lo = rpg[v], hi = rpg[v + 1];
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (cg[mid] < u) lo = mid + 1; else hi = mid;
+    }
+    if (lo >= rpg[v + 1] || cg[lo] != u || sg[lo] != s) f |= V_ASYM;
+  }
+  if (f) atomicOr((unsigned long long*)(ctl + C_FLAGS), (unsigned long long)f);
+}
+
+// per vertex: first entry above the diagonal (global entry index) and count
+__global__ void k_b_upper(const int32_t* rp, const int32_t* col, const BatchGraph* meta,
+                          const int64_t* vo, int32_t G, int64_t n_total, int32_t* ustart,
+                          int32_t* ucnt) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n_total;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t g = which(vo, G, v);
+    const BatchGraph b = meta[g];
+    const int32_t u = (int32_t)(v - b.vo);
+    const int32_t* rpg = rp + b.ro;
+    const int32_t* cg = col + b.no;
+    int32_t lo = rpg[u], hi = rpg[u + 1];
+    while (lo < hi) {
+      const int32_t mid = lo + ((hi - lo) >> 1);
+      if (cg[mid] <= u) lo = mid + 1; else hi = mid;
+    }
+    ustart[v] = (int32_t)(b.no + lo);
+    ucnt[v] = rpg[u + 1] - lo;
+  }
+}
+
+__global__ void k_b_pack(const int32_t* rp, const int32_t* col, const int8_t* sign,
+                         const BatchGraph* meta, const int64_t* no, int32_t G, int64_t total,
+                         const int32_t* ustart, const int32_t* eoff, uint32_t* adj, uint2* edges,
+                         int32_t* rp_out) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t g = which(no, G, e);
+    const BatchGraph b = meta[g];
+    const int32_t* rpg = rp + b.ro;
+    const int64_t le = e - b.no;
+    const int32_t u = row_in(rpg, b.n, le);
+    const uint32_t v = (uint32_t)col[e];
+    const uint32_t a = v | ((sign[e] < 0 ? 1u : 0u) << 31);
+    adj[e] = a;
+    if ((int32_t)v > u) {
+      const int64_t gv = b.vo + u;
+      edges[eoff[gv] + (e - ustart[gv])] = make_uint2((uint32_t)u, a);
+    }
+  }
+  (void)rp_out;
+}
+
+__global__ void k_b_copy_rp(const int32_t* rp, int32_t* out, int64_t total) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = rp[i];
+}
+
+// Union-find over global vertex ids (graph offset + local id); graphs are
+// disjoint, so every component lies inside one graph.
+__device__ __forceinline__ int32_t uf_find(int32_t* parent, int32_t x) {
+  int32_t p = load_agent_i32(parent + x);
+  while (p != x) {
+    x = p;
+    p = load_agent_i32(parent + x);
+  }
+  return x;
+}
+
+__global__ void k_b_uf_init(int32_t* parent, int64_t n) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x)
+    parent[v] = (int32_t)v;
+}
+
+__global__ void k_b_uf_hook(const uint2* edges, const BatchGraph* meta, const int64_t* me, int32_t G,
+                            int64_t m_total, int32_t* parent) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m_total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t g = which(me, G, e);
+    const int64_t base = meta[g].vo;
+    const int32_t u = (int32_t)(base + edges[e].x);
+    const int32_t v = (int32_t)(base + (edges[e].y & kVertexMask));
+    while (true) {
+      const int32_t ru = uf_find(parent, u), rv = uf_find(parent, v);
+      if (ru == rv) break;
+      const int32_t lo = min(ru, rv), hi = max(ru, rv);
+      if (atomicCAS(parent + hi, hi, lo) == hi) break;
+    }
+  }
+}
+
+// final: graph-local anchor (smallest local id of the component)
+__global__ void k_b_uf_local(int32_t* parent, const BatchGraph* meta, const int64_t* vo, int32_t G,
+                             int64_t n, int32_t* comp) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t g = which(vo, G, v);
+    comp[v] = uf_find(parent, (int32_t)v) - (int32_t)meta[g].vo;
+  }
+}
+
+__global__ void k_b_reset(CloudSlot* clouds, int64_t nslots, uint64_t* gctl, int32_t G,
+                          uint64_t* ctl) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nslots;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    CloudSlot s;
+    s.tag = kEmpty;
+    s.khi_min = ~0ull; s.khi_max = 0;
+    s.s_min = ~0ull; s.s_max = 0;
+    s.freq = 0; s.first = ~0ull; s.pad = 0;
+    clouds[i] = s;
+  }
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < G;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t* c = gctl + g * kCtlPerGraph;
+    c[C_ERR] = 0;
+    c[C_BEST] = ~0ull;
+    c[C_COUNT] = 0;
+    c[C_TREES] = 0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl[C_ERR] = 0;
+    ctl[kTicket0] = 0;
+    ctl[kTicket1] = 0;
+  }
+}
+
+__global__ void k_b_finish(const uint64_t* gctl, int32_t G, uint64_t* min_out, uint64_t* distinct,
+                           uint64_t* ctl) {
+  uint64_t err = 0;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < G;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t* c = gctl + g * kCtlPerGraph;
+    const uint64_t best = c[C_BEST];
+    min_out[2 * g] = best >> 32;
+    min_out[2 * g + 1] = best & 0xFFFFFFFFull;
+    if (distinct) distinct[g] = c[C_COUNT];
+    err |= c[C_ERR];
+  }
+  if (err) atomicOr((unsigned long long*)(ctl + C_ERR), (unsigned long long)err);
+}
+
+struct BatchArgs {
+  const BatchGraph* meta;
+  const int32_t* row_ptr;
+  const uint32_t* adj;
+  const uint2* edges;
+  const int32_t* comp;
+  CloudSlot* clouds;
+  uint64_t* gctl;
+  uint64_t* ticket;     // next work item of this size class
+  const int32_t* order; // graph ids of this size class, largest first
+  int64_t nitems;       // graphs in the class * trees per graph
+  int64_t trees;
+  uint64_t seed;
+  uint64_t tsize;
+  uint64_t cap;
+  char* slots;
+  size_t slot_stride;
+};
+
+template <int NT, bool IN_LDS>
+__global__ void __launch_bounds__(NT) k_batch_wg(BatchArgs B) {
+  __shared__ wg::WgShared<NT> sh;
+  __shared__ int64_t s_item;
+  extern __shared__ uint64_t dyn[];
+  while (true) {
+    if (threadIdx.x == 0) s_item = (int64_t)atomicAdd((unsigned long long*)B.ticket, 1ull);
+    __syncthreads();
+    const int64_t item = s_item;
+    __syncthreads();
+    if (item >= B.nitems) break;
+    const int32_t gi = B.order[item / B.trees];
+    const uint64_t t = (uint64_t)(item % B.trees);
+    const BatchGraph b = B.meta[gi];
+    DevGraph G{};
+    G.n = b.n;
+    G.nwords = b.nwords;
+    G.nnz = b.nnz;
+    G.m = b.m;
+    G.row_ptr = B.row_ptr + b.ro;
+    G.adj = B.adj + b.no;
+    G.edges = B.edges + b.me;
+    G.comp = B.comp + b.vo;
+    G.cloud = B.clouds + (size_t)gi * B.tsize;
+    G.cloud_mask = B.tsize - 1;
+    G.cloud_cap = B.cap;
+    G.ctl = B.gctl + (size_t)gi * kCtlPerGraph;
+    SweepArgs A{};
+    A.seed = B.seed;
+    A.t0 = 0;
+    A.t1 = (uint64_t)B.trees;
+    A.insert = 1;
+    uint64_t* pw;
+    int32_t* q;
+    if (IN_LDS) {
+      pw = dyn;
+      q = (int32_t*)(dyn + b.n);
+    } else {
+      char* slot = B.slots + (size_t)blockIdx.x * B.slot_stride;
+      pw = (uint64_t*)slot;
+      q = (int32_t*)(slot + 8 * (size_t)b.n);
+    }
+    wg::wg_tree<NT>(G, A, t, pw, q, sh);
+  }
+}
+
+inline int nt_index(int nt) { return nt == 1024 ? 2 : nt == 512 ? 1 : 0; }
+
+// Done once at create, so a sweep only launches kernels: the LDS size of the
+// in-LDS class and the resident workgroups per CU of both classes.
+template <int NT>
+hipError_t batch_occupancy(BatchInfo* bi) {
+  const int k = nt_index(NT);
+  const size_t bytes = 12 * (size_t)bi->n_max_small;
+  hipError_t e = hipFuncSetAttribute((const void*)k_batch_wg<NT, true>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&bi->per_cu[k][0], k_batch_wg<NT, true>, NT, bytes);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(&bi->per_cu[k][1], k_batch_wg<NT, false>, NT, 0);
+}
+
+template <int NT>
+void launch_class(fi_graph* h, const BatchArgs& a, bool lds, hipStream_t s) {
+  const BatchInfo* bi = (const BatchInfo*)h->batch;
+  int64_t grid = (int64_t)std::max(1, bi->per_cu[nt_index(NT)][lds ? 0 : 1]) * h->cu_count;
+  if (h->sched.grid > 0) grid = std::min<int64_t>(grid, h->sched.grid);
+  if (!lds) grid = std::min<int64_t>(grid, (int64_t)bi->L.nslots);
+  grid = std::max<int64_t>(1, std::min<int64_t>(grid, a.nitems));
+  if (lds)
+    hipLaunchKernelGGL((k_batch_wg<NT, true>), dim3((int)grid), dim3(NT), 12 * (size_t)bi->n_max_small,
+                       s, a);
+  else
+    hipLaunchKernelGGL((k_batch_wg<NT, false>), dim3((int)grid), dim3(NT), 0, s, a);
+}
+
+bool host_offsets_ok(int32_t G, const int64_t* vo, const int64_t* no, int32_t* n_max) {
+  if (G < 1 || !vo || !no || vo[0] != 0 || no[0] != 0) return false;
+  *n_max = 0;
+  for (int32_t g = 0; g < G; ++g) {
+    const int64_t n = vo[g + 1] - vo[g], nnz = no[g + 1] - no[g];
+    if (n < 0 || nnz < 0 || (nnz & 1) || n > kMaxBatchN) return false;
+    *n_max = std::max(*n_max, (int32_t)n);
+  }
+  return vo[G] + G < ((int64_t)1 << 31) && no[G] < ((int64_t)1 << 31);
+}
+
+}  // namespace
+
+void batch_info_free(void* p) { delete (BatchInfo*)p; }
+
+}  // namespace fi
+
+using namespace fi;
 
 extern "C" {
 
 int fi_batch_workspace_size(int32_t G, const int64_t* h_vertex_offsets,
-                            const int64_t* h_nnz_offsets, size_t* out_bytes) {
-  (void)G; (void)h_vertex_offsets; (void)h_nnz_offsets; (void)out_bytes;
-  return FI_EINVAL;
+                            const int64_t* h_nnz_offsets, int64_t cloud_capacity_per_graph,
+                            size_t* out_bytes) {
+  int32_t n_max = 0;
+  if (!out_bytes || cloud_capacity_per_graph < 1 ||
+      !host_offsets_ok(G, h_vertex_offsets, h_nnz_offsets, &n_max))
+    return FI_EINVAL;
+  int32_t n_max_large = 0;
+  for (int32_t g = 0; g < G; ++g) {
+    const int32_t n = (int32_t)(h_vertex_offsets[g + 1] - h_vertex_offsets[g]);
+    if (n > kLdsMaxN) n_max_large = std::max(n_max_large, n);
+  }
+  *out_bytes = batch_layout(G, h_vertex_offsets[G], h_nnz_offsets[G], n_max_large,
+                            table_size_for(cloud_capacity_per_graph)).total;
+  return FI_OK;
 }
 
 int fi_batch_create(int32_t G, const int64_t* h_vertex_offsets, const int64_t* h_nnz_offsets,
                     const int32_t* d_row_ptr, const int32_t* d_col, const int8_t* d_sign,
-                    void* d_workspace, size_t ws_bytes, void* stream, fi_graph** out) {
-  (void)G; (void)h_vertex_offsets; (void)h_nnz_offsets; (void)d_row_ptr; (void)d_col;
-  (void)d_sign; (void)d_workspace; (void)ws_bytes; (void)stream;
-  if (out) *out = nullptr;
-  return FI_EINVAL;
+                    int64_t cloud_capacity_per_graph, void* d_workspace, size_t ws_bytes,
+                    void* stream, fi_graph** out) {
+  if (!out) return FI_EINVAL;
+  *out = nullptr;
+  int32_t n_max = 0;
+  if (cloud_capacity_per_graph < 1 || !host_offsets_ok(G, h_vertex_offsets, h_nnz_offsets, &n_max))
+    return FI_EINVAL;
+  const int64_t n_total = h_vertex_offsets[G], nnz_total = h_nnz_offsets[G];
+  if (!d_row_ptr || (nnz_total > 0 && (!d_col || !d_sign))) return FI_EINVAL;
+  // host metadata and the two size classes, largest graph first
+  std::vector<BatchGraph> meta(G);
+  std::vector<int64_t> offs(4 * ((size_t)G + 1));
+  int64_t me = 0;
+  int32_t n_max_small = 0, n_max_large = 0;
+  std::vector<int32_t> small, large;
+  for (int32_t g = 0; g < G; ++g) {
+    BatchGraph& b = meta[g];
+    b.n = (int32_t)(h_vertex_offsets[g + 1] - h_vertex_offsets[g]);
+    b.nwords = (b.n + 63) / 64;
+    b.nnz = h_nnz_offsets[g + 1] - h_nnz_offsets[g];
+    b.m = b.nnz / 2;
+    b.vo = h_vertex_offsets[g];
+    b.no = h_nnz_offsets[g];
+    b.me = me;
+    b.ro = h_vertex_offsets[g] + g;
+    me += b.m;
+    if (b.n <= kLdsMaxN) {
+      small.push_back(g);
+      n_max_small = std::max(n_max_small, b.n);
+    } else {
+      large.push_back(g);
+      n_max_large = std::max(n_max_large, b.n);
+    }
+  }
+  for (int32_t g = 0; g <= G; ++g) {
+    offs[g] = g < G ? meta[g].vo : n_total;
+    offs[(G + 1) + g] = g < G ? meta[g].no : nnz_total;
+    offs[2 * (G + 1) + g] = g < G ? meta[g].me : me;
+    offs[3 * (G + 1) + g] = g < G ? meta[g].ro : n_total + G;
+  }
+  auto by_size = [&](int32_t a, int32_t b) {
+    return meta[a].nnz != meta[b].nnz ? meta[a].nnz > meta[b].nnz : a < b;
+  };
+  std::sort(small.begin(), small.end(), by_size);
+  std::sort(large.begin(), large.end(), by_size);
+  const uint64_t tsize = table_size_for(cloud_capacity_per_graph);
+  BatchLayout L = batch_layout(G, n_total, nnz_total, n_max_large, tsize);
+  if (!d_workspace || ws_bytes < L.total || ((uintptr_t)d_workspace % kAlign)) return FI_EWORKSPACE;
+
+  fi_graph* h = new (std::nothrow) fi_graph();
+  BatchInfo* bi = new (std::nothrow) BatchInfo();
+  if (!h || !bi) {
+    delete h;
+    delete bi;
+    return FI_EINVAL;
+  }
+  h->is_batch = true;
+  h->batch = bi;
+  auto fail = [&](int code) {
+    fi_graph_destroy(h);
+    return code;
+  };
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = (char*)d_workspace;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&h->cu_count, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipDeviceGetAttribute(&h->max_shared, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return fail(FI_EDEVICE);
+  bi->G = G;
+  bi->n_total = n_total;
+  bi->nnz_total = nnz_total;
+  bi->m_total = me;
+  bi->cap = cloud_capacity_per_graph;
+  bi->tsize = tsize;
+  bi->n_max_small = n_max_small;
+  bi->n_max_large = n_max_large;
+  bi->n_small = (int32_t)small.size();
+  bi->n_large = (int32_t)large.size();
+  bi->L = L;
+  h->ws = ws;
+  h->ws_bytes = ws_bytes;
+  h->sched = fi_schedule{0, 256, 0, 512, 1};
+  h->dg.ctl = (uint64_t*)(ws + L.ctl);
+  h->prof_events = prof_events_new();
+  if (!h->prof_events) return fail(FI_EINVAL);
+
+  BatchGraph* d_meta = (BatchGraph*)(ws + L.meta);
+  int64_t* d_offs = (int64_t*)(ws + L.offs);
+  const int64_t *d_vo = d_offs, *d_no = d_offs + (G + 1), *d_me = d_offs + 2 * (G + 1),
+                *d_ro = d_offs + 3 * (G + 1);
+  uint64_t* ctl = h->dg.ctl;
+  const int B = 256;
+  std::vector<uint64_t> zeros(C_WORDS, 0);
+  if (hipMemcpyAsync(d_meta, meta.data(), sizeof(BatchGraph) * G, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(d_offs, offs.data(), 8 * offs.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(ctl, zeros.data(), 8 * C_WORDS, hipMemcpyHostToDevice, s) != hipSuccess ||
+      (small.size() && hipMemcpyAsync(ws + L.small, small.data(), 4 * small.size(),
+                                      hipMemcpyHostToDevice, s) != hipSuccess) ||
+      (large.size() && hipMemcpyAsync(ws + L.large, large.data(), 4 * large.size(),
+                                      hipMemcpyHostToDevice, s) != hipSuccess))
+    return fail(FI_EDEVICE);
+  // row offsets first: the entry checks index columns through them
+  hipLaunchKernelGGL(k_b_rowptr, dim3(grid_for(n_total + G, B)), dim3(B), 0, s, d_row_ptr, d_meta,
+                     d_ro, G, n_total + G, ctl);
+  uint64_t flags = 0;
+  if (hipMemcpyAsync(&flags, ctl + C_FLAGS, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(FI_EDEVICE);
+  if (flags & V_ROWPTR) return fail(FI_EINVAL);
+  if (nnz_total > 0)
+    hipLaunchKernelGGL(k_b_entries, dim3(grid_for(nnz_total, B, 16384)), dim3(B), 0, s, d_row_ptr,
+                       d_col, d_sign, d_meta, d_no, G, nnz_total, ctl);
+  if (hipMemcpyAsync(&flags, ctl + C_FLAGS, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(FI_EDEVICE);
+  if (flags & V_RANGE) return fail(FI_EINVAL);
+  if (flags & V_SIGN) return fail(FI_ESIGN);
+  if (flags & V_SELF) return fail(FI_ESELFLOOP);
+  if (flags & V_DUP) return fail(FI_EDUP);
+  if (flags & V_UNSORTED) return fail(FI_EUNSORTED);
+  if (flags & V_ASYM) return fail(FI_EASYM);
+
+  int32_t* rp = (int32_t*)(ws + L.row_ptr);
+  int32_t* ustart = (int32_t*)(ws + L.ustart);
+  int32_t* eoff = (int32_t*)(ws + L.eoff);
+  hipLaunchKernelGGL(k_b_copy_rp, dim3(grid_for(n_total + G, B)), dim3(B), 0, s, d_row_ptr, rp,
+                     n_total + G);
+  if (n_total > 0) {
+    hipLaunchKernelGGL(k_b_upper, dim3(grid_for(n_total, B)), dim3(B), 0, s, d_row_ptr, d_col, d_meta,
+                       d_vo, G, n_total, ustart, eoff);
+    // exclusive scan of the per-vertex upper counts (graphs in order, so each
+    // graph's edges are contiguous from its edge offset)
+    std::vector<int32_t> cnt(n_total);
+    if (hipMemcpyAsync(cnt.data(), eoff, 4 * n_total, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail(FI_EDEVICE);
+    int64_t acc = 0;
+    for (int64_t v = 0; v < n_total; ++v) {
+      const int32_t c = cnt[v];
+      cnt[v] = (int32_t)acc;
+      acc += c;
+    }
+    if (acc != me) return fail(FI_EASYM);
+    if (hipMemcpyAsync(eoff, cnt.data(), 4 * n_total, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail(FI_EDEVICE);
+  }
+  if (nnz_total > 0)
+    hipLaunchKernelGGL(k_b_pack, dim3(grid_for(nnz_total, B, 16384)), dim3(B), 0, s, d_row_ptr, d_col,
+                       d_sign, d_meta, d_no, G, nnz_total, ustart, eoff, (uint32_t*)(ws + L.adj),
+                       (uint2*)(ws + L.edges), rp);
+  if (n_total > 0) {
+    int32_t* parent = (int32_t*)(ws + L.ustart);  // free again after packing
+    hipLaunchKernelGGL(k_b_uf_init, dim3(grid_for(n_total, B)), dim3(B), 0, s, parent, n_total);
+    if (me > 0)
+      hipLaunchKernelGGL(k_b_uf_hook, dim3(grid_for(me, B, 16384)), dim3(B), 0, s,
+                         (const uint2*)(ws + L.edges), d_meta, d_me, G, me, parent);
+    hipLaunchKernelGGL(k_b_uf_local, dim3(grid_for(n_total, B)), dim3(B), 0, s, parent, d_meta, d_vo,
+                       G, n_total, (int32_t*)(ws + L.comp));
+  }
+  if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess) return fail(FI_EDEVICE);
+  if (batch_occupancy<256>(bi) != hipSuccess || batch_occupancy<512>(bi) != hipSuccess ||
+      batch_occupancy<1024>(bi) != hipSuccess)
+    return fail(FI_EDEVICE);
+  *out = h;
+  return FI_OK;
 }
 
-int fi_batch_sweep(fi_graph* b, int64_t trees_per_graph, uint64_t seed, uint64_t* d_min_per_graph,
+int fi_batch_sweep(fi_graph* h, int64_t trees_per_graph, uint64_t seed, uint64_t* d_min_per_graph,
                    uint64_t* d_distinct_per_graph, void* stream) {
-  (void)b; (void)trees_per_graph; (void)seed; (void)d_min_per_graph; (void)d_distinct_per_graph;
-  (void)stream;
-  return FI_EINVAL;
+  if (!h || !h->is_batch || trees_per_graph < 1 || !d_min_per_graph) return FI_EINVAL;
+  if (trees_per_graph >= ((int64_t)1 << 32)) return FI_ERANGE;
+  BatchInfo* bi = (BatchInfo*)h->batch;
+  const BatchLayout& L = bi->L;
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = h->ws;
+  uint64_t* ctl = h->dg.ctl;
+  BatchArgs a{};
+  a.meta = (const BatchGraph*)(ws + L.meta);
+  a.row_ptr = (const int32_t*)(ws + L.row_ptr);
+  a.adj = (const uint32_t*)(ws + L.adj);
+  a.edges = (const uint2*)(ws + L.edges);
+  a.comp = (const int32_t*)(ws + L.comp);
+  a.clouds = (CloudSlot*)(ws + L.clouds);
+  a.gctl = (uint64_t*)(ws + L.gctl);
+  a.trees = trees_per_graph;
+  a.seed = seed;
+  a.tsize = bi->tsize;
+  a.cap = (uint64_t)bi->cap;
+  a.slots = ws + L.slots;
+  a.slot_stride = L.slot_stride;
+  const int nt = h->sched.block;
+  // clouds, per-graph minima and counters, error bits and both tickets
+  hipLaunchKernelGGL(k_b_reset, dim3(grid_for((int64_t)bi->tsize * bi->G, 256)), dim3(256), 0, s,
+                     (CloudSlot*)(ws + L.clouds), (int64_t)bi->tsize * bi->G, (uint64_t*)(ws + L.gctl),
+                     bi->G, ctl);
+  hipError_t e = hipGetLastError();
+  for (int cls = 0; cls < 2 && e == hipSuccess; ++cls) {
+    const bool lds = cls == 0;
+    a.order = (const int32_t*)(ws + (lds ? L.small : L.large));
+    a.nitems = (int64_t)(lds ? bi->n_small : bi->n_large) * trees_per_graph;
+    a.ticket = ctl + (lds ? kTicket0 : kTicket1);
+    if (a.nitems == 0) continue;
+    void* tok = nullptr;
+    if (prof_begin(h, s, &tok)) return FI_EDEVICE;
+    if (nt == 1024) launch_class<1024>(h, a, lds, s);
+    else if (nt == 512) launch_class<512>(h, a, lds, s);
+    else launch_class<256>(h, a, lds, s);
+    e = hipGetLastError();
+    prof_end(h, s, tok, 0);
+  }
+  if (e != hipSuccess) return FI_EDEVICE;
+  hipLaunchKernelGGL(k_b_finish, dim3(grid_for(bi->G, 256)), dim3(256), 0, s,
+                     (const uint64_t*)(ws + L.gctl), bi->G, d_min_per_graph, d_distinct_per_graph, ctl);
+  return hipGetLastError() == hipSuccess ? FI_OK : FI_EDEVICE;
 }
 
 }  // extern "C"

@@ -188,6 +188,8 @@ constexpr int kGraphLMaxR = 64;
 constexpr int kGraphLBlocks = 1024;
 
 // profiling events around one launch (no-ops unless profiling is on)
+void batch_info_free(void* p);
+void* prof_events_new();
 int prof_begin(fi_graph* g, hipStream_t s, void** token);
 void prof_end(fi_graph* g, hipStream_t s, void* token, int kernel);
 

@@ -554,6 +554,14 @@ int fi_graph_create(int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int3
   return FI_OK;
 }
 
+}  // extern "C"
+
+namespace fi {
+void* prof_events_new() { return new (std::nothrow) std::vector<ProfEvent>(); }
+}  // namespace fi
+
+extern "C" {
+
 void fi_graph_destroy(fi_graph* g) {
   if (!g) return;
   auto* ev = (std::vector<ProfEvent>*)g->prof_events;
@@ -564,12 +572,12 @@ void fi_graph_destroy(fi_graph* g) {
     }
     delete ev;
   }
-  if (g->batch) std::free(g->batch);
+  if (g->batch) batch_info_free(g->batch);
   delete g;
 }
 
 int fi_graph_info(fi_graph* g, int32_t* out_components, int32_t* out_isolated) {
-  if (!g) return FI_EINVAL;
+  if (!g || g->is_batch) return FI_EINVAL;
   if (out_components) *out_components = g->ncomp;
   if (out_isolated) *out_isolated = g->nisolated;
   return FI_OK;
@@ -586,7 +594,7 @@ int fi_graph_status(fi_graph* g, void* stream) {
 
 int fi_min_frustration(fi_graph* g, uint64_t* out_switches, uint64_t* out_first_tree,
                        void* stream) {
-  if (!g) return FI_EINVAL;
+  if (!g || g->is_batch) return FI_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   uint64_t w[4];
   FI_HIP(hipMemcpyAsync(w, g->dg.ctl, 32, hipMemcpyDeviceToHost, s));

@@ -85,8 +85,8 @@ def load_library(path: str = LIB_PATH):
             "fi_graphl_backward": ([vp, vp, i32, vp, vp, vp], c.c_int),
             "fi_graphl_step": ([vp, vp, i32, c.c_float, vp, vp], c.c_int),
             "fi_round_count": ([vp, vp, i32, vp, vp, vp], c.c_int),
-            "fi_batch_workspace_size": ([i32, vp, vp, P(sz)], c.c_int),
-            "fi_batch_create": ([i32, vp, vp, vp, vp, vp, vp, sz, vp, P(vp)], c.c_int),
+            "fi_batch_workspace_size": ([i32, vp, vp, i64, P(sz)], c.c_int),
+            "fi_batch_create": ([i32, vp, vp, vp, vp, vp, i64, vp, sz, vp, P(vp)], c.c_int),
             "fi_batch_sweep": ([vp, i64, u64, vp, vp, vp], c.c_int),
             "fi_set_schedule": ([vp, P(Schedule)], c.c_int),
             "fi_get_schedule": ([vp, P(Schedule)], c.c_int),
@@ -292,6 +292,109 @@ class Graph:
         s = Schedule()
         _check(self.lib.fi_get_schedule(self.handle, ctypes.byref(s)), "get_schedule")
         return dict(path=s.path, block=s.block, grid=s.grid, heavy=s.heavy, batch=s.batch)
+
+    def prof_enable(self, on=True):
+        _check(self.lib.fi_prof_enable(self.handle, 1 if on else 0), "prof_enable")
+
+    def prof_read(self, kernel=0):
+        ms, k = ctypes.c_double(), ctypes.c_int64()
+        _check(self.lib.fi_prof_read(self.handle, kernel, ctypes.byref(ms), ctypes.byref(k)), "prof_read")
+        return float(ms.value), int(k.value)
+
+
+class BatchGraph:
+    """Many independent signed graphs of uneven size swept in the same
+    launches, each with its own vertex ids, cloud and minimum.
+
+    graphs: a sequence of (row_ptr, col, sign) CSR triples (or objects with
+    those attributes).  They are concatenated on the host, uploaded once and
+    validated, packed and split into components on the GPU.
+    """
+
+    def __init__(self, graphs, cloud_capacity_per_graph: int = 1024, device="cuda", stream=None):
+        _require_gpu()
+        self.lib = load_library()
+        self.device = torch.device(device)
+        rps, cols, sgns = [], [], []
+        vo, no = [0], [0]
+        for gr in graphs:
+            if isinstance(gr, (tuple, list)):
+                rp, cl, sg = gr
+            else:
+                rp, cl, sg = gr.row_ptr, gr.col, gr.sign
+            rp = np.asarray(rp, dtype=np.int32)
+            cl = np.asarray(cl, dtype=np.int32)
+            sg = np.asarray(sg, dtype=np.int8)
+            rps.append(rp)
+            cols.append(cl)
+            sgns.append(sg)
+            vo.append(vo[-1] + rp.size - 1)
+            no.append(no[-1] + cl.size)
+        self.G = len(rps)
+        if self.G < 1:
+            raise FrustrationError(-1, "batch_create")
+        self.vertex_offsets = np.asarray(vo, dtype=np.int64)
+        self.nnz_offsets = np.asarray(no, dtype=np.int64)
+        self.cloud_capacity = int(cloud_capacity_per_graph)
+        rp_all = torch.from_numpy(np.concatenate(rps)).to(self.device)
+        col_all = torch.from_numpy(np.concatenate(cols) if no[-1] else np.zeros(1, np.int32)).to(self.device)
+        sg_all = torch.from_numpy(np.concatenate(sgns) if no[-1] else np.zeros(1, np.int8)).to(self.device)
+        vop = self.vertex_offsets.ctypes.data_as(ctypes.c_void_p)
+        nop = self.nnz_offsets.ctypes.data_as(ctypes.c_void_p)
+        size = ctypes.c_size_t(0)
+        _check(self.lib.fi_batch_workspace_size(self.G, vop, nop, self.cloud_capacity,
+                                                ctypes.byref(size)), "batch_workspace_size")
+        self.ws_bytes = int(size.value)
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        self._ws_ptr = (self.workspace.data_ptr() + 255) // 256 * 256
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = self.lib.fi_batch_create(self.G, vop, nop, _ptr(rp_all), _ptr(col_all), _ptr(sg_all),
+                                          self.cloud_capacity, ctypes.c_void_p(self._ws_ptr),
+                                          self.ws_bytes, _stream_ptr(stream), ctypes.byref(h))
+        _check(rc, "batch_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            torch.cuda.synchronize(self.device)
+            self.lib.fi_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sweep_into(self, trees: int, seed: int, min_out, distinct_out=None, stream=None):
+        """Launch-only form (no host synchronisation), usable under HIP graph
+        capture: min_out int64 [G, 2] receives (switches, first tree) per
+        graph, distinct_out int64 [G] the number of distinct states."""
+        _check(self.lib.fi_batch_sweep(self.handle, int(trees), seed & (2**64 - 1), _ptr(min_out),
+                                       _ptr(distinct_out) if distinct_out is not None else None,
+                                       _stream_ptr(stream)), "batch_sweep")
+
+    def sweep(self, trees: int, seed: int, stream=None):
+        """Sweep `trees` trees of every graph; returns (min [G, 2], distinct [G])
+        as int64 device tensors, after checking the sticky error bits."""
+        mn = torch.empty((self.G, 2), dtype=torch.int64, device=self.device)
+        ds = torch.empty(self.G, dtype=torch.int64, device=self.device)
+        self.sweep_into(trees, seed, mn, ds, stream)
+        self.status(stream)
+        return mn, ds
+
+    def status(self, stream=None):
+        _check(self.lib.fi_graph_status(self.handle, _stream_ptr(stream)), "batch_status")
+
+    def set_schedule(self, block=256, grid=0):
+        s = Schedule(0, block, grid, 512, 1)
+        _check(self.lib.fi_set_schedule(self.handle, ctypes.byref(s)), "set_schedule")
+
+    def get_schedule(self):
+        s = Schedule()
+        _check(self.lib.fi_get_schedule(self.handle, ctypes.byref(s)), "get_schedule")
+        return dict(block=s.block, grid=s.grid)
 
     def prof_enable(self, on=True):
         _check(self.lib.fi_prof_enable(self.handle, 1 if on else 0), "prof_enable")
