@@ -72,6 +72,8 @@ def main():
     ap.add_argument("--no-graphl", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-trees", type=int, default=2)
+    ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch leg")
+    ap.add_argument("--no-planted", action="store_true", help="skip the 10^4-tree planted leg")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -87,6 +89,14 @@ def main():
     from paper_2311_00869_amd import frustration as fr
     from paper_2311_00869_amd import synth
     from paper_2311_00869_amd import tune
+
+    batch_graphs = None
+    if not args.no_batch:
+        # generated before the GPU is touched; workers are spawned either way
+        t_gen = time.perf_counter()
+        batch_graphs = synth.config_batch_parallel(4096, 0)
+        print(f"# generated the uneven batch in {time.perf_counter() - t_gen:.1f}s",
+              file=sys.stderr, flush=True)
 
     t_gen = time.perf_counter()
     if args.workload == "large":
@@ -161,6 +171,11 @@ def main():
 
     if not args.no_graphl:
         extra["graphl"] = bench_graphl(fr, synth, torch)
+    if batch_graphs is not None:
+        extra["batch"] = bench_batch(fr, tune, torch, batch_graphs, args.steps)
+        del batch_graphs
+    if not args.no_planted:
+        extra["planted"] = bench_planted(fr, synth, tune, torch)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -231,6 +246,86 @@ def bench_graphl(fr, synth, torch):
         "autograd_steps_per_s": round(1.0 / autograd, 1),
         "best_rounded_frustration": int(counts.min().item()),
     }
+
+
+def bench_batch(fr, tune, torch, graphs, steps, trees=64):
+    """The uneven batch: 4,096 graphs x 64 trees in one fi_batch_sweep,
+    captured once as a HIP graph and replayed; against one launch per tree on
+    a sample of the graphs (the plain path)."""
+    G = len(graphs)
+    B = fr.BatchGraph(graphs, cloud_capacity_per_graph=trees)
+    sched, _ = tune.autotune_batch(B, trees=2, save=False)
+    mn = torch.zeros((G, 2), dtype=torch.int64, device="cuda")
+    ds = torch.zeros(G, dtype=torch.int64, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        B.sweep_into(trees, 0, mn, ds)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    B.status()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        B.sweep_into(trees, 0, mn, ds)
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    B.status()
+    out = {
+        "workload": f"{G} path+uniform graphs, n ~ U{{100..50,000}}, avg degree ~ U[4,16], "
+                    f"p+ ~ U[0.7,0.9], {trees} trees each, seed 0",
+        "trees_per_s": round(G * trees * steps / el, 1),
+        "ms_per_step": round(el / steps * 1e3, 3),
+        "schedule": sched, "hip_graph": True,
+        "total_nnz": int(B.nnz_offsets[-1]),
+        "sum_min_switches": int(mn[:, 0].sum().item()),
+    }
+    del graph
+    B.close()
+    # plain path: one single-graph handle and one launch per tree, 16 graphs
+    Gp, Tp = 16, 8
+    t_plain = 0.0
+    for g in graphs[:: G // Gp][:Gp]:
+        H = fr.Graph(g.row_ptr, g.col, g.sign, cloud_capacity=Tp)
+        H.set_schedule(**tune.default_schedule(H.n, H.nnz))
+        H.sweep_range(0, 1, 9)
+        torch.cuda.synchronize()
+        H.cloud_reset()
+        t0 = time.perf_counter()
+        for t in range(Tp):
+            H.sweep_range(t, t + 1, 0)
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t0
+        H.close()
+    out["plain_per_tree_trees_per_s"] = round(Gp * Tp / t_plain, 1)
+    return out
+
+
+def bench_planted(fr, synth, tune, torch, trees=10_000):
+    """10^4 trees in one sweep of the 1M-vertex planted graph."""
+    g = synth.config_planted_powerlaw(0)
+    G = fr.Graph(g.row_ptr, g.col, g.sign, cloud_capacity=trees)
+    G.set_schedule(**tune.default_schedule(G.n, G.nnz))
+    G.sweep(64, 1)
+    torch.cuda.synchronize()
+    G.cloud_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    G.sweep(trees, 0)
+    best = G.min_frustration()
+    el = time.perf_counter() - t0
+    out = {
+        "workload": "planted chung-lu n=1,000,000 m=10,000,000 gamma=2.1 flip=0.05, seed 0",
+        "trees": trees, "trees_per_s": round(trees / el, 1), "schedule": G.get_schedule(),
+        "min_switches": best[0], "planted_flipped": int(g.meta.get("flipped", -1)),
+        "distinct_states": G.cloud_size(),
+    }
+    G.close()
+    return out
 
 
 def cpu_baseline(g, trees):

@@ -228,6 +228,28 @@ def config_batch(G=4096, seed=0, n_lo=100, n_hi=50_000, indices=None):
     return [erdos_renyi_connected(int(ns[g]), int(ms[g]), float(pp[g]), (seed, g)) for g in idx]
 
 
+def _batch_one(args):
+    n, m, p, seed = args
+    return erdos_renyi_connected(n, m, p, seed)
+
+
+def config_batch_parallel(G=4096, seed=0, n_lo=100, n_hi=50_000, indices=None, workers=None):
+    """config_batch generated by worker processes (spawned, so a parent that
+    already uses the GPU is never forked); the graphs are identical."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import os
+
+    ns, ms, pp = config_batch_shapes(G, seed, n_lo, n_hi)
+    idx = list(range(G) if indices is None else indices)
+    jobs = [(int(ns[g]), int(ms[g]), float(pp[g]), (seed, g)) for g in idx]
+    workers = workers or min(16, os.cpu_count() or 1)
+    if workers <= 1 or len(jobs) < 8:
+        return [_batch_one(j) for j in jobs]
+    with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(_batch_one, jobs, chunksize=max(1, len(jobs) // (8 * workers))))
+
+
 def graphl_init(n: int, R: int, seed) -> np.ndarray:
     """Gamma_0 ~ U(-1, 1) in float32, laid out [n, R] (restart r is column r)."""
     rng = np.random.default_rng(seed)

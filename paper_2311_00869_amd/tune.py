@@ -82,3 +82,45 @@ def autotune(graph, trees: int = 16, seed: int = 12345, save: bool = True, verbo
         with open(CACHE, "w") as f:
             json.dump(cache, f, indent=1, sort_keys=True)
     return best[1], results
+
+
+def _batch_key(batch):
+    import hashlib
+    h = hashlib.sha256(batch.vertex_offsets.tobytes() + batch.nnz_offsets.tobytes()).hexdigest()
+    return f"batch:{h[:16]}"
+
+
+def default_batch_schedule(batch):
+    cache = _load()
+    if _batch_key(batch) in cache:
+        return dict(cache[_batch_key(batch)])
+    return dict(block=512, grid=0)
+
+
+def autotune_batch(batch, trees: int = 4, seed: int = 12345, save: bool = True, verbose=False):
+    """Time each block size of the batched sweep on `trees` trees per graph;
+    keep the fastest (results do not depend on the choice)."""
+    import torch
+
+    best, results = None, []
+    for b in (256, 512, 1024):
+        batch.set_schedule(block=b)
+        batch.sweep(1, seed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        batch.sweep(trees, seed)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        s = dict(block=b, grid=0)
+        results.append((el, s))
+        if verbose:
+            print(f"# tune batch {s}: {trees * batch.G / el:.1f} trees/s", flush=True)
+        if best is None or el < best[0]:
+            best = (el, s)
+    batch.set_schedule(**best[1])
+    if save:
+        cache = _load()
+        cache[_batch_key(batch)] = best[1]
+        with open(CACHE, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+    return best[1], results

@@ -65,3 +65,31 @@ def test_planted_powerlaw_all_paths():
     np.bitwise_or.at(w, idx // 64, np.left_shift(np.uint64(1), (idx % 64).astype(np.uint64)))
     assert int(G.count(torch.from_numpy(w.view(np.int64))).item()) == gold["planted_flipped"]
     G.close()
+
+
+def test_uneven_batch_full_size_sampled():
+    """The full uneven batch (4,096 graphs x 64 trees, the benchmark's batch
+    leg) in one fi_batch_sweep, checked on 256 sampled graphs against the
+    oracle's per-graph results (tests/golden/make_batch_golden.py), and on
+    every graph against what holds at any size."""
+    path = os.path.join(GOLDEN, "batch_uneven.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    with open(path) as f:
+        gold = json.load(f)
+    G, K = gold["graphs"], gold["trees_per_graph"]
+    graphs = synth.config_batch_parallel(G, 0)
+    B = fr.BatchGraph(graphs, cloud_capacity_per_graph=K)
+    ms = [g.nnz // 2 for g in graphs]
+    del graphs
+    for sched in [tune.default_batch_schedule(B), dict(block=256), dict(block=1024)]:
+        B.set_schedule(**sched)
+        mn, ds = B.sweep(K, gold["seed"])
+        mn, ds = mn.cpu().numpy(), ds.cpu().numpy()
+        for g, n, nnz, s, first, distinct in gold["rows"]:
+            assert int(B.nnz_offsets[g + 1] - B.nnz_offsets[g]) == nnz
+            assert (mn[g, 0], mn[g, 1], ds[g]) == (s, first, distinct), (sched, g)
+        assert np.all((ds >= 1) & (ds <= K))
+        assert np.all((mn[:, 1] >= 0) & (mn[:, 1] < K))
+        assert np.all(mn[:, 0] <= np.asarray(ms))
+    B.close()
