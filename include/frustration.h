@@ -234,7 +234,9 @@ int fi_batch_sweep(fi_graph* b, int64_t trees_per_graph, uint64_t seed, uint64_t
  * 1 = one workgroup per tree with the tree state in LDS (n <= 12,000),
  * 2 = one workgroup per tree with the tree state in workspace memory
  * (n <= 1,000,000), 3 = the whole grid on a few trees at a time
- * (persistent cooperative kernel, any n).  block: threads per workgroup
+ * (persistent cooperative kernel, any n), 4 = the whole grid on 64 trees
+ * at once with one bit per tree in every per-vertex word (cooperative, any
+ * n; fi_tree_state falls back to path 3).  block: threads per workgroup
  * (256, 512 or 1024); grid: workgroups (0 = default); heavy: degree above
  * which a top-down frontier vertex is expanded by several workgroups
  * (path 3, >= 32); batch: trees in flight on path 3 (1 .. 8). */

@@ -178,8 +178,16 @@ struct Layout {
   size_t gwstride;     // per-slot bitmap stride (words rounded up to 32)
   size_t slots;        // one-workgroup-per-tree scratch in workspace memory
   size_t nslots, slot_stride;
+  // multi-tree path: 32-byte per-vertex records, split-row partial minima,
+  // vertices listed by component, and root-finding tasks
+  size_t mrec, mhslot, mhcap, aslot, cverts, ccount, cptr, mtasks, mtcap, rootbig, nbigcap;
   size_t total;
 };
+
+// multi-tree path constants shared by create and the kernel
+constexpr int kMSplit = 2048;     // rows longer than this are split into units of this many edges
+constexpr int kBigComp = 1024;    // components larger than this find their roots in chunks
+constexpr int kRootChunk = 1024;  // vertices per root-finding task of a big component
 
 Layout make_layout(int32_t n, int64_t nnz, int64_t cloud_capacity, uint64_t table_size);
 uint64_t table_size_for(int64_t cloud_capacity);
@@ -196,6 +204,7 @@ void prof_end(fi_graph* g, hipStream_t s, void* token, int kernel);
 // launchers implemented in the .hip files
 hipError_t launch_sweep(fi_graph* g, const SweepArgs& a, hipStream_t s);
 hipError_t launch_grid(fi_graph* g, const SweepArgs& a, hipStream_t s);
+hipError_t launch_multi(fi_graph* g, const SweepArgs& a, hipStream_t s);
 hipError_t launch_count(const DevGraph& dg, const uint64_t* bits, int32_t B, uint64_t* counts,
                         hipStream_t s);
 
@@ -210,6 +219,7 @@ struct fi_graph {
   int64_t cloud_capacity;
   uint64_t table_size;
   int32_t ncomp, nisolated, nanch;
+  int32_t mtasks, mnbig;  // multi-tree path: root-finding tasks, big components
   fi_schedule sched;
   int cu_count;
   int max_shared;

@@ -179,4 +179,36 @@ __device__ __forceinline__ void cloud_insert(const DevGraph& G, uint64_t khi, ui
   atomicOr((unsigned long long*)(G.ctl + C_ERR), (unsigned long long)E_CAPACITY);
 }
 
+// Barrier among `nb` workgroups of a cooperative launch (local ranks
+// 0..nb-1): they arrive in groups of kBarGroup, the last of each group
+// arrives at the root, the last root arrival bumps the generation.  bar:
+// [0] generation, [16] root, [32 + 16 g] group g (each on its own line).
+constexpr int kBarGroup = 16;
+__device__ __forceinline__ void group_sync(uint64_t* bar, uint32_t rank, uint32_t nb) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t* gen = bar;
+    uint64_t* root = bar + 16;
+    const uint32_t g = rank / kBarGroup;
+    const uint32_t ngroups = (nb + kBarGroup - 1) / kBarGroup;
+    const uint32_t gsize = min((uint32_t)kBarGroup, nb - g * kBarGroup);
+    uint64_t* grp = bar + 32 + 16 * g;
+    const uint64_t g0 = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    const uint64_t a = __hip_atomic_fetch_add(grp, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (a == gsize - 1) {
+      __hip_atomic_store(grp, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint64_t b = __hip_atomic_fetch_add(root, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      if (b == ngroups - 1) {
+        __hip_atomic_store(root, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(gen, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0)
+      __builtin_amdgcn_s_sleep(1);
+    __threadfence();
+  }
+  __syncthreads();
+}
+
 }  // namespace fi

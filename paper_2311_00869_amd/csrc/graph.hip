@@ -232,6 +232,37 @@ __global__ void k_word_info(const int32_t* rp, const int32_t* comp, int32_t n, i
   }
 }
 
+// Component vertex lists for the multi-tree path: slot of each anchor,
+// vertices per slot, then every vertex with an edge placed in its slot's range.
+__global__ void k_aslot(const int32_t* anchors, int32_t nanch, int32_t* aslot) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nanch;
+       i += (int64_t)gridDim.x * blockDim.x)
+    aslot[anchors[i]] = (int32_t)i;
+}
+
+__global__ void k_ccount(const int32_t* rp, const int32_t* comp, const int32_t* aslot, int32_t n,
+                         int32_t* count) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x)
+    if (rp[v + 1] > rp[v]) atomicAdd(count + aslot[comp[v]], 1);
+}
+
+__global__ void k_cfill(const int32_t* rp, const int32_t* comp, const int32_t* aslot,
+                        const int32_t* cptr, int32_t n, int32_t* fill, int32_t* cverts) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x)
+    if (rp[v + 1] > rp[v]) {
+      const int32_t sl = aslot[comp[v]];
+      cverts[cptr[sl] + atomicAdd(fill + sl, 1)] = (int32_t)v;
+    }
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t len, int32_t val) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = val;
+}
+
 __global__ void k_fill_u64(uint64_t* p, int64_t len, uint64_t val) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -381,8 +412,79 @@ Layout make_layout(int32_t n, int64_t nnz, int64_t cloud_capacity, uint64_t tabl
     L.nslots = std::min<size_t>(2048, std::max<size_t>(1, budget / L.slot_stride));
   }
   L.slots = take(L.slot_stride * L.nslots);
+  // multi-tree path (the lists, bitmaps, control and barrier words are the
+  // whole-grid path's, which never runs at the same time)
+  L.mrec = take(32 * nn);
+  L.mhcap = (size_t)nnz / kMSplit + 1;
+  L.mhslot = take(8 * 64 * L.mhcap);
+  L.aslot = take(4 * nn);
+  L.cverts = take(4 * nn);
+  L.ccount = take(4 * (nn / 2 + 1));
+  L.cptr = take(4 * (nn / 2 + 2));
+  L.mtcap = nn / 2 + nn / kRootChunk + 2;
+  L.mtasks = take(16 * L.mtcap);
+  L.nbigcap = nn / kBigComp + 1;
+  L.rootbig = take(8 * 64 * L.nbigcap);
   L.total = off;
   return L;
+}
+
+// The multi-tree path's component lists and root-finding tasks: every
+// component with an edge gets one task if it has at most kBigComp vertices,
+// else one task per kRootChunk of its vertices and a row of big-component
+// minima.  Also resets the split-row and big-component minima.
+int build_components(fi_graph* g, hipStream_t s) {
+  const Layout& L = g->L;
+  char* ws = g->ws;
+  const DevGraph& G = g->dg;
+  const int32_t n = G.n;
+  const int B = 256;
+  uint64_t nanch64 = 0;
+  if (hipMemcpyAsync(&nanch64, G.ctl + C_NANCH, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return FI_EDEVICE;
+  const int32_t nanch = (int32_t)nanch64;
+  int32_t* aslot = (int32_t*)(ws + L.aslot);
+  int32_t* count = (int32_t*)(ws + L.ccount);
+  int32_t* cptr = (int32_t*)(ws + L.cptr);
+  std::vector<int32_t> cnt(nanch), ptr(nanch + 1, 0);
+  std::vector<int4> tasks;
+  int32_t nbig = 0;
+  if (nanch > 0) {
+    hipLaunchKernelGGL(k_aslot, dim3(grid_for(nanch, B)), dim3(B), 0, s, G.anchors, nanch, aslot);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nanch, B)), dim3(B), 0, s, count, (int64_t)nanch, 0);
+    hipLaunchKernelGGL(k_ccount, dim3(grid_for(n, B)), dim3(B), 0, s, G.row_ptr, G.comp, aslot, n,
+                       count);
+    if (hipMemcpyAsync(cnt.data(), count, 4 * (size_t)nanch, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return FI_EDEVICE;
+    for (int32_t i = 0; i < nanch; ++i) {
+      ptr[i + 1] = ptr[i] + cnt[i];
+      if (cnt[i] <= kBigComp) {
+        tasks.push_back(make_int4(ptr[i], ptr[i + 1], -1, 0));
+      } else {
+        for (int32_t b = ptr[i]; b < ptr[i + 1]; b += kRootChunk)
+          tasks.push_back(make_int4(b, std::min(ptr[i + 1], b + kRootChunk), nbig, 0));
+        ++nbig;
+      }
+    }
+    if (tasks.size() > L.mtcap || (size_t)nbig > L.nbigcap) return FI_EDEVICE;
+    if (hipMemcpyAsync(cptr, ptr.data(), 4 * ptr.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(ws + L.mtasks, tasks.data(), sizeof(int4) * tasks.size(), hipMemcpyHostToDevice,
+                       s) != hipSuccess)
+      return FI_EDEVICE;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nanch, B)), dim3(B), 0, s, count, (int64_t)nanch, 0);
+    hipLaunchKernelGGL(k_cfill, dim3(grid_for(n, B)), dim3(B), 0, s, G.row_ptr, G.comp, aslot, cptr,
+                       n, count, (int32_t*)(ws + L.cverts));
+  }
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(64 * (int64_t)L.mhcap, B)), dim3(B), 0, s,
+                     (uint64_t*)(ws + L.mhslot), 64 * (int64_t)L.mhcap, kUnvisited);
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(64 * (int64_t)L.nbigcap, B)), dim3(B), 0, s,
+                     (uint64_t*)(ws + L.rootbig), 64 * (int64_t)L.nbigcap, kUnvisited);
+  if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess) return FI_EDEVICE;
+  g->mtasks = (int32_t)tasks.size();
+  g->mnbig = nbig;
+  return FI_OK;
 }
 
 }  // namespace fi
@@ -530,6 +632,7 @@ int fi_graph_create(int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int3
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(nroot, B)), dim3(B), 0, s,
                        (uint64_t*)(ws + L.grootkey), nroot, kUnvisited);
   }
+  if (build_components(g, s) != FI_OK) return fail(FI_EDEVICE);
   hipLaunchKernelGGL(k_fill_u64, dim3(64), dim3(B), 0, s, (uint64_t*)(ws + L.gbar),
                      (int64_t)kGridSlots * kGridBarWords, 0ull);
   hipLaunchKernelGGL(k_fill_u64, dim3(4), dim3(B), 0, s, (uint64_t*)(ws + L.gctl),
@@ -685,7 +788,7 @@ int fi_count(fi_graph* g, const uint64_t* d_bits, int32_t B, uint64_t* d_counts,
 
 int fi_set_schedule(fi_graph* g, const fi_schedule* sc) {
   if (!g || !sc) return FI_EINVAL;
-  if (sc->path < 0 || sc->path > 3) return FI_EINVAL;
+  if (sc->path < 0 || sc->path > 4) return FI_EINVAL;
   if (sc->block != 256 && sc->block != 512 && sc->block != 1024) return FI_EINVAL;
   if (sc->grid < 0 || sc->heavy < 32 || sc->batch < 1 || sc->batch > kGridSlots) return FI_EINVAL;
   if (sc->grid > 16 * 4096) return FI_EINVAL;

@@ -10,6 +10,8 @@
 //   k_sweep_grid - sweep_grid.hip: the whole grid works on a few trees at a
 //                  time (persistent cooperative kernel), for graphs far
 //                  beyond one workgroup.
+//   k_sweep_multi - sweep_multi.hip: the whole grid sweeps 64 trees at once
+//                  with one bit per tree in every per-vertex word.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -85,12 +87,16 @@ int pick_path(fi_graph* g) {
 
 hipError_t launch_sweep(fi_graph* g, const SweepArgs& a, hipStream_t s) {
   if (a.t1 <= a.t0) return hipSuccess;
-  const int path = pick_path(g);
+  int path = pick_path(g);
+  // the multi-tree path keeps no per-tree state words to hand out
+  if (path == 4 && a.bits_out) path = 3;
   const int nt = g->sched.block;
   void* tok = nullptr;
   if (prof_begin(g, s, &tok)) return hipErrorUnknown;
   hipError_t e;
-  if (path == 3) {
+  if (path == 4) {
+    e = launch_multi(g, a, s);
+  } else if (path == 3) {
     e = launch_grid(g, a, s);
   } else {
     e = nt == 1024 ? launch_wg<1024>(g, a, path, s) : nt == 512 ? launch_wg<512>(g, a, path, s)

@@ -43,7 +43,7 @@ constexpr int kStage = 2048;        // LDS staging entries for next-level lists
 constexpr int kBUWordsPerWave = 4;  // bottom-up words per wave per unit
 constexpr int kWordCost = 16;       // bottom-up cost of one word, in edge visits
 constexpr int kTDCost = 4;          // top-down cost of one frontier edge
-constexpr int kGroup = 16;          // workgroups per barrier group
+constexpr int kGroup = kBarGroup;   // workgroups per barrier group
 
 // control words of slot s: gctl + s * kSlotWords
 //   [r * 8 + k], r = level % 4: k = 0 light count, 1 heavy (count << 32 |
@@ -112,34 +112,9 @@ __device__ __forceinline__ uint32_t bit_at(const uint64_t* words, uint32_t v) {
   return (uint32_t)(words[v >> 6] >> (v & 63)) & 1u;
 }
 
-// Barrier among the `nb` workgroups of one sub-grid (local ranks 0..nb-1):
-// they arrive in groups of kGroup, the last of each group arrives at the
-// root, the last root arrival bumps the generation.
+// Barrier among the `nb` workgroups of one sub-grid (local ranks 0..nb-1).
 __device__ __forceinline__ void sub_sync(uint64_t* bar, uint32_t rank, uint32_t nb) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint64_t* gen = bar;
-    uint64_t* root = bar + 16;
-    const uint32_t g = rank / kGroup;
-    const uint32_t ngroups = (nb + kGroup - 1) / kGroup;
-    const uint32_t gsize = min((uint32_t)kGroup, nb - g * kGroup);
-    uint64_t* grp = bar + 32 + 16 * g;
-    const uint64_t g0 = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    const uint64_t a = __hip_atomic_fetch_add(grp, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (a == gsize - 1) {
-      __hip_atomic_store(grp, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const uint64_t b = __hip_atomic_fetch_add(root, 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-      if (b == ngroups - 1) {
-        __hip_atomic_store(root, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(gen, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      }
-    }
-    while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g0)
-      __builtin_amdgcn_s_sleep(1);
-    __threadfence();
-  }
-  __syncthreads();
+  group_sync(bar, rank, nb);
 }
 
 // Move the LDS staging list into a global list (one reservation per block).
