@@ -37,7 +37,7 @@ def algorithmic_bytes_per_tree(n: int, nnz: int) -> int:
 
 def kernel_source_sha() -> str:
     h = hashlib.sha256()
-    for f in ("sweep.hip", "sweep_grid.hip", "fi_prims.h", "fi_internal.h"):
+    for f in ("sweep.hip", "sweep_grid.hip", "sweep_multi.hip", "fi_prims.h", "fi_internal.h"):
         with open(os.path.join(ROOT, "paper_2311_00869_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -149,7 +149,7 @@ def main():
     achieved = bpt * T / avg_launch_s / 1e9
     traffic = load_traffic(args.workload)
     roofline = {
-        "kernel": "k_sweep_grid" if G.get_schedule()["path"] == 3 else "k_sweep_wg",
+        "kernel": {3: "k_sweep_grid", 4: "k_sweep_multi"}.get(G.get_schedule()["path"], "k_sweep_wg"),
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": None if traffic is None else traffic["bytes_per_launch"],
@@ -159,7 +159,9 @@ def main():
 
     extra = {}
     if not args.no_plain:
-        # the plain per-tree path: one launch per tree, no persistence across trees
+        # the plain per-tree path: one launch per tree, one tree in flight
+        # (whole-grid path, no batching of trees)
+        G.set_schedule(path=3, block=1024, batch=1)
         G.cloud_reset()
         Tp = min(T, 100)
         torch.cuda.synchronize()

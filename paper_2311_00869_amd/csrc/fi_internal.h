@@ -180,7 +180,7 @@ struct Layout {
   size_t nslots, slot_stride;
   // multi-tree path: 32-byte per-vertex records, split-row partial minima,
   // vertices listed by component, and root-finding tasks
-  size_t mrec, mhslot, mhcap, aslot, cverts, ccount, cptr, mtasks, mtcap, rootbig, nbigcap;
+  size_t mrec, mhslot, mhcap, mreach, aslot, cverts, ccount, cptr, mtasks, mtcap, rootbig, nbigcap;
   size_t total;
 };
 

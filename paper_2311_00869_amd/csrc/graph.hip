@@ -417,6 +417,8 @@ Layout make_layout(int32_t n, int64_t nnz, int64_t cloud_capacity, uint64_t tabl
   L.mrec = take(32 * nn);
   L.mhcap = (size_t)nnz / kMSplit + 1;
   L.mhslot = take(8 * 64 * L.mhcap);
+  // reached bitmaps over the two levels' list entries: light, then split rows
+  L.mreach = take(8 * (4 * ((nn + 64) / 64 + 2) + 2 * (L.mhcap / 64 + 2)));
   L.aslot = take(4 * nn);
   L.cverts = take(4 * nn);
   L.ccount = take(4 * (nn / 2 + 1));

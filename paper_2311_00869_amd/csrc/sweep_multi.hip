@@ -9,12 +9,16 @@
 //   push - while the frontier is small, its rows mark as candidates every
 //          neighbour still unvisited in a tree where the frontier vertex was
 //          just discovered;
-//   pull - a wave takes a candidate (or, on large frontiers, every vertex not
-//          yet visited by all trees) and walks its row; lane t keeps the
-//          minimum key over the neighbours discovered at the previous level
-//          of tree t, which is exactly the single-tree parent rule, and the
-//          state bit that comes with it.  Rows longer than kMSplit are cut
-//          into parts whose minima meet through atomic minima.
+//   pull - a wave takes 64 entries of the candidate list (or, on large
+//          frontiers, of the list of every vertex not yet visited by all
+//          trees) and walks their rows, several short rows per 64-edge round;
+//          for each vertex lane t keeps the minimum key over the neighbours
+//          discovered at the previous level of tree t, which is exactly the
+//          single-tree parent rule, and the state bit that comes with it.
+//          Rows longer than kMSplit are cut into parts whose minima meet
+//          through atomic minima.
+// The frontier of a level is its pull list together with a bitmap of the
+// entries some tree reached.
 // A neighbour's discovery word may still carry bits from two levels back;
 // such a tree has already visited every neighbour of that vertex, so the
 // bit never survives the mask of unvisited trees and the words need no
@@ -38,7 +42,9 @@ namespace {
 
 constexpr int kStageM = 2048;      // LDS staging entries for light list appends
 constexpr int kPushCost = 2;       // push while kPushCost * frontier edges < unfinished edges
-constexpr int kPullPerWave = 4;    // light pull vertices per wave per unit
+constexpr int kSmall = 64;         // rows up to this many edges are pulled 64 vertices per wave
+constexpr int kMedPerWave = 4;     // medium rows per wave per unit
+constexpr int kMedChunk = 64;      // medium frontier rows per push unit
 constexpr int kPlanes = 8;         // bit-sliced counter planes (flushed every 255 edges)
 
 // Per-vertex record: discovered at the last even / odd level, state bits,
@@ -50,16 +56,17 @@ struct __align__(32) MRec {
 };
 
 // Control words; each group sits on its own 128-byte line.  r = level mod 4.
-//   F(r): frontier lists of the level: light count, heavy (count << 32 |
-//         units), vertices reached, their degree sum
-//   P(r): pull lists of the level: light count, heavy (count << 32 | units)
-//   TP(r), TQ(r): work tickets of the list / push phase and the pull phase
+//   F(r): the level's pull lists and frontier: small-row count, heavy
+//         (count << 32 | units), vertices reached, their degree sum,
+//         medium-row count
+//   TP(r), TQ(r), TM(r): work tickets of the push phase, of the split-row
+//         parts and of the medium rows
 //   UNF: degree sum of vertices not yet visited by every tree
 //   ACC + 4 t: tree t's switches, key_hi, key_lo
 __host__ __device__ constexpr int cF(int r) { return 16 * r; }
-__host__ __device__ constexpr int cP(int r) { return 64 + 16 * r; }
 __host__ __device__ constexpr int cTP(int r) { return 128 + 16 * r; }
 __host__ __device__ constexpr int cTQ(int r) { return 192 + 16 * r; }
+__host__ __device__ constexpr int cTM(int r) { return 384 + 16 * r; }
 constexpr int cUNF = 256;
 constexpr int cACC = 512;
 constexpr int kMCtlWords = 768;
@@ -73,11 +80,13 @@ struct MArgs {
   MRec* rec;
   uint64_t* unf;        // [nwords] vertices with an edge not yet visited by every tree
   uint64_t* cand;       // [nwords] push candidates of the level
-  int32_t* fl;          // [2][lstride] frontier light lists (by level parity)
-  int2* fh;             // [2][hstride] frontier heavy lists (vertex, first unit)
-  int32_t* pl;          // [lstride] pull light list
-  int2* ph;             // [hstride] pull heavy list; entry h owns hslot row h
-  int64_t lstride, hstride;
+  int32_t* pl;          // [2][lstride] pull lists of rows up to kSmall (by level parity)
+  int32_t* pm;          // [2][lstride] pull lists of rows up to kMSplit
+  int2* ph;             // [2][hstride] split rows (vertex, first unit); entry h owns hslot row h
+  uint64_t* rl;         // [2][rlstride] entries of pl some tree reached
+  uint64_t* rm;         // [2][rlstride] entries of pm some tree reached
+  uint64_t* rh;         // [2][rhstride] entries of ph some tree reached
+  int64_t lstride, hstride, rlstride, rhstride;
   uint64_t* hslot;      // [rows][64] partial minima of split rows
   const int4* tasks;    // root tasks: (begin, end) in cverts, big slot or -1
   const int32_t* cverts;
@@ -92,16 +101,18 @@ struct MS {
   int start[NT];
   uint64_t base[NT];
   int scan[NT / 64 + 1];
-  int32_t q[kStageM];
-  uint32_t qn;
+  int32_t q[kStageM];   // staging: small rows
+  int32_t q2[kStageM];  // staging: medium rows
+  uint32_t qn, qn2;
   uint32_t unit;
   int hidx;
   int2 heavy;
   uint64_t cnt, deg, fin;
   int mode, active;
-  uint32_t nl, nh, hunits;
+  uint32_t nl, nm, nh, hunits;
   uint64_t hbest[64];
   uint64_t tacc[3][64];
+  int wflag[NT];        // per wave: starts of the rows of a pull round
 };
 
 __device__ __forceinline__ uint64_t amin64(uint64_t* p, uint64_t v) {
@@ -124,35 +135,46 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t x, int j) {
 
 // Move the LDS staging list into a global list (one reservation per block).
 template <int NT>
-__device__ __forceinline__ void mflush(MS<NT>& sh, int32_t* list, uint64_t* ring) {
+__device__ __forceinline__ void mflush1(MS<NT>& sh, int32_t* q, uint32_t* qn, int32_t* list,
+                                        uint64_t* counter) {
   __syncthreads();
-  const uint32_t k = sh.qn;
+  const uint32_t k = *qn;
   if (k) {
-    if (threadIdx.x == 0) sh.unit = atomicAdd((uint32_t*)ring, k);
+    if (threadIdx.x == 0) sh.unit = atomicAdd((uint32_t*)counter, k);
     __syncthreads();
     const uint32_t base = sh.unit;
-    for (uint32_t i = threadIdx.x; i < k; i += NT) list[base + i] = sh.q[i];
+    for (uint32_t i = threadIdx.x; i < k; i += NT) list[base + i] = q[i];
     __syncthreads();
-    if (threadIdx.x == 0) sh.qn = 0;
+    if (threadIdx.x == 0) *qn = 0;
   }
   __syncthreads();
 }
+// both staging lists into the level's small and medium lists
+template <int NT>
+__device__ __forceinline__ void mflush(MS<NT>& sh, int32_t* ls, int32_t* lm, uint64_t* ring) {
+  mflush1<NT>(sh, sh.q, &sh.qn, ls, ring);
+  mflush1<NT>(sh, sh.q2, &sh.qn2, lm, ring + 4);
+}
 
-// Lanes with `in` list vertex v of degree dv: light ones into the LDS
-// staging list, split rows straight into the heavy list with their units.
+// Lanes with `in` list vertex v of degree dv: small and medium rows into
+// their LDS staging lists, split rows straight into the heavy list with
+// their units.
+__device__ __forceinline__ void stage(bool pred, int32_t v, int32_t* q, uint32_t* qn) {
+  const uint64_t mask = __ballot(pred);
+  if (mask) {
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    uint32_t base = 0;
+    if (lane_id() == leader) base = atomicAdd(qn, (uint32_t)__popcll(mask));
+    base = __shfl(base, leader);
+    if (pred) q[base + lanes_below(mask)] = v;
+  }
+}
 template <int NT>
 __device__ __forceinline__ void mlist(bool in, int32_t v, int dv, MS<NT>& sh, int2* qh,
                                       uint64_t* ring) {
   const bool heavy = in && dv > kMSplit;
-  const bool light = in && !heavy;
-  const uint64_t mask = __ballot(light);
-  if (mask) {
-    const int leader = __ffsll((unsigned long long)mask) - 1;
-    uint32_t base = 0;
-    if (lane_id() == leader) base = atomicAdd(&sh.qn, (uint32_t)__popcll(mask));
-    base = __shfl(base, leader);
-    if (light) sh.q[base + lanes_below(mask)] = v;
-  }
+  stage(in && dv <= kSmall, v, sh.q, &sh.qn);
+  stage(in && dv > kSmall && !heavy, v, sh.q2, &sh.qn2);
   if (heavy) {
     const uint64_t units = (uint64_t)((dv + kMSplit - 1) / kMSplit);
     const uint64_t old = atomicAdd((unsigned long long*)(ring + 1),
@@ -162,10 +184,11 @@ __device__ __forceinline__ void mlist(bool in, int32_t v, int dv, MS<NT>& sh, in
 }
 
 // The same straight into the global lists (no staging).
-__device__ __forceinline__ void mlist_global(bool in, int32_t v, int dv, int32_t* ql, int2* qh,
-                                             uint64_t* ring) {
+__device__ __forceinline__ void mlist_global(bool in, int32_t v, int dv, int32_t* ql, int32_t* qm,
+                                             int2* qh, uint64_t* ring) {
   const bool heavy = in && dv > kMSplit;
-  wave_append(in && !heavy, v, ql, (uint32_t*)ring);
+  wave_append(in && dv <= kSmall, v, ql, (uint32_t*)ring);
+  wave_append(in && dv > kSmall && !heavy, v, qm, (uint32_t*)(ring + 4));
   if (heavy) {
     const uint64_t units = (uint64_t)((dv + kMSplit - 1) / kMSplit);
     const uint64_t old = atomicAdd((unsigned long long*)(ring + 1),
@@ -260,30 +283,129 @@ __device__ __forceinline__ void set_roots(uint64_t best, bool vlane, uint64_t va
       fin += (uint64_t)dv;
     }
   }
-  mlist_global(leader, (int32_t)r, dv, A.fl, A.fh, A.ctl + cF(0));
+  mlist_global(leader, (int32_t)r, dv, A.pl, A.pm, A.ph, A.ctl + cF(0));
   cnt += (uint64_t)__popcll(__ballot(leader));
   deg += wave_sum_u64(leader ? (uint64_t)dv : 0ull);
 }
 
-// Write back a vertex whose trees of this level are decided (one lane; newb
-// / stb are the trees that reached it and their state bits) and clear its
-// candidate bit; fin gathers the degree of a vertex every tree has now
-// visited.
-__device__ __forceinline__ void finish_vertex(const MArgs& A, int32_t v, uint64_t vis, uint64_t st,
-                                              uint64_t newb, uint64_t stb, int p, uint64_t valid,
-                                              bool push_mode, int dv, uint64_t& fin) {
-  MRec* r = A.rec + v;
-  const uint64_t bit = 1ull << (v & 63);
-  if (newb) {
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// Lane t: the write-back of vertex v once its trees of this level are
+// decided (best: lane t's minimum candidate, kUnvisited if none).  One lane
+// stores; every lane gets the reached / finished bookkeeping.
+__device__ __forceinline__ bool settle(const MArgs& A, int32_t v, uint64_t vis, uint64_t st, int dv,
+                                       uint64_t best, int p, uint64_t valid, uint64_t& cnt,
+                                       uint64_t& deg, uint64_t& fin) {
+  const uint64_t newb = __ballot(best != kUnvisited);
+  if (!newb) return false;
+  const uint64_t stb = __ballot(best != kUnvisited && (best & 1));
+  const bool full = (vis | newb) == valid;
+  if (lane_id() == 0) {
+    MRec* r = A.rec + v;
     r->vis = vis | newb;
     r->nb[p] = newb;
     if (stb) r->st = st | stb;
-    if ((vis | newb) == valid) {
-      aand64(A.unf + (v >> 6), ~bit);
-      fin += (uint64_t)dv;
-    }
+    if (full) aand64(A.unf + (v >> 6), ~(1ull << (v & 63)));
   }
-  if (push_mode) aand64(A.cand + (v >> 6), ~bit);
+  if (full) fin += (uint64_t)dv;
+  cnt += 1;
+  deg += (uint64_t)dv;
+  return true;
+}
+
+// One wave pulls the small-row list entries i0 .. i0 + ne - 1 (ne <= 64;
+// lane k holds entry i0 + k; every row has at most kSmall edges).  Rows are
+// walked in rounds of at most 64 edges, as many whole rows as fit, all
+// loads of a round in flight together; a vertex is settled when the walk
+// leaves its row.  Returns the entries some tree reached (bit k).
+__device__ __forceinline__ uint64_t pull_small(const DevGraph& G, const MArgs& A, const int32_t* list,
+                                               int64_t i0, int ne, int pp, int p, uint64_t valid,
+                                               KeyMix km, bool push, int* wflag, uint64_t& cnt,
+                                               uint64_t& deg, uint64_t& fin) {
+  const int lane = lane_id();
+  const bool ok = lane < ne;
+  int32_t v = 0;
+  int s = 0, d = 0;
+  uint64_t vis = 0, st = 0;
+  if (ok) {
+    v = list[i0 + lane];
+    s = G.row_ptr[v];
+    d = G.row_ptr[v + 1] - s;
+    vis = A.rec[v].vis;
+    st = A.rec[v].st;
+    if (push) aand64(A.cand + (v >> 6), ~(1ull << (v & 63)));
+  }
+  const uint64_t want = valid & ~vis;
+  int inc = d;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  const int excl = inc - d;
+  uint64_t reached = 0;
+  int k0 = 0;
+  while (k0 < ne) {
+    const int eb = uni(__shfl(excl, k0));
+    const uint64_t fit = __ballot(ok && lane >= k0 && inc - eb <= 64);
+    const int k1 = k0 + (int)__popcll(fit);  // >= k0 + 1: every row fits a round
+    const int total = uni(__shfl(inc, k1 - 1)) - eb;
+    // owner of each edge lane: the rows' starts as a bit mask
+    wflag[lane] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (lane >= k0 && lane < k1) wflag[excl - eb] = 1;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const uint64_t starts = __ballot(wflag[lane] != 0);
+    __builtin_amdgcn_wave_barrier();
+    const int r = (int)__popcll(starts & ((2ull << lane) - 1));
+    const int kj = k0 + (r > 0 ? r - 1 : 0);
+    const int sk = __shfl(s, kj);
+    const int ek = __shfl(excl, kj);
+    const uint32_t wlo = (uint32_t)__shfl((int)(uint32_t)want, kj);
+    const uint32_t whi = (uint32_t)__shfl((int)(uint32_t)(want >> 32), kj);
+    const uint64_t wk = ((uint64_t)whi << 32) | wlo;
+    uint32_t a = 0;
+    uint64_t F = 0, S = 0;
+    if (lane < total) {
+      a = G.adj[(int64_t)sk + (eb + lane - ek)];
+      const MRec* ru = A.rec + (a & kVertexMask);
+      F = ru->nb[pp] & wk;
+      if (F) S = ru->st;
+    }
+    uint64_t hits = __ballot(F != 0);
+    uint64_t best = kUnvisited;
+    int cur = -1;
+    while (hits) {
+      const int jj = __builtin_ctzll(hits);
+      hits &= hits - 1;
+      const int kk = __builtin_amdgcn_readlane(kj, jj);
+      if (kk != cur) {
+        if (cur >= 0 &&
+            settle(A, __builtin_amdgcn_readlane(v, cur), readlane64(vis, cur), readlane64(st, cur),
+                   __builtin_amdgcn_readlane(d, cur), best, p, valid, cnt, deg, fin))
+          reached |= 1ull << cur;
+        best = kUnvisited;
+        cur = kk;
+      }
+      const uint32_t aj = __builtin_amdgcn_readlane(a, jj);
+      const uint64_t Fj = readlane64(F, jj);
+      const uint64_t Sj = readlane64(S, jj);
+      if ((Fj >> lane) & 1) {
+        const uint32_t uj = aj & kVertexMask;
+        const uint64_t bit = ((Sj >> lane) & 1) ^ (uint64_t)(aj >> 31);
+        const uint64_t c2 = ((uint64_t)vhash20(km, uj) << 33) | ((uint64_t)uj << 1) | bit;
+        best = c2 < best ? c2 : best;
+      }
+    }
+    if (cur >= 0 &&
+        settle(A, __builtin_amdgcn_readlane(v, cur), readlane64(vis, cur), readlane64(st, cur),
+               __builtin_amdgcn_readlane(d, cur), best, p, valid, cnt, deg, fin))
+      reached |= 1ull << cur;
+    k0 = k1;
+  }
+  return reached;
 }
 
 template <int NT>
@@ -297,6 +419,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
   const int32_t n = G.n, nw = G.nwords;
   const int32_t* rp = G.row_ptr;
   uint64_t* ctl = A.ctl;
+  int* wflag = sh.wflag + wave * 64;
 
   for (uint64_t tb = A.t0; tb < A.t1; tb += 64) {
     const int nvalid = (int)min<uint64_t>(64, A.t1 - tb);
@@ -319,10 +442,14 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
     }
     if (rank == 0)
       for (int i = tid; i < kMCtlWords; i += NT) ctl[i] = i == cUNF ? (uint64_t)G.nnz : 0ull;
-    if (tid == 0) sh.qn = 0;
+    if (tid == 0) {
+      sh.qn = 0;
+      sh.qn2 = 0;
+    }
     group_sync(A.bar, rank, nb);
 
-    // ---- roots: the minimum key of every component, per tree
+    // ---- roots: the minimum key of every component, per tree; they form
+    // the lists of level 0, all reached
     {
       uint64_t cnt = 0, deg = 0, fin = 0;
       for (int64_t k = gwave; k < A.ntasks; k += nwaves) {
@@ -356,13 +483,24 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
       const int pp = (int)((L - 1) & 1), p = (int)(L & 1);
       uint64_t* rfp = ctl + cF((L - 1) & 3);
       uint64_t* rf = ctl + cF(L & 3);
-      uint64_t* rpl = ctl + cP(L & 3);
-      const int32_t* flp = A.fl + (size_t)pp * A.lstride;
-      const int2* fhp = A.fh + (size_t)pp * A.hstride;
-      int32_t* fln = A.fl + (size_t)p * A.lstride;
-      int2* fhn = A.fh + (size_t)p * A.hstride;
+      // lists and frontier of level L-1
+      const int32_t* plp = A.pl + (size_t)pp * A.lstride;
+      const int32_t* pmp = A.pm + (size_t)pp * A.lstride;
+      const int2* php = A.ph + (size_t)pp * A.hstride;
+      const uint64_t* rlp = A.rl + (size_t)pp * A.rlstride;
+      const uint64_t* rmp = A.rm + (size_t)pp * A.rlstride;
+      const uint64_t* rhp = A.rh + (size_t)pp * A.rhstride;
+      // lists of level L
+      int32_t* pln = A.pl + (size_t)p * A.lstride;
+      int32_t* pmn = A.pm + (size_t)p * A.lstride;
+      int2* phn = A.ph + (size_t)p * A.hstride;
+      uint64_t* rln = A.rl + (size_t)p * A.rlstride;
+      uint64_t* rmn = A.rm + (size_t)p * A.rlstride;
+      uint64_t* rhn = A.rh + (size_t)p * A.rhstride;
+      const bool all_reached = L == 1;  // level 0 lists only roots
       if (tid == 0) {
         sh.nl = (uint32_t)load_agent(rfp);
+        sh.nm = (uint32_t)load_agent(rfp + 4);
         const uint64_t hp = load_agent(rfp + 1);
         sh.nh = (uint32_t)(hp >> 32);
         sh.hunits = (uint32_t)hp;
@@ -372,44 +510,57 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
         sh.mode = (uint64_t)kPushCost * fdeg < unf ? 1 : 2;
       }
       __syncthreads();
-      if (!sh.active) break;
+      if (!uni(sh.active)) break;
       if (L > (uint32_t)kMaxLevel) {
         if (stid == 0) atomicOr((unsigned long long*)(G.ctl + C_ERR), (unsigned long long)E_DEPTH);
         break;
       }
-      const bool push = sh.mode == 1;
+      const bool push = uni(sh.mode) == 1;
       // counters and tickets of level L + 1 start from zero
-      if (rank == 0 && tid < 4) {
+      if (rank == 0 && tid < 8) {
         const int r = (int)((L + 1) & 3);
         ctl[cF(r) + tid] = 0;
-        if (tid < 2) ctl[cP(r) + tid] = 0;
         if (tid == 0) {
           ctl[cTP(r)] = 0;
           ctl[cTQ(r)] = 0;
+          ctl[cTM(r)] = 0;
         }
       }
+      // medium rows set their reached bits with atomics
+      for (int64_t i = stid; i < A.rlstride; i += sstride) rmn[i] = 0;
 
-      // ---- phase 1: the pull lists
+      // ---- phase 1: the pull lists of level L
       if (push) {
-        const uint32_t nchunks = (sh.nl + NT - 1) / NT;
-        const uint32_t U = nchunks + sh.hunits;
+        // the rows of the frontier mark their unvisited neighbours
+        // units: chunks of NT small rows, chunks of kMedChunk medium rows,
+        // then the parts of split rows
+        const uint32_t nlp = uni(sh.nl), nmp = uni(sh.nm);
+        const uint32_t nsc = (nlp + NT - 1) / NT;
+        const uint32_t nchunks = nsc + (nmp + kMedChunk - 1) / kMedChunk;
+        const uint32_t U = nchunks + uni(sh.hunits);
         uint64_t* ticket = ctl + cTP(L & 3);
         bool firstu = true;
         while (true) {
           if (tid == 0) sh.unit = firstu ? rank : (U > nb ? nb + atomicAdd((uint32_t*)ticket, 1u) : U);
           firstu = false;
           __syncthreads();
-          const uint32_t k = sh.unit;
+          const uint32_t k = uni(sh.unit);
           if (k >= U) break;
           int total = 0;
           int64_t e0 = 0;
           uint64_t hbits = 0;
           if (k < nchunks) {
-            const uint32_t i = k * NT + tid;
             int d = 0, st = 0;
             uint64_t bits = 0;
-            if (i < sh.nl) {
-              const int32_t u = flp[i];
+            int32_t u = -1;
+            if (k < nsc) {
+              const uint32_t i = k * NT + tid;
+              if (i < nlp && (all_reached || ((rlp[i >> 6] >> (i & 63)) & 1))) u = plp[i];
+            } else if (tid < kMedChunk) {
+              const uint32_t i = (k - nsc) * kMedChunk + tid;
+              if (i < nmp && (all_reached || ((rmp[i >> 6] >> (i & 63)) & 1))) u = pmp[i];
+            }
+            if (u >= 0) {
               st = rp[u];
               d = rp[u + 1] - st;
               bits = A.rec[u].nb[pp] & valid;
@@ -419,23 +570,28 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
             sh.start[tid] = st;
             sh.base[tid] = bits;
             __syncthreads();
+            total = uni(total);
           } else {
             const uint32_t hk = k - nchunks;
             if (tid == 0) {
               int lo = 0, hi = (int)sh.nh;
               while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
-                if ((uint32_t)fhp[mid].y <= hk) lo = mid; else hi = mid;
+                if ((uint32_t)php[mid].y <= hk) lo = mid; else hi = mid;
               }
-              sh.heavy = fhp[lo];
+              sh.hidx = lo;
+              sh.heavy = php[lo];
             }
             __syncthreads();
-            const int32_t u = sh.heavy.x;
-            const uint32_t part = hk - (uint32_t)sh.heavy.y;
-            e0 = rp[u] + (int64_t)part * kMSplit;
-            const int64_t e1 = min<int64_t>(rp[u + 1], e0 + kMSplit);
-            hbits = A.rec[u].nb[pp] & valid;
-            total = (int)(e1 - e0);
+            const int hidx = uni(sh.hidx);
+            if (all_reached || ((rhp[hidx >> 6] >> (hidx & 63)) & 1)) {
+              const int32_t u = uni(sh.heavy.x);
+              const uint32_t part = hk - (uint32_t)uni(sh.heavy.y);
+              e0 = rp[u] + (int64_t)part * kMSplit;
+              const int64_t e1 = min<int64_t>(rp[u + 1], e0 + kMSplit);
+              hbits = A.rec[u].nb[pp] & valid;
+              total = (int)(e1 - e0);
+            }
           }
           for (int j0 = 0; j0 < total; j0 += NT) {
             const int j = j0 + tid;
@@ -462,9 +618,9 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
                 }
               }
             }
-            mlist<NT>(first, v, dv, sh, A.ph, rpl);
+            mlist<NT>(first, v, dv, sh, phn, rf);
             __syncthreads();
-            if (sh.qn > kStageM - NT) mflush<NT>(sh, A.pl, rpl);
+            if (sh.qn > kStageM - NT || sh.qn2 > kStageM - NT) mflush<NT>(sh, pln, pmn, rf);
           }
           __syncthreads();
         }
@@ -476,18 +632,19 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
           const bool in = (bits >> lane) & 1;
           const int32_t v = (int32_t)(w * 64 + lane);
           const int dv = in ? rp[v + 1] - rp[v] : 0;
-          mlist<NT>(in, v, dv, sh, A.ph, rpl);
+          mlist<NT>(in, v, dv, sh, phn, rf);
           __syncthreads();
-          if (sh.qn > kStageM - NT) mflush<NT>(sh, A.pl, rpl);
+          if (sh.qn > kStageM - NT || sh.qn2 > kStageM - NT) mflush<NT>(sh, pln, pmn, rf);
         }
       }
-      mflush<NT>(sh, A.pl, rpl);
+      mflush<NT>(sh, pln, pmn, rf);
       group_sync(A.bar, rank, nb);
 
       // ---- phase 2: pull
       if (tid == 0) {
-        sh.nl = (uint32_t)load_agent(rpl);
-        const uint64_t hp = load_agent(rpl + 1);
+        sh.nl = (uint32_t)load_agent(rf);
+        sh.nm = (uint32_t)load_agent(rf + 4);
+        const uint64_t hp = load_agent(rf + 1);
         sh.nh = (uint32_t)(hp >> 32);
         sh.hunits = (uint32_t)hp;
         sh.cnt = 0;
@@ -496,74 +653,87 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
       }
       __syncthreads();
       {
-        constexpr uint32_t VPU = kPullPerWave * NW;
-        const uint32_t nchunks = (sh.nl + VPU - 1) / VPU;
-        const uint32_t U = nchunks + sh.hunits;
-        uint64_t* ticket = ctl + cTQ(L & 3);
-        bool firstu = true;
-        while (true) {
-          if (tid == 0) sh.unit = firstu ? rank : (U > nb ? nb + atomicAdd((uint32_t*)ticket, 1u) : U);
-          firstu = false;
-          __syncthreads();
-          const uint32_t k = sh.unit;
-          if (k >= U) break;
-          if (k < nchunks) {
-            uint64_t fin = 0;
-            for (int it = 0; it < kPullPerWave; ++it) {
+        uint64_t cnt = 0, deg = 0, fin = 0;
+        // small rows: 64 list entries per wave, whole bitmap words
+        const int64_t nl = (int64_t)uni(sh.nl);
+        for (int64_t b = gwave; b * 64 < nl; b += nwaves) {
+          const int ne = (int)min<int64_t>(64, nl - b * 64);
+          const uint64_t r = pull_small(G, A, pln, b * 64, ne, pp, p, valid, km, push, wflag, cnt,
+                                        deg, fin);
+          if (lane == 0) rln[b] = r;
+        }
+        // medium rows: one per wave, units of kMedPerWave rows per wave
+        {
+          constexpr uint32_t VPU = kMedPerWave * NW;
+          const uint32_t nm = uni(sh.nm);
+          const uint32_t U = (nm + VPU - 1) / VPU;
+          uint64_t* ticket = ctl + cTM(L & 3);
+          bool firstu = true;
+          while (true) {
+            __syncthreads();
+            if (tid == 0) sh.unit = firstu ? rank : (U > nb ? nb + atomicAdd((uint32_t*)ticket, 1u) : U);
+            firstu = false;
+            __syncthreads();
+            const uint32_t k = uni(sh.unit);
+            if (k >= U) break;
+            for (int it = 0; it < kMedPerWave; ++it) {
               const uint32_t i = k * VPU + (uint32_t)(it * NW + wave);
-              if (i >= sh.nl) break;
-              const int32_t v = A.pl[i];
+              if (i >= nm) break;
+              const int32_t v = pmn[i];
               const uint64_t vis = A.rec[v].vis, st = A.rec[v].st;
               const uint64_t want = valid & ~vis;
               const int dv = rp[v + 1] - rp[v];
               uint64_t best = kUnvisited;
               if (want) best = pull_edges(G.adj, A.rec, rp[v], rp[v + 1], pp, want, km, best);
-              const bool found = best != kUnvisited;
-              const uint64_t newb = __ballot(found);
-              const uint64_t stb = __ballot(found && (best & 1));
-              if (lane == 0) {
-                finish_vertex(A, v, vis, st, newb, stb, p, valid, push, dv, fin);
-                if (newb) {
-                  sh.q[atomicAdd(&sh.qn, 1u)] = v;
-                  atomicAdd((unsigned long long*)&sh.cnt, 1ull);
-                  atomicAdd((unsigned long long*)&sh.deg, (unsigned long long)dv);
-                }
-              }
+              if (settle(A, v, vis, st, dv, best, p, valid, cnt, deg, fin) && lane == 0)
+                aor64(rmn + (i >> 6), 1ull << (i & 63));
+              if (push && lane == 0) aand64(A.cand + (v >> 6), ~(1ull << (v & 63)));
             }
-            if (lane == 0 && fin) atomicAdd((unsigned long long*)&sh.fin, (unsigned long long)fin);
-          } else {
-            // one part of a split row: the block's waves share its edges
-            const uint32_t hk = k - nchunks;
-            if (tid == 0) {
-              int lo = 0, hi = (int)sh.nh;
-              while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if ((uint32_t)A.ph[mid].y <= hk) lo = mid; else hi = mid;
-              }
-              sh.hidx = lo;
-              sh.heavy = A.ph[lo];
-            }
-            if (tid < 64) sh.hbest[tid] = kUnvisited;
-            __syncthreads();
-            const int32_t v = sh.heavy.x;
-            const uint32_t part = hk - (uint32_t)sh.heavy.y;
-            const int64_t e0 = rp[v] + (int64_t)part * kMSplit;
-            const int64_t e1 = min<int64_t>(rp[v + 1], e0 + kMSplit);
-            const uint64_t want = valid & ~A.rec[v].vis;
-            const int64_t seg = ((e1 - e0 + NW - 1) / NW + 63) / 64 * 64;
-            const int64_t s0 = min<int64_t>(e1, e0 + (int64_t)wave * seg);
-            const int64_t s1 = min<int64_t>(e1, s0 + seg);
-            uint64_t best = kUnvisited;
-            if (want && s0 < s1) best = pull_edges(G.adj, A.rec, s0, s1, pp, want, km, best);
-            if (best != kUnvisited) atomicMin((unsigned long long*)&sh.hbest[lane], (unsigned long long)best);
-            __syncthreads();
-            if (tid < 64 && sh.hbest[tid] != kUnvisited)
-              amin64(A.hslot + (size_t)sh.hidx * 64 + tid, sh.hbest[tid]);
           }
-          __syncthreads();
-          if (sh.qn > kStageM - VPU) mflush<NT>(sh, fln, rf);
         }
-        mflush<NT>(sh, fln, rf);
+        if (lane == 0 && cnt) {
+          atomicAdd((unsigned long long*)&sh.cnt, (unsigned long long)cnt);
+          atomicAdd((unsigned long long*)&sh.deg, (unsigned long long)deg);
+        }
+        if (lane == 0 && fin) atomicAdd((unsigned long long*)&sh.fin, (unsigned long long)fin);
+        // parts of split rows: the block's waves share each part's edges
+        const uint32_t U = uni(sh.hunits);
+        uint64_t* ticket = ctl + cTQ(L & 3);
+        bool firstu = true;
+        while (true) {
+          __syncthreads();
+          if (tid == 0) sh.unit = firstu ? rank : (U > nb ? nb + atomicAdd((uint32_t*)ticket, 1u) : U);
+          firstu = false;
+          __syncthreads();
+          const uint32_t hk = uni(sh.unit);
+          if (hk >= U) break;
+          if (tid == 0) {
+            int lo = 0, hi = (int)sh.nh;
+            while (hi - lo > 1) {
+              const int mid = (lo + hi) >> 1;
+              if ((uint32_t)phn[mid].y <= hk) lo = mid; else hi = mid;
+            }
+            sh.hidx = lo;
+            sh.heavy = phn[lo];
+          }
+          if (tid < 64) sh.hbest[tid] = kUnvisited;
+          __syncthreads();
+          const int32_t v = uni(sh.heavy.x);
+          const uint32_t part = hk - (uint32_t)uni(sh.heavy.y);
+          const int64_t e0 = rp[v] + (int64_t)part * kMSplit;
+          const int64_t e1 = min<int64_t>(rp[v + 1], e0 + kMSplit);
+          const uint64_t want = valid & ~A.rec[v].vis;
+          const int64_t seg = ((e1 - e0 + NW - 1) / NW + 63) / 64 * 64;
+          const int64_t s0 = min<int64_t>(e1, e0 + (int64_t)wave * seg);
+          const int64_t s1 = min<int64_t>(e1, s0 + seg);
+          uint64_t best = kUnvisited;
+          if (want && s0 < s1) best = pull_edges(G.adj, A.rec, s0, s1, pp, want, km, best);
+          if (best != kUnvisited) atomicMin((unsigned long long*)&sh.hbest[lane], (unsigned long long)best);
+          __syncthreads();
+          if (tid < 64 && sh.hbest[tid] != kUnvisited)
+            amin64(A.hslot + (size_t)sh.hidx * 64 + tid, sh.hbest[tid]);
+        }
+        __syncthreads();
         if (tid == 0) {
           if (sh.cnt) {
             aadd64(rf + 2, sh.cnt);
@@ -572,30 +742,27 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
           if (sh.fin) aadd64(ctl + cUNF, (uint64_t)0 - sh.fin);
         }
       }
-      const uint32_t nheavy = sh.nh;
+      const uint32_t nheavy = uni(sh.nh);
       group_sync(A.bar, rank, nb);
 
-      // ---- phase 3: split rows take their minima
+      // ---- phase 3: split rows take their minima (64 entries per wave)
       if (nheavy > 0) {
         uint64_t cnt = 0, deg = 0, fin = 0;
-        for (int64_t h = gwave; h < (int64_t)nheavy; h += nwaves) {
-          const int32_t v = A.ph[h].x;
-          uint64_t* hs = A.hslot + (size_t)h * 64;
-          const uint64_t best = hs[lane];
-          if (best != kUnvisited) hs[lane] = kUnvisited;
-          const bool found = best != kUnvisited;
-          const uint64_t newb = __ballot(found);
-          const uint64_t stb = __ballot(found && (best & 1));
-          const int dv = rp[v + 1] - rp[v];
-          if (lane == 0) {
+        for (int64_t wd = gwave; wd * 64 < (int64_t)nheavy; wd += nwaves) {
+          const int ne = (int)min<int64_t>(64, (int64_t)nheavy - wd * 64);
+          uint64_t bits = 0;
+          for (int q = 0; q < ne; ++q) {
+            const int64_t h = wd * 64 + q;
+            const int32_t v = phn[h].x;
+            uint64_t* hs = A.hslot + (size_t)h * 64;
+            const uint64_t best = hs[lane];
+            if (best != kUnvisited) hs[lane] = kUnvisited;
             const uint64_t vis = A.rec[v].vis, st = A.rec[v].st;
-            finish_vertex(A, v, vis, st, newb, stb, p, valid, push, dv, fin);
+            const int dv = rp[v + 1] - rp[v];
+            if (settle(A, v, vis, st, dv, best, p, valid, cnt, deg, fin)) bits |= 1ull << q;
+            if (push && lane == 0) aand64(A.cand + (v >> 6), ~(1ull << (v & 63)));
           }
-          mlist_global(lane == 0 && newb != 0, v, dv, fln, fhn, rf);
-          if (newb) {
-            cnt += 1;
-            deg += (uint64_t)dv;
-          }
+          if (lane == 0) rhn[wd] = bits;
         }
         if (lane == 0) {
           if (cnt) {
@@ -722,10 +889,14 @@ hipError_t launch_multi(fi_graph* g, const SweepArgs& sa, hipStream_t s) {
   a.cand = (uint64_t*)(ws + L.gsb);
   a.lstride = (int64_t)g->dg.n + 64;
   a.hstride = (int64_t)L.hcap + 64;
-  a.fl = (int32_t*)(ws + L.gql);
-  a.pl = a.fl + 2 * a.lstride;
-  a.fh = (int2*)(ws + L.gqh);
-  a.ph = a.fh + 2 * a.hstride;
+  a.rlstride = a.lstride / 64 + 2;
+  a.rhstride = (int64_t)L.mhcap / 64 + 2;
+  a.pl = (int32_t*)(ws + L.gql);
+  a.pm = a.pl + 2 * a.lstride;
+  a.ph = (int2*)(ws + L.gqh);
+  a.rl = (uint64_t*)(ws + L.mreach);
+  a.rm = a.rl + 2 * a.rlstride;
+  a.rh = a.rm + 2 * a.rlstride;
   a.hslot = (uint64_t*)(ws + L.mhslot);
   a.tasks = (const int4*)(ws + L.mtasks);
   a.cverts = (const int32_t*)(ws + L.cverts);
