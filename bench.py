@@ -74,7 +74,16 @@ def main():
     ap.add_argument("--cpu-trees", type=int, default=2)
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch leg")
     ap.add_argument("--no-planted", action="store_true", help="skip the 10^4-tree planted leg")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first copy this many MiB device to device (a kernel of known traffic "
+                         "for scaling hardware byte counters)")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic_sweep_<workload>.json from two rocprofv3 "
+                         "counter collections (FETCH_SIZE, WRITE_SIZE) of a --copy-probe-mib run")
     args = ap.parse_args()
+    if args.summarize_traffic:
+        summarize_traffic(args.summarize_traffic[0], args.summarize_traffic[1], args)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -110,6 +119,13 @@ def main():
         wname = "path+uniform n=1,000 m=5,000 p+=0.8"
     t_gen = time.perf_counter() - t_gen
     print(f"# generated {wname} in {t_gen:.1f}s", file=sys.stderr, flush=True)
+
+    if args.copy_probe_mib:
+        # one elementwise kernel that reads and writes copy_probe_mib MiB
+        src = torch.ones((args.copy_probe_mib << 20) // 4, dtype=torch.int32, device="cuda")
+        dst = torch.add(src, 1)
+        torch.cuda.synchronize()
+        del src, dst
 
     T = args.trees
     G = fr.Graph(g.row_ptr, g.col, g.sign, cloud_capacity=T)
@@ -157,6 +173,7 @@ def main():
         "launches": launches,
     }
 
+    sched_used = G.get_schedule()
     extra = {}
     if not args.no_plain:
         # the plain per-tree path: one launch per tree, one tree in flight
@@ -197,7 +214,7 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": wname, "trees_per_step": T, "seed": "step index",
-                   "schedule": G.get_schedule()},
+                   "schedule": sched_used},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "min_switches_last_step": best[0] if best else None,
@@ -248,6 +265,46 @@ def bench_graphl(fr, synth, torch):
         "autograd_steps_per_s": round(1.0 / autograd, 1),
         "best_rounded_frustration": int(counts.min().item()),
     }
+
+
+def _counter_per_dispatch(path, counter):
+    """Sum of `counter` per dispatch id (over all hardware instances), with the
+    kernel name of each dispatch, from a rocprofv3 counter_collection CSV."""
+    import csv
+    per = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] != counter:
+                continue
+            d = per.setdefault(r["Dispatch_Id"], [r["Kernel_Name"], 0.0])
+            d[1] += float(r["Counter_Value"])
+    return per
+
+
+def summarize_traffic(fetch_csv, write_csv, args):
+    """HBM bytes per launch of the sweep kernel: FETCH_SIZE and WRITE_SIZE (KiB)
+    of its dispatches, each scaled by what the same counter reads for the copy
+    probe (copy_probe_mib MiB read and as many written)."""
+    out = {"workload": args.workload, "kernel_sha": kernel_source_sha(),
+           "copy_probe_mib": args.copy_probe_mib}
+    total = 0.0
+    for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        per = _counter_per_dispatch(path, name)
+        copies = [v for k, v in per.values() if "elementwise" in k.lower()]
+        sweeps = [v for k, v in per.values() if "k_sweep_" in k]
+        if not copies or not sweeps:
+            raise SystemExit(f"{path}: no copy probe or no sweep dispatch for {name}")
+        probe_kib = max(copies)
+        scale = (args.copy_probe_mib << 20) / probe_kib  # bytes per counted KiB
+        per_launch = sum(sweeps) / len(sweeps) * scale
+        out[name] = {"probe_kib": probe_kib, "bytes_per_counted_kib": scale,
+                     "sweep_dispatches": len(sweeps), "bytes_per_launch": per_launch}
+        total += per_launch
+    out["bytes_per_launch"] = total
+    dst = os.path.join(ROOT, "profiles", f"traffic_sweep_{args.workload}.json")
+    with open(dst, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
 
 
 def bench_batch(fr, tune, torch, graphs, steps, trees=64):

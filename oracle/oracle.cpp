@@ -81,15 +81,14 @@ uint64_t tree_salt(uint64_t seed, int64_t t) {
     return splitmix_output(state);
 }
 
-// Vertex key of u in the tree with the given salt: 20 high bits of the
-// MurmurHash3 finalizer applied to (u * multiplier + addend) mod 2^32, where
-// the multiplier is the salt's high word forced odd and the addend its low
-// word; the vertex id below breaks ties.
+// Vertex key of u in the tree with the given salt: the MurmurHash3
+// finalizer of u, xor the salt's low word, times the salt's high word forced
+// odd, mod 2^32.  Each step is invertible, so distinct vertices never share
+// a key and "the minimum-key vertex" is always one vertex.
 uint64_t vertex_key(uint64_t salt, int32_t u) {
-    uint32_t mul = (uint32_t)(salt >> 32) | 1u;
-    uint32_t add = (uint32_t)(salt & 0xFFFFFFFFull);
-    uint32_t h = murmur_fmix32((uint32_t)u * mul + add) >> 12;
-    return ((uint64_t)h << 31) | (uint64_t)(uint32_t)u;
+    const uint32_t x = (uint32_t)(salt & 0xFFFFFFFFull);
+    const uint32_t m = (uint32_t)(salt >> 32) | 1u;
+    return (uint64_t)((murmur_fmix32((uint32_t)u) ^ x) * m);
 }
 
 // 128-bit key of a canonical state given as 64-bit words (vertex v is bit
@@ -168,9 +167,10 @@ void build_tree(const Graph& g, const std::vector<int32_t>& comp, uint64_t seed,
     const int32_t n = g.n;
     // roots: argmin of the key within each component
     std::vector<uint64_t> best(n, UINT64_MAX);
+    std::vector<int32_t> argbest(n, -1);
     for (int32_t v = 0; v < n; ++v) {
         uint64_t k = vertex_key(salt, v);
-        if (k < best[comp[v]]) best[comp[v]] = k;
+        if (k < best[comp[v]]) { best[comp[v]] = k; argbest[comp[v]] = v; }
     }
     T.level.assign(n, -1);
     T.parent.assign(n, -1);
@@ -179,8 +179,8 @@ void build_tree(const Graph& g, const std::vector<int32_t>& comp, uint64_t seed,
     T.order.clear();
     std::queue<int32_t> q;
     for (int32_t c = 0; c < n; ++c) {
-        if (best[c] == UINT64_MAX) continue;
-        int32_t r = (int32_t)(best[c] & 0x7FFFFFFFull);
+        if (argbest[c] < 0) continue;
+        int32_t r = argbest[c];
         T.level[r] = 0;
         q.push(r);
     }

@@ -41,38 +41,39 @@ __host__ __device__ __forceinline__ uint64_t tree_salt(uint64_t seed, uint64_t t
   return mix64(seed + t * kWeyl);
 }
 
-// Per-tree vertex hash: 20 high bits of fmix32(u * (salt_hi | 1) + salt_lo).
+// Per-tree vertex key: (fmix32(u) xor x) * m mod 2^32, with x the salt's low
+// word and m its high word forced odd.  A bijection of the 32-bit id, so no
+// two vertices share a key; fmix32(u) does not depend on the tree, so it is
+// computed once for all trees that need it.
 struct KeyMix {
-  uint32_t mul, add;
+  uint32_t x, m;
 };
 __host__ __device__ __forceinline__ KeyMix key_mix(uint64_t salt) {
-  return KeyMix{(uint32_t)(salt >> 32) | 1u, (uint32_t)salt};
+  return KeyMix{(uint32_t)salt, (uint32_t)(salt >> 32) | 1u};
 }
-__device__ __forceinline__ uint32_t vhash20(KeyMix k, uint32_t u) {
-  return fmix32(u * k.mul + k.add) >> 12;
-}
+__device__ __forceinline__ uint32_t vkey_of(KeyMix k, uint32_t h) { return (h ^ k.x) * k.m; }
+__device__ __forceinline__ uint32_t vkey(KeyMix k, uint32_t u) { return vkey_of(k, fmix32(u)); }
 
 // ----------------------------------------------------------------- tree words
 // One 64-bit word per vertex carries the BFS level (12 bits), the parent's
-// hash (20 bits) and id (31 bits) and the vertex's state bit (1 = state -1):
-//   level << 52 | hash << 32 | parent << 1 | bit.
+// key (32 bits) and the vertex's state bit (1 = state -1):
+//   level << 52 | key << 20 | bit.
 // Unsigned order is (level, parent key), so an atomic minimum keeps the
 // earliest level and, within it, the minimum-key parent; words of earlier
 // levels are never overwritten.  All ones = not reached yet.
 constexpr uint64_t kUnvisited = ~0ull;
 constexpr uint32_t kMaxLevel = 4094;
 
-__device__ __forceinline__ uint64_t tree_word(uint32_t level, uint32_t h20, uint32_t u,
-                                              uint32_t bit) {
-  return ((uint64_t)level << 52) | ((uint64_t)h20 << 32) | ((uint64_t)u << 1) | bit;
+__device__ __forceinline__ uint64_t tree_word(uint32_t level, uint32_t key, uint32_t bit) {
+  return ((uint64_t)level << 52) | ((uint64_t)key << 20) | bit;
+}
+// Candidate word used to pick a component's root or a parent while its id
+// is still needed: key, then id, then a spare low bit.
+__device__ __forceinline__ uint64_t root_candidate(uint32_t key, uint32_t u) {
+  return ((uint64_t)key << 32) | ((uint64_t)u << 1);
 }
 __device__ __forceinline__ uint32_t word_vertex(uint64_t w) {
   return (uint32_t)(w >> 1) & 0x7FFFFFFFu;
-}
-// Candidate word used to pick a component's root: same order as tree_word at
-// level 0 (hash, then id).
-__device__ __forceinline__ uint64_t root_candidate(uint32_t h20, uint32_t u) {
-  return ((uint64_t)h20 << 32) | ((uint64_t)u << 1);
 }
 
 // Packed adjacency entry: neighbour id in the low 31 bits, bit 31 set for a

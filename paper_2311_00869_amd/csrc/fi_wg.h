@@ -44,7 +44,7 @@ __device__ __forceinline__ void wg_tree(const DevGraph& G, const SweepArgs& A, u
   __syncthreads();
   // (b) component roots: minimum key, accumulated in the anchor's word
   for (int32_t v = tid; v < n; v += NT)
-    if (rp[v + 1] > rp[v]) amin64(pw + G.comp[v], root_candidate(vhash20(km, v), v));
+    if (rp[v + 1] > rp[v]) amin64(pw + G.comp[v], root_candidate(vkey(km, v), v));
   __syncthreads();
   // (c) collect the roots of components with an edge
   for (int32_t v = tid; v < n; v += NT) {
@@ -59,10 +59,10 @@ __device__ __forceinline__ void wg_tree(const DevGraph& G, const SweepArgs& A, u
   const uint32_t nroots = sh.tail;
   for (uint32_t i = tid; i < nroots; i += NT) {
     int32_t r = q[i];
-    pw[r] = tree_word(0, vhash20(km, r), r, 0);
+    pw[r] = tree_word(0, vkey(km, r), 0);
   }
   for (int32_t v = tid; v < n; v += NT)
-    if (rp[v + 1] == rp[v]) pw[v] = tree_word(0, vhash20(km, v), v, 0);
+    if (rp[v + 1] == rp[v]) pw[v] = tree_word(0, vkey(km, v), 0);
   __syncthreads();
 
   // (d) BFS, level by level; the frontier is q[lo, hi)
@@ -80,7 +80,7 @@ __device__ __forceinline__ void wg_tree(const DevGraph& G, const SweepArgs& A, u
         const int32_t u = q[i];
         st = rp[u];
         d = rp[u + 1] - st;
-        base = tree_word(L + 1, vhash20(km, u), u, (uint32_t)(pw[u] & 1));
+        base = tree_word(L + 1, vkey(km, u), (uint32_t)(pw[u] & 1));
       }
       int total;
       const int off = block_exclusive_scan<NT>(d, total, sh.scan);

@@ -240,21 +240,49 @@ __global__ void k_aslot(const int32_t* anchors, int32_t nanch, int32_t* aslot) {
     aslot[anchors[i]] = (int32_t)i;
 }
 
+// Slot of vertex v's component (-1 without an edge).  Whole waves of one
+// component (the common case of a giant component) take one atomic.
+__device__ __forceinline__ int32_t comp_slot(const int32_t* rp, const int32_t* comp,
+                                             const int32_t* aslot, int64_t v, int32_t n) {
+  return v < n && rp[v + 1] > rp[v] ? aslot[comp[v]] : -1;
+}
+
 __global__ void k_ccount(const int32_t* rp, const int32_t* comp, const int32_t* aslot, int32_t n,
                          int32_t* count) {
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
-       v += (int64_t)gridDim.x * blockDim.x)
-    if (rp[v + 1] > rp[v]) atomicAdd(count + aslot[comp[v]], 1);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v0 = blockIdx.x * (int64_t)blockDim.x; v0 < n; v0 += stride) {
+    const int64_t v = v0 + threadIdx.x;
+    const int32_t sl = comp_slot(rp, comp, aslot, v, n);
+    const uint64_t mask = __ballot(sl >= 0);
+    if (!mask) continue;
+    const int32_t s0 = __shfl(sl, __ffsll((unsigned long long)mask) - 1);
+    if (__ballot(sl >= 0 && sl != s0) == 0) {
+      if (lanes_below(mask) == 0 && sl >= 0) atomicAdd(count + s0, (int)__popcll(mask));
+    } else if (sl >= 0) {
+      atomicAdd(count + sl, 1);
+    }
+  }
 }
 
 __global__ void k_cfill(const int32_t* rp, const int32_t* comp, const int32_t* aslot,
                         const int32_t* cptr, int32_t n, int32_t* fill, int32_t* cverts) {
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
-       v += (int64_t)gridDim.x * blockDim.x)
-    if (rp[v + 1] > rp[v]) {
-      const int32_t sl = aslot[comp[v]];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v0 = blockIdx.x * (int64_t)blockDim.x; v0 < n; v0 += stride) {
+    const int64_t v = v0 + threadIdx.x;
+    const int32_t sl = comp_slot(rp, comp, aslot, v, n);
+    const uint64_t mask = __ballot(sl >= 0);
+    if (!mask) continue;
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    const int32_t s0 = __shfl(sl, leader);
+    if (__ballot(sl >= 0 && sl != s0) == 0) {
+      int32_t base = 0;
+      if (lane_id() == leader) base = atomicAdd(fill + s0, (int)__popcll(mask));
+      base = __shfl(base, leader);
+      if (sl >= 0) cverts[cptr[s0] + base + (int32_t)lanes_below(mask)] = (int32_t)v;
+    } else if (sl >= 0) {
       cverts[cptr[sl] + atomicAdd(fill + sl, 1)] = (int32_t)v;
     }
+  }
 }
 
 __global__ void k_fill_i32(int32_t* p, int64_t len, int32_t val) {

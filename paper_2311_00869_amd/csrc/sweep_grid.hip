@@ -260,7 +260,7 @@ __global__ void __launch_bounds__(NT, 4) k_sweep_grid(DevGraph G, GridArgs A) {
           cur = wc;
           cmin = kUnvisited;
         }
-        const uint64_t cand = root_candidate(vhash20(km, v), v);
+        const uint64_t cand = root_candidate(vkey(km, v), v);
         const uint64_t mn = wave_min_u64(((main >> lane) & 1) ? cand : kUnvisited);
         cmin = mn < cmin ? mn : cmin;
         if ((minor >> lane) & 1) amin64(rootkey + G.comp[v], cand);
@@ -288,7 +288,7 @@ __global__ void __launch_bounds__(NT, 4) k_sweep_grid(DevGraph G, GridArgs A) {
           rootkey[a] = kUnvisited;
           r = (int32_t)word_vertex(k);
           dr = rp[r + 1] - rp[r];
-          pw[r] = tree_word(0, vhash20(km, r), r, 0);
+          pw[r] = tree_word(0, vkey(km, r), 0);
           aor64(fbuf + (r >> 6), 1ull << (r & 63));
         }
         list_vertex<NT>(ok, r, dr, A, sh, qhb, ring0);
@@ -386,7 +386,7 @@ __global__ void __launch_bounds__(NT, 4) k_sweep_grid(DevGraph G, GridArgs A) {
               st = rp[u];
               d = rp[u + 1] - st;
               const uint32_t b = (uint32_t)(pw[u] & 1);
-              base = tree_word(L + 1, vhash20(km, u), u, b);
+              base = tree_word(L + 1, vkey(km, u), b);
               aor64(vis + (u >> 6), 1ull << (u & 63));
               if (b) aor64(sbs + (u >> 6), 1ull << (u & 63));
             }
@@ -415,7 +415,7 @@ __global__ void __launch_bounds__(NT, 4) k_sweep_grid(DevGraph G, GridArgs A) {
             }
             e0 = rp[u] + (int64_t)part * kHeavyUnit;
             const int64_t e1 = min<int64_t>(rp[u + 1], e0 + kHeavyUnit);
-            hbase = tree_word(L + 1, vhash20(km, u), u, b);
+            hbase = tree_word(L + 1, vkey(km, u), b);
             total = (int)(e1 - e0);
           }
           for (int j0 = 0; j0 < total; j0 += NT) {
@@ -502,7 +502,7 @@ __global__ void __launch_bounds__(NT, 4) k_sweep_grid(DevGraph G, GridArgs A) {
                 if (kk[q] < 0) continue;
                 const uint32_t u = a[q] & kVertexMask;
                 if (bit_at(fb, u)) {
-                  const uint64_t c = root_candidate(vhash20(km, u), u) | (a[q] >> 31);
+                  const uint64_t c = root_candidate(vkey(km, u), u) | (a[q] >> 31);
                   atomicMin((unsigned long long*)(wbest + kk[q]), (unsigned long long)c);
                 }
               }
@@ -514,7 +514,7 @@ __global__ void __launch_bounds__(NT, 4) k_sweep_grid(DevGraph G, GridArgs A) {
             if (found) {
               const uint32_t u = word_vertex(best);
               b = bit_at(sbs, u) ^ (uint32_t)(best & 1);
-              pw[v] = tree_word(L + 1, (uint32_t)(best >> 32), u, b);
+              pw[v] = tree_word(L + 1, (uint32_t)(best >> 32), b);
             }
             const uint64_t nbits = __ballot(found);
             const uint64_t bbits = __ballot(found && b);

@@ -41,7 +41,7 @@ namespace fi {
 namespace {
 
 constexpr int kStageM = 2048;      // LDS staging entries for light list appends
-constexpr int kPushCost = 2;       // push while kPushCost * frontier edges < unfinished edges
+constexpr int kPushCost = 4;       // push while kPushCost * frontier edges < unfinished edges
 constexpr int kSmall = 64;         // rows up to this many edges are pulled 64 vertices per wave
 constexpr int kMedPerWave = 4;     // medium rows per wave per unit
 constexpr int kMedChunk = 64;      // medium frontier rows per push unit
@@ -197,34 +197,34 @@ __device__ __forceinline__ void mlist_global(bool in, int32_t v, int dv, int32_t
   }
 }
 
-// Lane t: minimum over the edges [e0, e1) of the candidate key (hash, id,
+// Lane t: minimum over the edges [e0, e1) of the candidate (key << 1 |
 // state bit) of every neighbour discovered at the previous level of tree t
-// (parity pp) in a tree of `want`.
+// (parity pp) in a tree of `want`.  The tree-independent part of each
+// neighbour's key and the edge sign are folded in once per edge lane.
 __device__ __forceinline__ uint64_t pull_edges(const uint32_t* adj, const MRec* rec, int64_t e0,
                                                int64_t e1, int pp, uint64_t want, KeyMix km,
                                                uint64_t best) {
   const int lane = lane_id();
   for (int64_t c = e0; c < e1; c += 64) {
     const int64_t e = c + lane;
-    uint32_t a = 0;
+    uint32_t H = 0;
     uint64_t F = 0, S = 0;
     if (e < e1) {
-      a = adj[e];
+      const uint32_t a = adj[e];
       const MRec* ru = rec + (a & kVertexMask);
       F = ru->nb[pp] & want;
-      if (F) S = ru->st;
+      if (F) S = ru->st ^ ((a >> 31) ? ~0ull : 0ull);
+      H = fmix32(a & kVertexMask);
     }
     uint64_t hits = __ballot(F != 0);
     while (hits) {
       const int j = __builtin_ctzll(hits);
       hits &= hits - 1;
-      const uint32_t aj = __builtin_amdgcn_readlane(a, j);
+      const uint32_t Hj = __builtin_amdgcn_readlane(H, j);
       const uint64_t Fj = readlane64(F, j);
       const uint64_t Sj = readlane64(S, j);
       if ((Fj >> lane) & 1) {
-        const uint32_t uj = aj & kVertexMask;
-        const uint64_t bit = ((Sj >> lane) & 1) ^ (uint64_t)(aj >> 31);
-        const uint64_t c2 = ((uint64_t)vhash20(km, uj) << 33) | ((uint64_t)uj << 1) | bit;
+        const uint64_t c2 = ((uint64_t)vkey_of(km, Hj) << 1) | ((Sj >> lane) & 1);
         best = c2 < best ? c2 : best;
       }
     }
@@ -240,9 +240,11 @@ __device__ __forceinline__ uint64_t comp_min(const int32_t* cverts, int32_t b, i
     const int32_t i = c + lane;
     const int32_t mine = i < e ? cverts[i] : 0;
     const int cnt = min(64, e - c);
+    const uint32_t hm = fmix32((uint32_t)mine);
     for (int j = 0; j < cnt; ++j) {
       const uint32_t v = (uint32_t)__builtin_amdgcn_readlane(mine, j);
-      const uint64_t k = root_candidate(vhash20(km, v), v);
+      const uint32_t h = (uint32_t)__builtin_amdgcn_readlane((int)hm, j);
+      const uint64_t k = root_candidate(vkey_of(km, h), v);
       best = k < best ? k : best;
     }
   }
@@ -366,13 +368,14 @@ __device__ __forceinline__ uint64_t pull_small(const DevGraph& G, const MArgs& A
     const uint32_t wlo = (uint32_t)__shfl((int)(uint32_t)want, kj);
     const uint32_t whi = (uint32_t)__shfl((int)(uint32_t)(want >> 32), kj);
     const uint64_t wk = ((uint64_t)whi << 32) | wlo;
-    uint32_t a = 0;
+    uint32_t H = 0;
     uint64_t F = 0, S = 0;
     if (lane < total) {
-      a = G.adj[(int64_t)sk + (eb + lane - ek)];
+      const uint32_t a = G.adj[(int64_t)sk + (eb + lane - ek)];
       const MRec* ru = A.rec + (a & kVertexMask);
       F = ru->nb[pp] & wk;
-      if (F) S = ru->st;
+      if (F) S = ru->st ^ ((a >> 31) ? ~0ull : 0ull);
+      H = fmix32(a & kVertexMask);
     }
     uint64_t hits = __ballot(F != 0);
     uint64_t best = kUnvisited;
@@ -389,13 +392,11 @@ __device__ __forceinline__ uint64_t pull_small(const DevGraph& G, const MArgs& A
         best = kUnvisited;
         cur = kk;
       }
-      const uint32_t aj = __builtin_amdgcn_readlane(a, jj);
+      const uint32_t Hj = __builtin_amdgcn_readlane(H, jj);
       const uint64_t Fj = readlane64(F, jj);
       const uint64_t Sj = readlane64(S, jj);
       if ((Fj >> lane) & 1) {
-        const uint32_t uj = aj & kVertexMask;
-        const uint64_t bit = ((Sj >> lane) & 1) ^ (uint64_t)(aj >> 31);
-        const uint64_t c2 = ((uint64_t)vhash20(km, uj) << 33) | ((uint64_t)uj << 1) | bit;
+        const uint64_t c2 = ((uint64_t)vkey_of(km, Hj) << 1) | ((Sj >> lane) & 1);
         best = c2 < best ? c2 : best;
       }
     }

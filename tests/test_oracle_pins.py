@@ -62,12 +62,18 @@ def test_fmix32_published_vectors():
     assert _murmur3_x86_32(b"The quick brown fox jumps over the lazy dog", 0) == 0x2E4FF723
 
 
-def test_vertex_key_layout():
-    salt = oracle.tree_salt(5, 17)
-    for u in [0, 1, 2, 1000, 2**31 - 1]:
-        k = oracle.vertex_key(salt, u)
-        assert k & (2**31 - 1) == u
-        assert k >> 31 < 2**20
+def test_vertex_key_is_a_bijection():
+    # distinct vertices never share a key, so the minimum-key vertex of any
+    # set is unique; the key does depend on the tree
+    for seed, t in [(5, 17), (0, 0)]:
+        salt = oracle.tree_salt(seed, t)
+        keys = [oracle.vertex_key(salt, u) for u in range(1 << 14)]
+        keys += [oracle.vertex_key(salt, u) for u in range(2**31 - (1 << 12), 2**31)]
+        assert all(0 <= k < 2**32 for k in keys)
+        assert len(set(keys)) == len(keys)
+    a = [oracle.vertex_key(oracle.tree_salt(1, 0), u) for u in range(64)]
+    b = [oracle.vertex_key(oracle.tree_salt(1, 1), u) for u in range(64)]
+    assert np.argsort(a).tolist() != np.argsort(b).tolist()
 
 
 # ------------------------------------------------------------ Figure fig-Balance
