@@ -2,10 +2,10 @@
 // a time, one bit per tree in every per-vertex word (bit t is tree t0 + t and
 // lane t of every wavefront).
 //
-// Each vertex has a 32-byte record: the trees in which it was discovered at
-// the last even and the last odd level, its state bits, and the trees that
-// have visited it.  One BFS level then serves all 64 trees with one pass over
-// the rows involved:
+// Each vertex has two 16-byte records, one per level parity, each holding
+// the trees in which it was discovered at the last level of that parity and
+// its state bits, plus a word of the trees that have visited it.  One BFS
+// level then serves all 64 trees with one pass over the rows involved:
 //   push - while the frontier is small, its rows mark as candidates every
 //          neighbour still unvisited in a tree where the frontier vertex was
 //          just discovered;
@@ -47,12 +47,13 @@ constexpr int kMedPerWave = 4;     // medium rows per wave per unit
 constexpr int kMedChunk = 64;      // medium frontier rows per push unit
 constexpr int kPlanes = 8;         // bit-sliced counter planes (flushed every 255 edges)
 
-// Per-vertex record: discovered at the last even / odd level, state bits,
-// visited.
-struct __align__(32) MRec {
-  uint64_t nb[2];
+// Per-vertex state, one 16-byte record per level parity: the trees that
+// discovered the vertex at the last level of that parity, and the state bits
+// (kept equal in both records).  A pull gathers only the record of the
+// previous level's parity, half the bytes of one record holding both.
+struct __align__(16) MRec {
+  uint64_t nb;
   uint64_t st;
-  uint64_t vis;
 };
 
 // Control words; each group sits on its own 128-byte line.  r = level mod 4.
@@ -77,7 +78,8 @@ struct MArgs {
   uint64_t* tree_switches;
   int insert;
   int32_t ntasks, nbig;
-  MRec* rec;
+  MRec* rec[2];          // [parity][n]
+  uint64_t* vis;         // [n] trees that visited the vertex
   uint64_t* unf;        // [nwords] vertices with an edge not yet visited by every tree
   uint64_t* cand;       // [nwords] push candidates of the level
   int32_t* pl;          // [2][lstride] pull lists of rows up to kSmall (by level parity)
@@ -112,7 +114,6 @@ struct MS {
   uint32_t nl, nm, nh, hunits;
   uint64_t hbest[64];
   uint64_t tacc[3][64];
-  int wflag[NT];        // per wave: starts of the rows of a pull round
 };
 
 __device__ __forceinline__ uint64_t amin64(uint64_t* p, uint64_t v) {
@@ -197,10 +198,34 @@ __device__ __forceinline__ void mlist_global(bool in, int32_t v, int dv, int32_t
   }
 }
 
+// 64x64 bit transpose across the wave: afterwards bit j of lane t is what
+// bit t of lane j was.  Six exchange stages; stage s swaps bit s of the row
+// (lane) index with bit s of the column (bit) index.
+__device__ __forceinline__ uint64_t transpose64(uint64_t x) {
+  const int lane = lane_id();
+  const uint64_t masks[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                             0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int sft = 32 >> k;
+    const uint64_t m = masks[k];
+    const uint32_t ylo = (uint32_t)__shfl_xor((int)(uint32_t)x, sft);
+    const uint32_t yhi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), sft);
+    const uint64_t y = ((uint64_t)yhi << 32) | ylo;
+    x = (lane & sft) ? ((x & ~m) | ((y & ~m) >> sft)) : ((x & m) | ((y & m) << sft));
+  }
+  return x;
+}
+
+// Chunks with at least this many hit edges take the transposed walk.
+constexpr int kDenseHits = 8;
+
 // Lane t: minimum over the edges [e0, e1) of the candidate (key << 1 |
 // state bit) of every neighbour discovered at the previous level of tree t
 // (parity pp) in a tree of `want`.  The tree-independent part of each
-// neighbour's key and the edge sign are folded in once per edge lane.
+// neighbour's key and the edge sign are folded in once per edge lane.  A
+// chunk with few hit edges is walked edge by edge with all lanes; a dense
+// one is transposed so that lane t walks only the edges that hit tree t.
 __device__ __forceinline__ uint64_t pull_edges(const uint32_t* adj, const MRec* rec, int64_t e0,
                                                int64_t e1, int pp, uint64_t want, KeyMix km,
                                                uint64_t best) {
@@ -212,11 +237,27 @@ __device__ __forceinline__ uint64_t pull_edges(const uint32_t* adj, const MRec* 
     if (e < e1) {
       const uint32_t a = adj[e];
       const MRec* ru = rec + (a & kVertexMask);
-      F = ru->nb[pp] & want;
+      F = ru->nb & want;
       if (F) S = ru->st ^ ((a >> 31) ? ~0ull : 0ull);
       H = fmix32(a & kVertexMask);
     }
     uint64_t hits = __ballot(F != 0);
+    if (__popcll(hits) >= kDenseHits) {
+      uint64_t C = transpose64(F);   // bit j: edge lane j hits this lane's tree
+      const uint64_t SC = transpose64(S);
+      int iters = __popcll(C);
+#pragma unroll
+      for (int d = 32; d > 0; d >>= 1) iters = max(iters, __shfl_xor(iters, d));
+      for (int it = 0; it < iters; ++it) {
+        const bool on = C != 0;
+        const int j = on ? __builtin_ctzll(C) : 0;
+        C &= C - 1;
+        const uint32_t Hj = (uint32_t)__shfl((int)H, j);
+        const uint64_t c2 = ((uint64_t)vkey_of(km, Hj) << 1) | ((SC >> j) & 1);
+        if (on && c2 < best) best = c2;
+      }
+      continue;
+    }
     while (hits) {
       const int j = __builtin_ctzll(hits);
       hits &= hits - 1;
@@ -278,8 +319,8 @@ __device__ __forceinline__ void set_roots(uint64_t best, bool vlane, uint64_t va
   int dv = 0;
   if (leader) {
     dv = rp[r + 1] - rp[r];
-    A.rec[r].nb[0] = mine;
-    A.rec[r].vis = mine;
+    A.rec[0][r].nb = mine;
+    A.vis[r] = mine;
     if (mine == valid) {
       aand64(A.unf + (r >> 6), ~(1ull << (r & 63)));
       fin += (uint64_t)dv;
@@ -303,10 +344,12 @@ __device__ __forceinline__ bool settle(const MArgs& A, int32_t v, uint64_t vis, 
   const uint64_t stb = __ballot(best != kUnvisited && (best & 1));
   const bool full = (vis | newb) == valid;
   if (lane_id() == 0) {
-    MRec* r = A.rec + v;
-    r->vis = vis | newb;
-    r->nb[p] = newb;
-    if (stb) r->st = st | stb;
+    A.vis[v] = vis | newb;
+    A.rec[p][v].nb = newb;
+    if (stb) {
+      A.rec[0][v].st = st | stb;
+      A.rec[1][v].st = st | stb;
+    }
     if (full) aand64(A.unf + (v >> 6), ~(1ull << (v & 63)));
   }
   if (full) fin += (uint64_t)dv;
@@ -315,15 +358,28 @@ __device__ __forceinline__ bool settle(const MArgs& A, int32_t v, uint64_t vis, 
   return true;
 }
 
+__device__ __forceinline__ uint64_t wave_or64(uint64_t x) {
+#pragma unroll
+  for (int dd = 32; dd > 0; dd >>= 1) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, dd);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), dd);
+    x |= ((uint64_t)hi << 32) | lo;
+  }
+  return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32)) << 32) |
+         (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+}
+
 // One wave pulls the small-row list entries i0 .. i0 + ne - 1 (ne <= 64;
-// lane k holds entry i0 + k; every row has at most kSmall edges).  Rows are
-// walked in rounds of at most 64 edges, as many whole rows as fit, all
-// loads of a round in flight together; a vertex is settled when the walk
-// leaves its row.  Returns the entries some tree reached (bit k).
+// lane k holds entry i0 + k; every row has at most kSmall edges and at least
+// one).  Rows are walked in rounds of at most 64 edges, as many whole rows as
+// fit, all loads of a round in flight together.  Each row's outcome (trees
+// that reached the vertex, their state bits) stays in its lane until the
+// batch is walked, then every vertex is written back at once, so no store
+// is waited for inside the walk.  Returns the entries some tree reached.
 __device__ __forceinline__ uint64_t pull_small(const DevGraph& G, const MArgs& A, const int32_t* list,
                                                int64_t i0, int ne, int pp, int p, uint64_t valid,
-                                               KeyMix km, bool push, int* wflag, uint64_t& cnt,
-                                               uint64_t& deg, uint64_t& fin) {
+                                               KeyMix km, bool push, uint64_t& cnt, uint64_t& deg,
+                                               uint64_t& fin) {
   const int lane = lane_id();
   const bool ok = lane < ne;
   int32_t v = 0;
@@ -333,9 +389,8 @@ __device__ __forceinline__ uint64_t pull_small(const DevGraph& G, const MArgs& A
     v = list[i0 + lane];
     s = G.row_ptr[v];
     d = G.row_ptr[v + 1] - s;
-    vis = A.rec[v].vis;
-    st = A.rec[v].st;
-    if (push) aand64(A.cand + (v >> 6), ~(1ull << (v & 63)));
+    vis = A.vis[v];
+    st = A.rec[0][v].st;
   }
   const uint64_t want = valid & ~vis;
   int inc = d;
@@ -345,24 +400,25 @@ __device__ __forceinline__ uint64_t pull_small(const DevGraph& G, const MArgs& A
     if (lane >= o) inc += y;
   }
   const int excl = inc - d;
-  uint64_t reached = 0;
+  uint64_t mnew = 0, mstb = 0;  // outcome of this lane's row
+  auto keep = [&](int k, uint64_t newb, uint64_t stb) {
+    if (lane == k) {
+      mnew = newb;
+      mstb = stb;
+    }
+  };
   int k0 = 0;
   while (k0 < ne) {
     const int eb = uni(__shfl(excl, k0));
-    const uint64_t fit = __ballot(ok && lane >= k0 && inc - eb <= 64);
+    const bool inr = ok && lane >= k0 && inc - eb <= 64;
+    const uint64_t fit = __ballot(inr);
     const int k1 = k0 + (int)__popcll(fit);  // >= k0 + 1: every row fits a round
     const int total = uni(__shfl(inc, k1 - 1)) - eb;
-    // owner of each edge lane: the rows' starts as a bit mask
-    wflag[lane] = 0;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    if (lane >= k0 && lane < k1) wflag[excl - eb] = 1;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    const uint64_t starts = __ballot(wflag[lane] != 0);
-    __builtin_amdgcn_wave_barrier();
+    // the rows' starts: 0 and every row end but the last
+    const int e = inc - eb;
+    const uint64_t starts = 1ull | wave_or64(inr && e < total ? (1ull << e) : 0ull);
     const int r = (int)__popcll(starts & ((2ull << lane) - 1));
-    const int kj = k0 + (r > 0 ? r - 1 : 0);
+    const int kj = k0 + r - 1;
     const int sk = __shfl(s, kj);
     const int ek = __shfl(excl, kj);
     const uint32_t wlo = (uint32_t)__shfl((int)(uint32_t)want, kj);
@@ -372,12 +428,55 @@ __device__ __forceinline__ uint64_t pull_small(const DevGraph& G, const MArgs& A
     uint64_t F = 0, S = 0;
     if (lane < total) {
       const uint32_t a = G.adj[(int64_t)sk + (eb + lane - ek)];
-      const MRec* ru = A.rec + (a & kVertexMask);
-      F = ru->nb[pp] & wk;
+      const MRec* ru = A.rec[pp] + (a & kVertexMask);
+      F = ru->nb & wk;
       if (F) S = ru->st ^ ((a >> 31) ? ~0ull : 0ull);
       H = fmix32(a & kVertexMask);
     }
     uint64_t hits = __ballot(F != 0);
+    if (__popcll(hits) >= kDenseHits) {
+      // dense round: lane t walks the edges that hit tree t; per row it keeps
+      // whether tree t reached the vertex (found bit) and with which state
+      uint64_t C = transpose64(F);
+      const uint64_t SC = transpose64(S);
+      int iters = __popcll(C);
+#pragma unroll
+      for (int dd = 32; dd > 0; dd >>= 1) iters = max(iters, __shfl_xor(iters, dd));
+      uint64_t found = 0, sbits = 0, best = kUnvisited;
+      int cur = -1;
+      for (int it = 0; it < iters; ++it) {
+        const bool on = C != 0;
+        const int j = on ? __builtin_ctzll(C) : 0;
+        C &= C - 1;
+        const uint32_t Hj = (uint32_t)__shfl((int)H, j);
+        const int seg = (int)__popcll(starts & ((2ull << j) - 1)) - 1;
+        const uint64_t c2 = ((uint64_t)vkey_of(km, Hj) << 1) | ((SC >> j) & 1);
+        if (on) {
+          if (seg != cur) {
+            if (cur >= 0) {
+              found |= 1ull << cur;
+              sbits |= (best & 1) << cur;
+            }
+            cur = seg;
+            best = c2;
+          } else if (c2 < best) {
+            best = c2;
+          }
+        }
+      }
+      if (cur >= 0) {
+        found |= 1ull << cur;
+        sbits |= (best & 1) << cur;
+      }
+      uint64_t any = wave_or64(found);
+      while (any) {
+        const int q = __builtin_ctzll(any);
+        any &= any - 1;
+        keep(k0 + q, __ballot((found >> q) & 1), __ballot((found >> q) & (sbits >> q) & 1));
+      }
+      k0 = k1;
+      continue;
+    }
     uint64_t best = kUnvisited;
     int cur = -1;
     while (hits) {
@@ -385,10 +484,8 @@ __device__ __forceinline__ uint64_t pull_small(const DevGraph& G, const MArgs& A
       hits &= hits - 1;
       const int kk = __builtin_amdgcn_readlane(kj, jj);
       if (kk != cur) {
-        if (cur >= 0 &&
-            settle(A, __builtin_amdgcn_readlane(v, cur), readlane64(vis, cur), readlane64(st, cur),
-                   __builtin_amdgcn_readlane(d, cur), best, p, valid, cnt, deg, fin))
-          reached |= 1ull << cur;
+        if (cur >= 0)
+          keep(cur, __ballot(best != kUnvisited), __ballot(best != kUnvisited && (best & 1)));
         best = kUnvisited;
         cur = kk;
       }
@@ -400,12 +497,26 @@ __device__ __forceinline__ uint64_t pull_small(const DevGraph& G, const MArgs& A
         best = c2 < best ? c2 : best;
       }
     }
-    if (cur >= 0 &&
-        settle(A, __builtin_amdgcn_readlane(v, cur), readlane64(vis, cur), readlane64(st, cur),
-               __builtin_amdgcn_readlane(d, cur), best, p, valid, cnt, deg, fin))
-      reached |= 1ull << cur;
+    if (cur >= 0) keep(cur, __ballot(best != kUnvisited), __ballot(best != kUnvisited && (best & 1)));
     k0 = k1;
   }
+  // write back every reached vertex of the batch
+  const bool got = ok && mnew != 0;
+  const bool full = got && (vis | mnew) == valid;
+  if (got) {
+    A.vis[v] = vis | mnew;
+    A.rec[p][v].nb = mnew;
+    if (mstb) {
+      A.rec[0][v].st = st | mstb;
+      A.rec[1][v].st = st | mstb;
+    }
+    if (full) aand64(A.unf + (v >> 6), ~(1ull << (v & 63)));
+  }
+  if (ok && push) aand64(A.cand + (v >> 6), ~(1ull << (v & 63)));
+  const uint64_t reached = __ballot(got);
+  cnt += (uint64_t)__popcll(reached);
+  deg += wave_sum_u64(got ? (uint64_t)d : 0ull);
+  fin += wave_sum_u64(full ? (uint64_t)d : 0ull);
   return reached;
 }
 
@@ -420,7 +531,6 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
   const int32_t n = G.n, nw = G.nwords;
   const int32_t* rp = G.row_ptr;
   uint64_t* ctl = A.ctl;
-  int* wflag = sh.wflag + wave * 64;
 
   for (uint64_t tb = A.t0; tb < A.t1; tb += 64) {
     const int nvalid = (int)min<uint64_t>(64, A.t1 - tb);
@@ -431,11 +541,11 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
     // ---- reset: records, bitmaps, control words
     for (int64_t v = stid; v < n; v += sstride) {
       MRec z;
-      z.nb[0] = 0;
-      z.nb[1] = 0;
+      z.nb = 0;
       z.st = 0;
-      z.vis = 0;
-      A.rec[v] = z;
+      A.rec[0][v] = z;
+      A.rec[1][v] = z;
+      A.vis[v] = 0;
     }
     for (int64_t i = stid; i < nw; i += sstride) {
       A.unf[i] = G.word_mask[i];
@@ -527,8 +637,9 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
           ctl[cTM(r)] = 0;
         }
       }
-      // medium rows set their reached bits with atomics
+      // medium and split rows set their reached bits with atomics
       for (int64_t i = stid; i < A.rlstride; i += sstride) rmn[i] = 0;
+      for (int64_t i = stid; i < A.rhstride; i += sstride) rhn[i] = 0;
 
       // ---- phase 1: the pull lists of level L
       if (push) {
@@ -564,7 +675,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
             if (u >= 0) {
               st = rp[u];
               d = rp[u + 1] - st;
-              bits = A.rec[u].nb[pp] & valid;
+              bits = A.rec[pp][u].nb & valid;
             }
             const int off = block_exclusive_scan<NT>(d, total, sh.scan);
             sh.off[tid] = off;
@@ -590,7 +701,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
               const uint32_t part = hk - (uint32_t)uni(sh.heavy.y);
               e0 = rp[u] + (int64_t)part * kMSplit;
               const int64_t e1 = min<int64_t>(rp[u + 1], e0 + kMSplit);
-              hbits = A.rec[u].nb[pp] & valid;
+              hbits = A.rec[pp][u].nb & valid;
               total = (int)(e1 - e0);
             }
           }
@@ -611,7 +722,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
                 bits = hbits;
               }
               v = (int32_t)(a & kVertexMask);
-              if (bits & ~A.rec[v].vis) {
+              if (bits & ~A.vis[v]) {
                 const uint64_t bit = 1ull << (v & 63);
                 if (!(aor64(A.cand + (v >> 6), bit) & bit)) {
                   first = true;
@@ -659,8 +770,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
         const int64_t nl = (int64_t)uni(sh.nl);
         for (int64_t b = gwave; b * 64 < nl; b += nwaves) {
           const int ne = (int)min<int64_t>(64, nl - b * 64);
-          const uint64_t r = pull_small(G, A, pln, b * 64, ne, pp, p, valid, km, push, wflag, cnt,
-                                        deg, fin);
+          const uint64_t r = pull_small(G, A, pln, b * 64, ne, pp, p, valid, km, push, cnt, deg, fin);
           if (lane == 0) rln[b] = r;
         }
         // medium rows: one per wave, units of kMedPerWave rows per wave
@@ -677,19 +787,50 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
             __syncthreads();
             const uint32_t k = uni(sh.unit);
             if (k >= U) break;
-            for (int it = 0; it < kMedPerWave; ++it) {
-              const uint32_t i = k * VPU + (uint32_t)(it * NW + wave);
-              if (i >= nm) break;
-              const int32_t v = pmn[i];
-              const uint64_t vis = A.rec[v].vis, st = A.rec[v].st;
-              const uint64_t want = valid & ~vis;
-              const int dv = rp[v + 1] - rp[v];
-              uint64_t best = kUnvisited;
-              if (want) best = pull_edges(G.adj, A.rec, rp[v], rp[v + 1], pp, want, km, best);
-              if (settle(A, v, vis, st, dv, best, p, valid, cnt, deg, fin) && lane == 0)
-                aor64(rmn + (i >> 6), 1ull << (i & 63));
-              if (push && lane == 0) aand64(A.cand + (v >> 6), ~(1ull << (v & 63)));
+            // lane q < kMedPerWave holds row q of this wave's share; outcomes
+            // are written back after all of them are walked
+            const uint32_t iq = k * VPU + (uint32_t)(lane * NW + wave);
+            const bool okq = lane < kMedPerWave && iq < nm;
+            int32_t vq = 0;
+            int dq = 0, sq = 0;
+            uint64_t visq = 0, stq = 0, mnew = 0, mstb = 0;
+            if (okq) {
+              vq = pmn[iq];
+              sq = rp[vq];
+              dq = rp[vq + 1] - sq;
+              visq = A.vis[vq];
+              stq = A.rec[0][vq].st;
             }
+            for (int it = 0; it < kMedPerWave; ++it) {
+              if (k * VPU + (uint32_t)(it * NW + wave) >= nm) break;
+              const int64_t e0 = (int64_t)__builtin_amdgcn_readlane(sq, it);
+              const int64_t e1 = e0 + __builtin_amdgcn_readlane(dq, it);
+              const uint64_t want = valid & ~readlane64(visq, it);
+              uint64_t best = kUnvisited;
+              if (want) best = pull_edges(G.adj, A.rec[pp], e0, e1, pp, want, km, best);
+              const uint64_t newb = __ballot(best != kUnvisited);
+              const uint64_t stb = __ballot(best != kUnvisited && (best & 1));
+              if (lane == it) {
+                mnew = newb;
+                mstb = stb;
+              }
+            }
+            const bool got = okq && mnew != 0;
+            const bool full = got && (visq | mnew) == valid;
+            if (got) {
+              A.vis[vq] = visq | mnew;
+              A.rec[p][vq].nb = mnew;
+              if (mstb) {
+                A.rec[0][vq].st = stq | mstb;
+                A.rec[1][vq].st = stq | mstb;
+              }
+              if (full) aand64(A.unf + (vq >> 6), ~(1ull << (vq & 63)));
+              aor64(rmn + (iq >> 6), 1ull << (iq & 63));
+            }
+            if (okq && push) aand64(A.cand + (vq >> 6), ~(1ull << (vq & 63)));
+            cnt += (uint64_t)__popcll(__ballot(got));
+            deg += wave_sum_u64(got ? (uint64_t)dq : 0ull);
+            fin += wave_sum_u64(full ? (uint64_t)dq : 0ull);
           }
         }
         if (lane == 0 && cnt) {
@@ -723,12 +864,12 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
           const uint32_t part = hk - (uint32_t)uni(sh.heavy.y);
           const int64_t e0 = rp[v] + (int64_t)part * kMSplit;
           const int64_t e1 = min<int64_t>(rp[v + 1], e0 + kMSplit);
-          const uint64_t want = valid & ~A.rec[v].vis;
+          const uint64_t want = valid & ~A.vis[v];
           const int64_t seg = ((e1 - e0 + NW - 1) / NW + 63) / 64 * 64;
           const int64_t s0 = min<int64_t>(e1, e0 + (int64_t)wave * seg);
           const int64_t s1 = min<int64_t>(e1, s0 + seg);
           uint64_t best = kUnvisited;
-          if (want && s0 < s1) best = pull_edges(G.adj, A.rec, s0, s1, pp, want, km, best);
+          if (want && s0 < s1) best = pull_edges(G.adj, A.rec[pp], s0, s1, pp, want, km, best);
           if (best != kUnvisited) atomicMin((unsigned long long*)&sh.hbest[lane], (unsigned long long)best);
           __syncthreads();
           if (tid < 64 && sh.hbest[tid] != kUnvisited)
@@ -746,24 +887,19 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
       const uint32_t nheavy = uni(sh.nh);
       group_sync(A.bar, rank, nb);
 
-      // ---- phase 3: split rows take their minima (64 entries per wave)
+      // ---- phase 3: split rows take their minima (one wave per row)
       if (nheavy > 0) {
         uint64_t cnt = 0, deg = 0, fin = 0;
-        for (int64_t wd = gwave; wd * 64 < (int64_t)nheavy; wd += nwaves) {
-          const int ne = (int)min<int64_t>(64, (int64_t)nheavy - wd * 64);
-          uint64_t bits = 0;
-          for (int q = 0; q < ne; ++q) {
-            const int64_t h = wd * 64 + q;
-            const int32_t v = phn[h].x;
-            uint64_t* hs = A.hslot + (size_t)h * 64;
-            const uint64_t best = hs[lane];
-            if (best != kUnvisited) hs[lane] = kUnvisited;
-            const uint64_t vis = A.rec[v].vis, st = A.rec[v].st;
-            const int dv = rp[v + 1] - rp[v];
-            if (settle(A, v, vis, st, dv, best, p, valid, cnt, deg, fin)) bits |= 1ull << q;
-            if (push && lane == 0) aand64(A.cand + (v >> 6), ~(1ull << (v & 63)));
-          }
-          if (lane == 0) rhn[wd] = bits;
+        for (int64_t h = gwave; h < (int64_t)nheavy; h += nwaves) {
+          const int32_t v = phn[h].x;
+          uint64_t* hs = A.hslot + (size_t)h * 64;
+          const uint64_t best = hs[lane];
+          if (best != kUnvisited) hs[lane] = kUnvisited;
+          const uint64_t vis = A.vis[v], st = A.rec[0][v].st;
+          const int dv = rp[v + 1] - rp[v];
+          if (settle(A, v, vis, st, dv, best, p, valid, cnt, deg, fin) && lane == 0)
+            aor64(rhn + (h >> 6), 1ull << (h & 63));
+          if (push && lane == 0) aand64(A.cand + (v >> 6), ~(1ull << (v & 63)));
         }
         if (lane == 0) {
           if (cnt) {
@@ -802,7 +938,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
         uint64_t x = 0;
         if (e < G.m) {
           const uint2 uv = G.edges[e];
-          x = A.rec[uv.x].st ^ A.rec[uv.y & kVertexMask].st;
+          x = A.rec[0][uv.x].st ^ A.rec[0][uv.y & kVertexMask].st;
           if (uv.y >> 31) x = ~x;
         }
 #pragma unroll
@@ -822,7 +958,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
       for (int64_t i = gwave; i < nw; i += nwaves) {
         const int64_t v = i * 64 + lane;
         uint64_t cs = 0;
-        if (v < n) cs = A.rec[v].st ^ A.rec[G.comp[v]].st;
+        if (v < n) cs = A.rec[0][v].st ^ A.rec[0][G.comp[v]].st;
         uint64_t W = 0;
         for (int t = 0; t < 64; ++t) {
           const uint64_t b = __ballot((cs >> t) & 1);
@@ -885,7 +1021,9 @@ hipError_t launch_multi(fi_graph* g, const SweepArgs& sa, hipStream_t s) {
   a.insert = sa.insert;
   a.ntasks = g->mtasks;
   a.nbig = g->mnbig;
-  a.rec = (MRec*)(ws + L.mrec);
+  a.rec[0] = (MRec*)(ws + L.mrec);
+  a.rec[1] = a.rec[0] + g->dg.n;
+  a.vis = (uint64_t*)(a.rec[1] + g->dg.n);
   a.unf = (uint64_t*)(ws + L.gvis);
   a.cand = (uint64_t*)(ws + L.gsb);
   a.lstride = (int64_t)g->dg.n + 64;
