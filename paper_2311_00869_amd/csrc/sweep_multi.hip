@@ -43,18 +43,14 @@ namespace {
 constexpr int kStageM = 2048;      // LDS staging entries for light list appends
 constexpr int kPushCost = 4;       // push while kPushCost * frontier edges < unfinished edges
 constexpr int kSmall = 64;         // rows up to this many edges are pulled 64 vertices per wave
-constexpr int kMedPerWave = 4;     // medium rows per wave per unit
 constexpr int kMedChunk = 64;      // medium frontier rows per push unit
 constexpr int kPlanes = 8;         // bit-sliced counter planes (flushed every 255 edges)
 
-// Per-vertex state, one 16-byte record per level parity: the trees that
-// discovered the vertex at the last level of that parity, and the state bits
-// (kept equal in both records).  A pull gathers only the record of the
-// previous level's parity, half the bytes of one record holding both.
-struct __align__(16) MRec {
-  uint64_t nb;
-  uint64_t st;
-};
+// Per-vertex state in separate 8-byte words: the trees that discovered the
+// vertex at the last even / odd level, its state bits, the trees that have
+// visited it.  A pull gathers the previous parity's discovery word of every
+// neighbour (a 128 MB array at 16M vertices) and the state word only for
+// neighbours that hit some tree.
 
 // Control words; each group sits on its own 128-byte line.  r = level mod 4.
 //   F(r): the level's pull lists and frontier: small-row count, heavy
@@ -78,7 +74,8 @@ struct MArgs {
   uint64_t* tree_switches;
   int insert;
   int32_t ntasks, nbig;
-  MRec* rec[2];          // [parity][n]
+  uint64_t* nbw[2];      // [parity][n] trees that discovered the vertex at the last level
+  uint64_t* stw;         // [n] state bits
   uint64_t* vis;         // [n] trees that visited the vertex
   uint64_t* unf;        // [nwords] vertices with an edge not yet visited by every tree
   uint64_t* cand;       // [nwords] push candidates of the level
@@ -106,6 +103,8 @@ struct MS {
   int32_t q[kStageM];   // staging: small rows
   int32_t q2[kStageM];  // staging: medium rows
   uint32_t qn, qn2;
+  uint32_t bnext;       // next small-row batch of the block
+  uint32_t mnext;       // next medium row of the block
   uint32_t unit;
   int hidx;
   int2 heavy;
@@ -226,7 +225,8 @@ constexpr int kDenseHits = 8;
 // neighbour's key and the edge sign are folded in once per edge lane.  A
 // chunk with few hit edges is walked edge by edge with all lanes; a dense
 // one is transposed so that lane t walks only the edges that hit tree t.
-__device__ __forceinline__ uint64_t pull_edges(const uint32_t* adj, const MRec* rec, int64_t e0,
+__device__ __forceinline__ uint64_t pull_edges(const uint32_t* adj, const uint64_t* nbw,
+                                               const uint64_t* stw, int64_t e0,
                                                int64_t e1, int pp, uint64_t want, KeyMix km,
                                                uint64_t best) {
   const int lane = lane_id();
@@ -236,9 +236,9 @@ __device__ __forceinline__ uint64_t pull_edges(const uint32_t* adj, const MRec* 
     uint64_t F = 0, S = 0;
     if (e < e1) {
       const uint32_t a = adj[e];
-      const MRec* ru = rec + (a & kVertexMask);
-      F = ru->nb & want;
-      if (F) S = ru->st ^ ((a >> 31) ? ~0ull : 0ull);
+      const uint32_t u = a & kVertexMask;
+      F = nbw[u] & want;
+      if (F) S = stw[u] ^ ((a >> 31) ? ~0ull : 0ull);
       H = fmix32(a & kVertexMask);
     }
     uint64_t hits = __ballot(F != 0);
@@ -319,7 +319,7 @@ __device__ __forceinline__ void set_roots(uint64_t best, bool vlane, uint64_t va
   int dv = 0;
   if (leader) {
     dv = rp[r + 1] - rp[r];
-    A.rec[0][r].nb = mine;
+    A.nbw[0][r] = mine;
     A.vis[r] = mine;
     if (mine == valid) {
       aand64(A.unf + (r >> 6), ~(1ull << (r & 63)));
@@ -345,11 +345,8 @@ __device__ __forceinline__ bool settle(const MArgs& A, int32_t v, uint64_t vis, 
   const bool full = (vis | newb) == valid;
   if (lane_id() == 0) {
     A.vis[v] = vis | newb;
-    A.rec[p][v].nb = newb;
-    if (stb) {
-      A.rec[0][v].st = st | stb;
-      A.rec[1][v].st = st | stb;
-    }
+    A.nbw[p][v] = newb;
+    if (stb) A.stw[v] = st | stb;
     if (full) aand64(A.unf + (v >> 6), ~(1ull << (v & 63)));
   }
   if (full) fin += (uint64_t)dv;
@@ -390,7 +387,7 @@ __device__ __forceinline__ uint64_t pull_small(const DevGraph& G, const MArgs& A
     s = G.row_ptr[v];
     d = G.row_ptr[v + 1] - s;
     vis = A.vis[v];
-    st = A.rec[0][v].st;
+    st = A.stw[v];
   }
   const uint64_t want = valid & ~vis;
   int inc = d;
@@ -428,9 +425,9 @@ __device__ __forceinline__ uint64_t pull_small(const DevGraph& G, const MArgs& A
     uint64_t F = 0, S = 0;
     if (lane < total) {
       const uint32_t a = G.adj[(int64_t)sk + (eb + lane - ek)];
-      const MRec* ru = A.rec[pp] + (a & kVertexMask);
-      F = ru->nb & wk;
-      if (F) S = ru->st ^ ((a >> 31) ? ~0ull : 0ull);
+      const uint32_t u = a & kVertexMask;
+      F = A.nbw[pp][u] & wk;
+      if (F) S = A.stw[u] ^ ((a >> 31) ? ~0ull : 0ull);
       H = fmix32(a & kVertexMask);
     }
     uint64_t hits = __ballot(F != 0);
@@ -505,11 +502,8 @@ __device__ __forceinline__ uint64_t pull_small(const DevGraph& G, const MArgs& A
   const bool full = got && (vis | mnew) == valid;
   if (got) {
     A.vis[v] = vis | mnew;
-    A.rec[p][v].nb = mnew;
-    if (mstb) {
-      A.rec[0][v].st = st | mstb;
-      A.rec[1][v].st = st | mstb;
-    }
+    A.nbw[p][v] = mnew;
+    if (mstb) A.stw[v] = st | mstb;
     if (full) aand64(A.unf + (v >> 6), ~(1ull << (v & 63)));
   }
   if (ok && push) aand64(A.cand + (v >> 6), ~(1ull << (v & 63)));
@@ -540,11 +534,9 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
 
     // ---- reset: records, bitmaps, control words
     for (int64_t v = stid; v < n; v += sstride) {
-      MRec z;
-      z.nb = 0;
-      z.st = 0;
-      A.rec[0][v] = z;
-      A.rec[1][v] = z;
+      A.nbw[0][v] = 0;
+      A.nbw[1][v] = 0;
+      A.stw[v] = 0;
       A.vis[v] = 0;
     }
     for (int64_t i = stid; i < nw; i += sstride) {
@@ -675,7 +667,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
             if (u >= 0) {
               st = rp[u];
               d = rp[u + 1] - st;
-              bits = A.rec[pp][u].nb & valid;
+              bits = A.nbw[pp][u] & valid;
             }
             const int off = block_exclusive_scan<NT>(d, total, sh.scan);
             sh.off[tid] = off;
@@ -701,7 +693,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
               const uint32_t part = hk - (uint32_t)uni(sh.heavy.y);
               e0 = rp[u] + (int64_t)part * kMSplit;
               const int64_t e1 = min<int64_t>(rp[u + 1], e0 + kMSplit);
-              hbits = A.rec[pp][u].nb & valid;
+              hbits = A.nbw[pp][u] & valid;
               total = (int)(e1 - e0);
             }
           }
@@ -762,75 +754,56 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
         sh.cnt = 0;
         sh.deg = 0;
         sh.fin = 0;
+        sh.bnext = 0;
+        sh.mnext = 0;
       }
       __syncthreads();
       {
         uint64_t cnt = 0, deg = 0, fin = 0;
-        // small rows: 64 list entries per wave, whole bitmap words
+        // small rows: 64 list entries per wave, whole bitmap words; block b
+        // owns batches b, b + nb, ... and its waves draw them one at a time
         const int64_t nl = (int64_t)uni(sh.nl);
-        for (int64_t b = gwave; b * 64 < nl; b += nwaves) {
+        while (true) {
+          uint32_t i = 0;
+          if (lane == 0) i = atomicAdd(&sh.bnext, 1u);
+          const int64_t b = (int64_t)rank + (int64_t)uni((int)i) * nb;
+          if (b * 64 >= nl) break;
           const int ne = (int)min<int64_t>(64, nl - b * 64);
           const uint64_t r = pull_small(G, A, pln, b * 64, ne, pp, p, valid, km, push, cnt, deg, fin);
           if (lane == 0) rln[b] = r;
         }
-        // medium rows: one per wave, units of kMedPerWave rows per wave
+        // medium rows: block b owns rows b, b + nb, ...; its waves draw them
+        // one at a time and walk each with all lanes
         {
-          constexpr uint32_t VPU = kMedPerWave * NW;
           const uint32_t nm = uni(sh.nm);
-          const uint32_t U = (nm + VPU - 1) / VPU;
-          uint64_t* ticket = ctl + cTM(L & 3);
-          bool firstu = true;
           while (true) {
-            __syncthreads();
-            if (tid == 0) sh.unit = firstu ? rank : (U > nb ? nb + atomicAdd((uint32_t*)ticket, 1u) : U);
-            firstu = false;
-            __syncthreads();
-            const uint32_t k = uni(sh.unit);
-            if (k >= U) break;
-            // lane q < kMedPerWave holds row q of this wave's share; outcomes
-            // are written back after all of them are walked
-            const uint32_t iq = k * VPU + (uint32_t)(lane * NW + wave);
-            const bool okq = lane < kMedPerWave && iq < nm;
-            int32_t vq = 0;
-            int dq = 0, sq = 0;
-            uint64_t visq = 0, stq = 0, mnew = 0, mstb = 0;
-            if (okq) {
-              vq = pmn[iq];
-              sq = rp[vq];
-              dq = rp[vq + 1] - sq;
-              visq = A.vis[vq];
-              stq = A.rec[0][vq].st;
-            }
-            for (int it = 0; it < kMedPerWave; ++it) {
-              if (k * VPU + (uint32_t)(it * NW + wave) >= nm) break;
-              const int64_t e0 = (int64_t)__builtin_amdgcn_readlane(sq, it);
-              const int64_t e1 = e0 + __builtin_amdgcn_readlane(dq, it);
-              const uint64_t want = valid & ~readlane64(visq, it);
-              uint64_t best = kUnvisited;
-              if (want) best = pull_edges(G.adj, A.rec[pp], e0, e1, pp, want, km, best);
-              const uint64_t newb = __ballot(best != kUnvisited);
-              const uint64_t stb = __ballot(best != kUnvisited && (best & 1));
-              if (lane == it) {
-                mnew = newb;
-                mstb = stb;
+            uint32_t c = 0;
+            if (lane == 0) c = atomicAdd(&sh.mnext, 1u);
+            const int64_t i = (int64_t)rank + (int64_t)uni((int)c) * nb;
+            if (i >= (int64_t)nm) break;
+            const int32_t v = pmn[i];
+            const int64_t e0 = rp[v], e1 = rp[v + 1];
+            const uint64_t visq = A.vis[v], stq = A.stw[v];
+            const uint64_t want = valid & ~visq;
+            uint64_t best = kUnvisited;
+            if (want) best = pull_edges(G.adj, A.nbw[pp], A.stw, e0, e1, pp, want, km, best);
+            const uint64_t mnew = __ballot(best != kUnvisited);
+            const uint64_t mstb = __ballot(best != kUnvisited && (best & 1));
+            const int dq = (int)(e1 - e0);
+            if (mnew) {
+              const bool full = (visq | mnew) == valid;
+              if (lane == 0) {
+                A.vis[v] = visq | mnew;
+                A.nbw[p][v] = mnew;
+                if (mstb) A.stw[v] = stq | mstb;
+                if (full) aand64(A.unf + (v >> 6), ~(1ull << (v & 63)));
+                aor64(rmn + (i >> 6), 1ull << (i & 63));
               }
+              cnt += 1;
+              deg += (uint64_t)dq;
+              if (full) fin += (uint64_t)dq;
             }
-            const bool got = okq && mnew != 0;
-            const bool full = got && (visq | mnew) == valid;
-            if (got) {
-              A.vis[vq] = visq | mnew;
-              A.rec[p][vq].nb = mnew;
-              if (mstb) {
-                A.rec[0][vq].st = stq | mstb;
-                A.rec[1][vq].st = stq | mstb;
-              }
-              if (full) aand64(A.unf + (vq >> 6), ~(1ull << (vq & 63)));
-              aor64(rmn + (iq >> 6), 1ull << (iq & 63));
-            }
-            if (okq && push) aand64(A.cand + (vq >> 6), ~(1ull << (vq & 63)));
-            cnt += (uint64_t)__popcll(__ballot(got));
-            deg += wave_sum_u64(got ? (uint64_t)dq : 0ull);
-            fin += wave_sum_u64(full ? (uint64_t)dq : 0ull);
+            if (push && lane == 0) aand64(A.cand + (v >> 6), ~(1ull << (v & 63)));
           }
         }
         if (lane == 0 && cnt) {
@@ -869,7 +842,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
           const int64_t s0 = min<int64_t>(e1, e0 + (int64_t)wave * seg);
           const int64_t s1 = min<int64_t>(e1, s0 + seg);
           uint64_t best = kUnvisited;
-          if (want && s0 < s1) best = pull_edges(G.adj, A.rec[pp], s0, s1, pp, want, km, best);
+          if (want && s0 < s1) best = pull_edges(G.adj, A.nbw[pp], A.stw, s0, s1, pp, want, km, best);
           if (best != kUnvisited) atomicMin((unsigned long long*)&sh.hbest[lane], (unsigned long long)best);
           __syncthreads();
           if (tid < 64 && sh.hbest[tid] != kUnvisited)
@@ -895,7 +868,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
           uint64_t* hs = A.hslot + (size_t)h * 64;
           const uint64_t best = hs[lane];
           if (best != kUnvisited) hs[lane] = kUnvisited;
-          const uint64_t vis = A.vis[v], st = A.rec[0][v].st;
+          const uint64_t vis = A.vis[v], st = A.stw[v];
           const int dv = rp[v + 1] - rp[v];
           if (settle(A, v, vis, st, dv, best, p, valid, cnt, deg, fin) && lane == 0)
             aor64(rhn + (h >> 6), 1ull << (h & 63));
@@ -938,7 +911,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
         uint64_t x = 0;
         if (e < G.m) {
           const uint2 uv = G.edges[e];
-          x = A.rec[0][uv.x].st ^ A.rec[0][uv.y & kVertexMask].st;
+          x = A.stw[uv.x] ^ A.stw[uv.y & kVertexMask];
           if (uv.y >> 31) x = ~x;
         }
 #pragma unroll
@@ -958,7 +931,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
       for (int64_t i = gwave; i < nw; i += nwaves) {
         const int64_t v = i * 64 + lane;
         uint64_t cs = 0;
-        if (v < n) cs = A.rec[0][v].st ^ A.rec[0][G.comp[v]].st;
+        if (v < n) cs = A.stw[v] ^ A.stw[G.comp[v]];
         uint64_t W = 0;
         for (int t = 0; t < 64; ++t) {
           const uint64_t b = __ballot((cs >> t) & 1);
@@ -1021,9 +994,10 @@ hipError_t launch_multi(fi_graph* g, const SweepArgs& sa, hipStream_t s) {
   a.insert = sa.insert;
   a.ntasks = g->mtasks;
   a.nbig = g->mnbig;
-  a.rec[0] = (MRec*)(ws + L.mrec);
-  a.rec[1] = a.rec[0] + g->dg.n;
-  a.vis = (uint64_t*)(a.rec[1] + g->dg.n);
+  a.nbw[0] = (uint64_t*)(ws + L.mrec);
+  a.nbw[1] = a.nbw[0] + g->dg.n;
+  a.stw = a.nbw[1] + g->dg.n;
+  a.vis = a.stw + g->dg.n;
   a.unf = (uint64_t*)(ws + L.gvis);
   a.cand = (uint64_t*)(ws + L.gsb);
   a.lstride = (int64_t)g->dg.n + 64;
