@@ -42,7 +42,7 @@ namespace {
 
 constexpr int kStageM = 2048;      // LDS staging entries for light list appends
 constexpr int kPushCost = 4;       // push while kPushCost * frontier edges < unfinished edges
-constexpr int kSmall = 64;         // rows up to this many edges are pulled 64 vertices per wave
+constexpr int kSmall = 32;         // rows up to this many edges are pulled 64 vertices per wave
 constexpr int kMedChunk = 64;      // medium frontier rows per push unit
 constexpr int kPlanes = 8;         // bit-sliced counter planes (flushed every 255 edges)
 
@@ -197,34 +197,11 @@ __device__ __forceinline__ void mlist_global(bool in, int32_t v, int dv, int32_t
   }
 }
 
-// 64x64 bit transpose across the wave: afterwards bit j of lane t is what
-// bit t of lane j was.  Six exchange stages; stage s swaps bit s of the row
-// (lane) index with bit s of the column (bit) index.
-__device__ __forceinline__ uint64_t transpose64(uint64_t x) {
-  const int lane = lane_id();
-  const uint64_t masks[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
-                             0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    const int sft = 32 >> k;
-    const uint64_t m = masks[k];
-    const uint32_t ylo = (uint32_t)__shfl_xor((int)(uint32_t)x, sft);
-    const uint32_t yhi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), sft);
-    const uint64_t y = ((uint64_t)yhi << 32) | ylo;
-    x = (lane & sft) ? ((x & ~m) | ((y & ~m) >> sft)) : ((x & m) | ((y & m) << sft));
-  }
-  return x;
-}
-
-// Chunks with at least this many hit edges take the transposed walk.
-constexpr int kDenseHits = 8;
-
 // Lane t: minimum over the edges [e0, e1) of the candidate (key << 1 |
 // state bit) of every neighbour discovered at the previous level of tree t
 // (parity pp) in a tree of `want`.  The tree-independent part of each
-// neighbour's key and the edge sign are folded in once per edge lane.  A
-// chunk with few hit edges is walked edge by edge with all lanes; a dense
-// one is transposed so that lane t walks only the edges that hit tree t.
+// neighbour's key and the edge sign are folded in once per edge lane; the
+// edges that hit some tree are then walked one by one with all lanes.
 __device__ __forceinline__ uint64_t pull_edges(const uint32_t* adj, const uint64_t* nbw,
                                                const uint64_t* stw, int64_t e0,
                                                int64_t e1, int pp, uint64_t want, KeyMix km,
@@ -242,22 +219,6 @@ __device__ __forceinline__ uint64_t pull_edges(const uint32_t* adj, const uint64
       H = fmix32(a & kVertexMask);
     }
     uint64_t hits = __ballot(F != 0);
-    if (__popcll(hits) >= kDenseHits) {
-      uint64_t C = transpose64(F);   // bit j: edge lane j hits this lane's tree
-      const uint64_t SC = transpose64(S);
-      int iters = __popcll(C);
-#pragma unroll
-      for (int d = 32; d > 0; d >>= 1) iters = max(iters, __shfl_xor(iters, d));
-      for (int it = 0; it < iters; ++it) {
-        const bool on = C != 0;
-        const int j = on ? __builtin_ctzll(C) : 0;
-        C &= C - 1;
-        const uint32_t Hj = (uint32_t)__shfl((int)H, j);
-        const uint64_t c2 = ((uint64_t)vkey_of(km, Hj) << 1) | ((SC >> j) & 1);
-        if (on && c2 < best) best = c2;
-      }
-      continue;
-    }
     while (hits) {
       const int j = __builtin_ctzll(hits);
       hits &= hits - 1;
@@ -431,49 +392,6 @@ __device__ __forceinline__ uint64_t pull_small(const DevGraph& G, const MArgs& A
       H = fmix32(a & kVertexMask);
     }
     uint64_t hits = __ballot(F != 0);
-    if (__popcll(hits) >= kDenseHits) {
-      // dense round: lane t walks the edges that hit tree t; per row it keeps
-      // whether tree t reached the vertex (found bit) and with which state
-      uint64_t C = transpose64(F);
-      const uint64_t SC = transpose64(S);
-      int iters = __popcll(C);
-#pragma unroll
-      for (int dd = 32; dd > 0; dd >>= 1) iters = max(iters, __shfl_xor(iters, dd));
-      uint64_t found = 0, sbits = 0, best = kUnvisited;
-      int cur = -1;
-      for (int it = 0; it < iters; ++it) {
-        const bool on = C != 0;
-        const int j = on ? __builtin_ctzll(C) : 0;
-        C &= C - 1;
-        const uint32_t Hj = (uint32_t)__shfl((int)H, j);
-        const int seg = (int)__popcll(starts & ((2ull << j) - 1)) - 1;
-        const uint64_t c2 = ((uint64_t)vkey_of(km, Hj) << 1) | ((SC >> j) & 1);
-        if (on) {
-          if (seg != cur) {
-            if (cur >= 0) {
-              found |= 1ull << cur;
-              sbits |= (best & 1) << cur;
-            }
-            cur = seg;
-            best = c2;
-          } else if (c2 < best) {
-            best = c2;
-          }
-        }
-      }
-      if (cur >= 0) {
-        found |= 1ull << cur;
-        sbits |= (best & 1) << cur;
-      }
-      uint64_t any = wave_or64(found);
-      while (any) {
-        const int q = __builtin_ctzll(any);
-        any &= any - 1;
-        keep(k0 + q, __ballot((found >> q) & 1), __ballot((found >> q) & (sbits >> q) & 1));
-      }
-      k0 = k1;
-      continue;
-    }
     uint64_t best = kUnvisited;
     int cur = -1;
     while (hits) {
