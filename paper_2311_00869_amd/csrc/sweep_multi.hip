@@ -35,10 +35,13 @@
 
 #include "fi_internal.h"
 #include "fi_prims.h"
+#include "fi_multi.h"
 
 namespace fi {
 
 namespace {
+
+using namespace mt;
 
 constexpr int kStageM = 2048;      // LDS staging entries for light list appends
 constexpr int kPushCost = 4;       // push while kPushCost * frontier edges < unfinished edges
@@ -74,11 +77,7 @@ struct MArgs {
   uint64_t* tree_switches;
   int insert;
   int32_t ntasks, nbig;
-  uint64_t* nbw[2];      // [parity][n] trees that discovered the vertex at the last level
-  uint64_t* stw;         // [n] state bits
-  uint64_t* vis;         // [n] trees that visited the vertex
-  uint64_t* unf;        // [nwords] vertices with an edge not yet visited by every tree
-  uint64_t* cand;       // [nwords] push candidates of the level
+  MState S;              // per-vertex words and bitmaps of the pass
   int32_t* pl;          // [2][lstride] pull lists of rows up to kSmall (by level parity)
   int32_t* pm;          // [2][lstride] pull lists of rows up to kMSplit
   int2* ph;             // [2][hstride] split rows (vertex, first unit); entry h owns hslot row h
@@ -114,24 +113,6 @@ struct MS {
   uint64_t hbest[64];
   uint64_t tacc[3][64];
 };
-
-__device__ __forceinline__ uint64_t amin64(uint64_t* p, uint64_t v) {
-  return atomicMin((unsigned long long*)p, (unsigned long long)v);
-}
-__device__ __forceinline__ uint64_t aor64(uint64_t* p, uint64_t v) {
-  return atomicOr((unsigned long long*)p, (unsigned long long)v);
-}
-__device__ __forceinline__ void aand64(uint64_t* p, uint64_t v) {
-  atomicAnd((unsigned long long*)p, (unsigned long long)v);
-}
-__device__ __forceinline__ void aadd64(uint64_t* p, uint64_t v) {
-  atomicAdd((unsigned long long*)p, (unsigned long long)v);
-}
-__device__ __forceinline__ uint64_t readlane64(uint64_t x, int j) {
-  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)x, j);
-  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(x >> 32), j);
-  return ((uint64_t)hi << 32) | lo;
-}
 
 // Move the LDS staging list into a global list (one reservation per block).
 template <int NT>
@@ -197,62 +178,6 @@ __device__ __forceinline__ void mlist_global(bool in, int32_t v, int dv, int32_t
   }
 }
 
-// Lane t: minimum over the edges [e0, e1) of the candidate (key << 1 |
-// state bit) of every neighbour discovered at the previous level of tree t
-// (parity pp) in a tree of `want`.  The tree-independent part of each
-// neighbour's key and the edge sign are folded in once per edge lane; the
-// edges that hit some tree are then walked one by one with all lanes.
-__device__ __forceinline__ uint64_t pull_edges(const uint32_t* adj, const uint64_t* nbw,
-                                               const uint64_t* stw, int64_t e0,
-                                               int64_t e1, int pp, uint64_t want, KeyMix km,
-                                               uint64_t best) {
-  const int lane = lane_id();
-  for (int64_t c = e0; c < e1; c += 64) {
-    const int64_t e = c + lane;
-    uint32_t H = 0;
-    uint64_t F = 0, S = 0;
-    if (e < e1) {
-      const uint32_t a = adj[e];
-      const uint32_t u = a & kVertexMask;
-      F = nbw[u] & want;
-      if (F) S = stw[u] ^ ((a >> 31) ? ~0ull : 0ull);
-      H = fmix32(a & kVertexMask);
-    }
-    uint64_t hits = __ballot(F != 0);
-    while (hits) {
-      const int j = __builtin_ctzll(hits);
-      hits &= hits - 1;
-      const uint32_t Hj = __builtin_amdgcn_readlane(H, j);
-      const uint64_t Fj = readlane64(F, j);
-      const uint64_t Sj = readlane64(S, j);
-      if ((Fj >> lane) & 1) {
-        const uint64_t c2 = ((uint64_t)vkey_of(km, Hj) << 1) | ((Sj >> lane) & 1);
-        best = c2 < best ? c2 : best;
-      }
-    }
-  }
-  return best;
-}
-
-// Lane t: the minimum root candidate of tree t over cverts[b, e).
-__device__ __forceinline__ uint64_t comp_min(const int32_t* cverts, int32_t b, int32_t e, KeyMix km) {
-  const int lane = lane_id();
-  uint64_t best = kUnvisited;
-  for (int32_t c = b; c < e; c += 64) {
-    const int32_t i = c + lane;
-    const int32_t mine = i < e ? cverts[i] : 0;
-    const int cnt = min(64, e - c);
-    const uint32_t hm = fmix32((uint32_t)mine);
-    for (int j = 0; j < cnt; ++j) {
-      const uint32_t v = (uint32_t)__builtin_amdgcn_readlane(mine, j);
-      const uint32_t h = (uint32_t)__builtin_amdgcn_readlane((int)hm, j);
-      const uint64_t k = root_candidate(vkey_of(km, h), v);
-      best = k < best ? k : best;
-    }
-  }
-  return best;
-}
-
 // Roots of one component (the wave owns it): lanes are grouped by root
 // vertex; each root's record gets the trees it roots, and it enters the
 // level-0 lists.  cnt / deg gather the wave's roots and their degrees, fin
@@ -280,156 +205,16 @@ __device__ __forceinline__ void set_roots(uint64_t best, bool vlane, uint64_t va
   int dv = 0;
   if (leader) {
     dv = rp[r + 1] - rp[r];
-    A.nbw[0][r] = mine;
-    A.vis[r] = mine;
+    A.S.nbw[0][r] = mine;
+    A.S.vis[r] = mine;
     if (mine == valid) {
-      aand64(A.unf + (r >> 6), ~(1ull << (r & 63)));
+      aand64(A.S.unf + (r >> 6), ~(1ull << (r & 63)));
       fin += (uint64_t)dv;
     }
   }
   mlist_global(leader, (int32_t)r, dv, A.pl, A.pm, A.ph, A.ctl + cF(0));
   cnt += (uint64_t)__popcll(__ballot(leader));
   deg += wave_sum_u64(leader ? (uint64_t)dv : 0ull);
-}
-
-__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
-
-// Lane t: the write-back of vertex v once its trees of this level are
-// decided (best: lane t's minimum candidate, kUnvisited if none).  One lane
-// stores; every lane gets the reached / finished bookkeeping.
-__device__ __forceinline__ bool settle(const MArgs& A, int32_t v, uint64_t vis, uint64_t st, int dv,
-                                       uint64_t best, int p, uint64_t valid, uint64_t& cnt,
-                                       uint64_t& deg, uint64_t& fin) {
-  const uint64_t newb = __ballot(best != kUnvisited);
-  if (!newb) return false;
-  const uint64_t stb = __ballot(best != kUnvisited && (best & 1));
-  const bool full = (vis | newb) == valid;
-  if (lane_id() == 0) {
-    A.vis[v] = vis | newb;
-    A.nbw[p][v] = newb;
-    if (stb) A.stw[v] = st | stb;
-    if (full) aand64(A.unf + (v >> 6), ~(1ull << (v & 63)));
-  }
-  if (full) fin += (uint64_t)dv;
-  cnt += 1;
-  deg += (uint64_t)dv;
-  return true;
-}
-
-__device__ __forceinline__ uint64_t wave_or64(uint64_t x) {
-#pragma unroll
-  for (int dd = 32; dd > 0; dd >>= 1) {
-    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, dd);
-    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), dd);
-    x |= ((uint64_t)hi << 32) | lo;
-  }
-  return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32)) << 32) |
-         (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
-}
-
-// One wave pulls the small-row list entries i0 .. i0 + ne - 1 (ne <= 64;
-// lane k holds entry i0 + k; every row has at most kSmall edges and at least
-// one).  Rows are walked in rounds of at most 64 edges, as many whole rows as
-// fit, all loads of a round in flight together.  Each row's outcome (trees
-// that reached the vertex, their state bits) stays in its lane until the
-// batch is walked, then every vertex is written back at once, so no store
-// is waited for inside the walk.  Returns the entries some tree reached.
-__device__ __forceinline__ uint64_t pull_small(const DevGraph& G, const MArgs& A, const int32_t* list,
-                                               int64_t i0, int ne, int pp, int p, uint64_t valid,
-                                               KeyMix km, bool push, uint64_t& cnt, uint64_t& deg,
-                                               uint64_t& fin) {
-  const int lane = lane_id();
-  const bool ok = lane < ne;
-  int32_t v = 0;
-  int s = 0, d = 0;
-  uint64_t vis = 0, st = 0;
-  if (ok) {
-    v = list[i0 + lane];
-    s = G.row_ptr[v];
-    d = G.row_ptr[v + 1] - s;
-    vis = A.vis[v];
-    st = A.stw[v];
-  }
-  const uint64_t want = valid & ~vis;
-  int inc = d;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(inc, o);
-    if (lane >= o) inc += y;
-  }
-  const int excl = inc - d;
-  uint64_t mnew = 0, mstb = 0;  // outcome of this lane's row
-  auto keep = [&](int k, uint64_t newb, uint64_t stb) {
-    if (lane == k) {
-      mnew = newb;
-      mstb = stb;
-    }
-  };
-  int k0 = 0;
-  while (k0 < ne) {
-    const int eb = uni(__shfl(excl, k0));
-    const bool inr = ok && lane >= k0 && inc - eb <= 64;
-    const uint64_t fit = __ballot(inr);
-    const int k1 = k0 + (int)__popcll(fit);  // >= k0 + 1: every row fits a round
-    const int total = uni(__shfl(inc, k1 - 1)) - eb;
-    // the rows' starts: 0 and every row end but the last
-    const int e = inc - eb;
-    const uint64_t starts = 1ull | wave_or64(inr && e < total ? (1ull << e) : 0ull);
-    const int r = (int)__popcll(starts & ((2ull << lane) - 1));
-    const int kj = k0 + r - 1;
-    const int sk = __shfl(s, kj);
-    const int ek = __shfl(excl, kj);
-    const uint32_t wlo = (uint32_t)__shfl((int)(uint32_t)want, kj);
-    const uint32_t whi = (uint32_t)__shfl((int)(uint32_t)(want >> 32), kj);
-    const uint64_t wk = ((uint64_t)whi << 32) | wlo;
-    uint32_t H = 0;
-    uint64_t F = 0, S = 0;
-    if (lane < total) {
-      const uint32_t a = G.adj[(int64_t)sk + (eb + lane - ek)];
-      const uint32_t u = a & kVertexMask;
-      F = A.nbw[pp][u] & wk;
-      if (F) S = A.stw[u] ^ ((a >> 31) ? ~0ull : 0ull);
-      H = fmix32(a & kVertexMask);
-    }
-    uint64_t hits = __ballot(F != 0);
-    uint64_t best = kUnvisited;
-    int cur = -1;
-    while (hits) {
-      const int jj = __builtin_ctzll(hits);
-      hits &= hits - 1;
-      const int kk = __builtin_amdgcn_readlane(kj, jj);
-      if (kk != cur) {
-        if (cur >= 0)
-          keep(cur, __ballot(best != kUnvisited), __ballot(best != kUnvisited && (best & 1)));
-        best = kUnvisited;
-        cur = kk;
-      }
-      const uint32_t Hj = __builtin_amdgcn_readlane(H, jj);
-      const uint64_t Fj = readlane64(F, jj);
-      const uint64_t Sj = readlane64(S, jj);
-      if ((Fj >> lane) & 1) {
-        const uint64_t c2 = ((uint64_t)vkey_of(km, Hj) << 1) | ((Sj >> lane) & 1);
-        best = c2 < best ? c2 : best;
-      }
-    }
-    if (cur >= 0) keep(cur, __ballot(best != kUnvisited), __ballot(best != kUnvisited && (best & 1)));
-    k0 = k1;
-  }
-  // write back every reached vertex of the batch
-  const bool got = ok && mnew != 0;
-  const bool full = got && (vis | mnew) == valid;
-  if (got) {
-    A.vis[v] = vis | mnew;
-    A.nbw[p][v] = mnew;
-    if (mstb) A.stw[v] = st | mstb;
-    if (full) aand64(A.unf + (v >> 6), ~(1ull << (v & 63)));
-  }
-  if (ok && push) aand64(A.cand + (v >> 6), ~(1ull << (v & 63)));
-  const uint64_t reached = __ballot(got);
-  cnt += (uint64_t)__popcll(reached);
-  deg += wave_sum_u64(got ? (uint64_t)d : 0ull);
-  fin += wave_sum_u64(full ? (uint64_t)d : 0ull);
-  return reached;
 }
 
 template <int NT>
@@ -452,14 +237,14 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
 
     // ---- reset: records, bitmaps, control words
     for (int64_t v = stid; v < n; v += sstride) {
-      A.nbw[0][v] = 0;
-      A.nbw[1][v] = 0;
-      A.stw[v] = 0;
-      A.vis[v] = 0;
+      A.S.nbw[0][v] = 0;
+      A.S.nbw[1][v] = 0;
+      A.S.stw[v] = 0;
+      A.S.vis[v] = 0;
     }
     for (int64_t i = stid; i < nw; i += sstride) {
-      A.unf[i] = G.word_mask[i];
-      A.cand[i] = 0;
+      A.S.unf[i] = G.word_mask[i];
+      A.S.cand[i] = 0;
     }
     if (rank == 0)
       for (int i = tid; i < kMCtlWords; i += NT) ctl[i] = i == cUNF ? (uint64_t)G.nnz : 0ull;
@@ -585,7 +370,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
             if (u >= 0) {
               st = rp[u];
               d = rp[u + 1] - st;
-              bits = A.nbw[pp][u] & valid;
+              bits = A.S.nbw[pp][u] & valid;
             }
             const int off = block_exclusive_scan<NT>(d, total, sh.scan);
             sh.off[tid] = off;
@@ -611,7 +396,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
               const uint32_t part = hk - (uint32_t)uni(sh.heavy.y);
               e0 = rp[u] + (int64_t)part * kMSplit;
               const int64_t e1 = min<int64_t>(rp[u + 1], e0 + kMSplit);
-              hbits = A.nbw[pp][u] & valid;
+              hbits = A.S.nbw[pp][u] & valid;
               total = (int)(e1 - e0);
             }
           }
@@ -632,9 +417,9 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
                 bits = hbits;
               }
               v = (int32_t)(a & kVertexMask);
-              if (bits & ~A.vis[v]) {
+              if (bits & ~A.S.vis[v]) {
                 const uint64_t bit = 1ull << (v & 63);
-                if (!(aor64(A.cand + (v >> 6), bit) & bit)) {
+                if (!(aor64(A.S.cand + (v >> 6), bit) & bit)) {
                   first = true;
                   dv = rp[v + 1] - rp[v];
                 }
@@ -650,7 +435,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
         // every vertex some tree has not visited yet
         for (int64_t c0 = (int64_t)rank * NW; c0 < nw; c0 += (int64_t)nb * NW) {
           const int64_t w = c0 + wave;
-          const uint64_t bits = w < nw ? A.unf[w] : 0ull;
+          const uint64_t bits = w < nw ? A.S.unf[w] : 0ull;
           const bool in = (bits >> lane) & 1;
           const int32_t v = (int32_t)(w * 64 + lane);
           const int dv = in ? rp[v + 1] - rp[v] : 0;
@@ -687,7 +472,8 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
           const int64_t b = (int64_t)rank + (int64_t)uni((int)i) * nb;
           if (b * 64 >= nl) break;
           const int ne = (int)min<int64_t>(64, nl - b * 64);
-          const uint64_t r = pull_small(G, A, pln, b * 64, ne, pp, p, valid, km, push, cnt, deg, fin);
+          const uint64_t r = pull_small(G, A.S, b * 64 + lane < nl ? pln[b * 64 + lane] : 0, ne, pp, p, valid,
+                                        km, push, cnt, deg, fin);
           if (lane == 0) rln[b] = r;
         }
         // medium rows: block b owns rows b, b + nb, ...; its waves draw them
@@ -701,27 +487,27 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
             if (i >= (int64_t)nm) break;
             const int32_t v = pmn[i];
             const int64_t e0 = rp[v], e1 = rp[v + 1];
-            const uint64_t visq = A.vis[v], stq = A.stw[v];
+            const uint64_t visq = A.S.vis[v], stq = A.S.stw[v];
             const uint64_t want = valid & ~visq;
             uint64_t best = kUnvisited;
-            if (want) best = pull_edges(G.adj, A.nbw[pp], A.stw, e0, e1, pp, want, km, best);
+            if (want) best = pull_edges(G.adj, A.S.nbw[pp], A.S.stw, e0, e1, pp, want, km, best);
             const uint64_t mnew = __ballot(best != kUnvisited);
             const uint64_t mstb = __ballot(best != kUnvisited && (best & 1));
             const int dq = (int)(e1 - e0);
             if (mnew) {
               const bool full = (visq | mnew) == valid;
               if (lane == 0) {
-                A.vis[v] = visq | mnew;
-                A.nbw[p][v] = mnew;
-                if (mstb) A.stw[v] = stq | mstb;
-                if (full) aand64(A.unf + (v >> 6), ~(1ull << (v & 63)));
+                A.S.vis[v] = visq | mnew;
+                A.S.nbw[p][v] = mnew;
+                if (mstb) A.S.stw[v] = stq | mstb;
+                if (full) aand64(A.S.unf + (v >> 6), ~(1ull << (v & 63)));
                 aor64(rmn + (i >> 6), 1ull << (i & 63));
               }
               cnt += 1;
               deg += (uint64_t)dq;
               if (full) fin += (uint64_t)dq;
             }
-            if (push && lane == 0) aand64(A.cand + (v >> 6), ~(1ull << (v & 63)));
+            if (push && lane == 0) aand64(A.S.cand + (v >> 6), ~(1ull << (v & 63)));
           }
         }
         if (lane == 0 && cnt) {
@@ -755,12 +541,12 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
           const uint32_t part = hk - (uint32_t)uni(sh.heavy.y);
           const int64_t e0 = rp[v] + (int64_t)part * kMSplit;
           const int64_t e1 = min<int64_t>(rp[v + 1], e0 + kMSplit);
-          const uint64_t want = valid & ~A.vis[v];
+          const uint64_t want = valid & ~A.S.vis[v];
           const int64_t seg = ((e1 - e0 + NW - 1) / NW + 63) / 64 * 64;
           const int64_t s0 = min<int64_t>(e1, e0 + (int64_t)wave * seg);
           const int64_t s1 = min<int64_t>(e1, s0 + seg);
           uint64_t best = kUnvisited;
-          if (want && s0 < s1) best = pull_edges(G.adj, A.nbw[pp], A.stw, s0, s1, pp, want, km, best);
+          if (want && s0 < s1) best = pull_edges(G.adj, A.S.nbw[pp], A.S.stw, s0, s1, pp, want, km, best);
           if (best != kUnvisited) atomicMin((unsigned long long*)&sh.hbest[lane], (unsigned long long)best);
           __syncthreads();
           if (tid < 64 && sh.hbest[tid] != kUnvisited)
@@ -786,11 +572,11 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
           uint64_t* hs = A.hslot + (size_t)h * 64;
           const uint64_t best = hs[lane];
           if (best != kUnvisited) hs[lane] = kUnvisited;
-          const uint64_t vis = A.vis[v], st = A.stw[v];
+          const uint64_t vis = A.S.vis[v], st = A.S.stw[v];
           const int dv = rp[v + 1] - rp[v];
-          if (settle(A, v, vis, st, dv, best, p, valid, cnt, deg, fin) && lane == 0)
+          if (settle(A.S, v, vis, st, dv, best, p, valid, cnt, deg, fin) && lane == 0)
             aor64(rhn + (h >> 6), 1ull << (h & 63));
-          if (push && lane == 0) aand64(A.cand + (v >> 6), ~(1ull << (v & 63)));
+          if (push && lane == 0) aand64(A.S.cand + (v >> 6), ~(1ull << (v & 63)));
         }
         if (lane == 0) {
           if (cnt) {
@@ -829,7 +615,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
         uint64_t x = 0;
         if (e < G.m) {
           const uint2 uv = G.edges[e];
-          x = A.stw[uv.x] ^ A.stw[uv.y & kVertexMask];
+          x = A.S.stw[uv.x] ^ A.S.stw[uv.y & kVertexMask];
           if (uv.y >> 31) x = ~x;
         }
 #pragma unroll
@@ -849,7 +635,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
       for (int64_t i = gwave; i < nw; i += nwaves) {
         const int64_t v = i * 64 + lane;
         uint64_t cs = 0;
-        if (v < n) cs = A.stw[v] ^ A.stw[G.comp[v]];
+        if (v < n) cs = A.S.stw[v] ^ A.S.stw[G.comp[v]];
         uint64_t W = 0;
         for (int t = 0; t < 64; ++t) {
           const uint64_t b = __ballot((cs >> t) & 1);
@@ -912,12 +698,12 @@ hipError_t launch_multi(fi_graph* g, const SweepArgs& sa, hipStream_t s) {
   a.insert = sa.insert;
   a.ntasks = g->mtasks;
   a.nbig = g->mnbig;
-  a.nbw[0] = (uint64_t*)(ws + L.mrec);
-  a.nbw[1] = a.nbw[0] + g->dg.n;
-  a.stw = a.nbw[1] + g->dg.n;
-  a.vis = a.stw + g->dg.n;
-  a.unf = (uint64_t*)(ws + L.gvis);
-  a.cand = (uint64_t*)(ws + L.gsb);
+  a.S.nbw[0] = (uint64_t*)(ws + L.mrec);
+  a.S.nbw[1] = a.S.nbw[0] + g->dg.n;
+  a.S.stw = a.S.nbw[1] + g->dg.n;
+  a.S.vis = a.S.stw + g->dg.n;
+  a.S.unf = (uint64_t*)(ws + L.gvis);
+  a.S.cand = (uint64_t*)(ws + L.gsb);
   a.lstride = (int64_t)g->dg.n + 64;
   a.hstride = (int64_t)L.hcap + 64;
   a.rlstride = a.lstride / 64 + 2;
