@@ -16,6 +16,7 @@
 #include "fi_internal.h"
 #include "fi_prims.h"
 #include "fi_wg.h"
+#include "fi_multi.h"
 
 namespace fi {
 
@@ -40,12 +41,19 @@ struct BatchGraph {
   int32_t n, nwords;
   int64_t nnz, m;
   int64_t vo, no, me, ro;  // first vertex, CSR entry, edge, row_ptr slot
+  int32_t ncomp, cs;       // components with an edge; first one's slot among all graphs'
 };
+
+constexpr int kRootRows = 64;  // components whose roots one pass of the multi-tree sweep finds
 
 struct BatchLayout {
   size_t meta, offs, row_ptr, adj, edges, comp, ustart, eoff, tiles, gctl, clouds, ctl, small, large,
       slots;
   size_t slot_stride, nslots;
+  // multi-tree sweep: component index per vertex, graphs largest first, and
+  // per-workgroup slices (four words per vertex, an unfinished bitmap, root
+  // minima of kRootRows components)
+  size_t cidx, order, mslots, mslot_stride, nmslots;
   size_t total;
 };
 
@@ -57,11 +65,13 @@ struct BatchInfo {
   int32_t n_max_small, n_max_large;
   int32_t n_small, n_large;
   int per_cu[3][2];  // [block 256/512/1024][in LDS, in workspace]
+  int mt_per_cu[3];  // multi-tree sweep, per block size
+  int32_t n_max;
   BatchLayout L;
 };
 
 BatchLayout batch_layout(int32_t G, int64_t n_total, int64_t nnz_total, int32_t n_max_large,
-                         uint64_t tsize) {
+                         int32_t n_max, uint64_t tsize) {
   BatchLayout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -89,6 +99,12 @@ BatchLayout batch_layout(int32_t G, int64_t n_total, int64_t nnz_total, int32_t 
                  ? std::min<size_t>(2048, std::max<size_t>(64, ((size_t)8 << 30) / L.slot_stride))
                  : 0;
   L.slots = take(L.slot_stride * L.nslots);
+  L.cidx = take(4 * n);
+  L.order = take(4 * g);
+  const size_t nm = (size_t)std::max(n_max, 1);
+  L.mslot_stride = align_up(32 * nm + 8 * (nm / 64 + 2) + 8 * 64 * (size_t)kRootRows);
+  L.nmslots = std::min<size_t>(2048, std::max<size_t>(64, ((size_t)8 << 30) / L.mslot_stride));
+  L.mslots = take(L.mslot_stride * L.nmslots);
   L.total = off;
   return L;
 }
@@ -391,6 +407,321 @@ void launch_class(fi_graph* h, const BatchArgs& a, bool lds, hipStream_t s) {
     hipLaunchKernelGGL((k_batch_wg<NT, false>), dim3((int)grid), dim3(NT), 0, s, a);
 }
 
+
+// Anchors (each component's smallest vertex with an edge), global ids.
+__global__ void k_b_anchors(const int32_t* rp, const BatchGraph* meta, const int64_t* vo, int32_t G,
+                            int64_t n_total, const int32_t* comp, int32_t* list, uint32_t* count) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v0 = blockIdx.x * (int64_t)blockDim.x; v0 < n_total; v0 += stride) {
+    const int64_t v = v0 + threadIdx.x;
+    bool is = false;
+    if (v < n_total) {
+      const int32_t g = which(vo, G, v);
+      const BatchGraph b = meta[g];
+      const int32_t u = (int32_t)(v - b.vo);
+      is = rp[b.ro + u + 1] > rp[b.ro + u] && comp[v] == u;
+    }
+    wave_append(is, (int32_t)v, list, count);
+  }
+}
+
+__global__ void k_b_cidx_none(int32_t* cidx, int64_t n) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x)
+    cidx[v] = -1;
+}
+
+__global__ void k_b_scatter_slot(const int32_t* anchors, int64_t count, int32_t* slot) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    slot[anchors[i]] = (int32_t)i;
+}
+
+// Component index of every vertex within its graph (-1 without an edge).
+__global__ void k_b_cidx(const int32_t* rp, const BatchGraph* meta, const int64_t* vo, int32_t G,
+                         int64_t n_total, const int32_t* comp, const int32_t* slot, int32_t* cidx) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n_total;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t g = which(vo, G, v);
+    const BatchGraph b = meta[g];
+    const int32_t u = (int32_t)(v - b.vo);
+    cidx[v] = rp[b.ro + u + 1] > rp[b.ro + u] ? slot[b.vo + comp[v]] - b.cs : -1;
+  }
+}
+
+// The root-minima tables of every slice start at "none".
+__global__ void k_b_mt_tables(char* slots, size_t stride, size_t nslots, size_t table_off) {
+  const int64_t per = 64 * kRootRows;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (int64_t)nslots * per;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t* t = (uint64_t*)(slots + (size_t)(i / per) * stride + table_off);
+    t[i % per] = kUnvisited;
+  }
+}
+
+struct BatchMArgs {
+  const BatchGraph* meta;
+  const int32_t* row_ptr;
+  const uint32_t* adj;
+  const uint2* edges;
+  const int32_t* comp;
+  const int32_t* cidx;
+  CloudSlot* clouds;
+  uint64_t* gctl;
+  const int32_t* order;  // all graphs, largest first
+  uint64_t* ticket;
+  int32_t G, groups;      // graphs; groups of 64 trees per graph
+  int64_t trees;
+  uint64_t seed;
+  uint64_t tsize, cap;
+  char* slots;
+  size_t slot_stride;
+  int32_t n_max;
+};
+
+// Multi-tree sweep of a batch: one workgroup per (graph, group of up to 64
+// trees), largest graph first, drawn by persistent workgroups.  Within a
+// workgroup the levels are pulls over every vertex not yet visited by all
+// trees (rows up to 64 edges 64 vertices per wave, longer rows one per
+// wave), separated by workgroup barriers.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_batch_multi(BatchMArgs B) {
+  constexpr int NW = NT / 64;
+  constexpr int kPlanes = 8;
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+  __shared__ int64_t s_item;
+  __shared__ int s_any[2];  // some vertex reached, by level parity
+  __shared__ uint64_t s_acc[3][64];
+  char* slot = B.slots + (size_t)blockIdx.x * B.slot_stride;
+  const size_t nm = (size_t)B.n_max;
+  mt::MState S;
+  S.nbw[0] = (uint64_t*)slot;
+  S.nbw[1] = S.nbw[0] + nm;
+  S.stw = S.nbw[1] + nm;
+  S.vis = S.stw + nm;
+  S.unf = S.vis + nm;
+  S.cand = nullptr;
+  uint64_t* table = S.unf + (nm / 64 + 2);
+  const int64_t nitems = (int64_t)B.G * B.groups;
+
+  while (true) {
+    if (tid == 0) s_item = (int64_t)atomicAdd((unsigned long long*)B.ticket, 1ull);
+    __syncthreads();
+    const int64_t item = s_item;
+    __syncthreads();
+    if (item >= nitems) break;
+    const int32_t gi = B.order[item / B.groups];
+    const int64_t tb = (item % B.groups) * 64;
+    const BatchGraph b = B.meta[gi];
+    DevGraph G{};
+    G.n = b.n;
+    G.nwords = b.nwords;
+    G.nnz = b.nnz;
+    G.m = b.m;
+    G.row_ptr = B.row_ptr + b.ro;
+    G.adj = B.adj + b.no;
+    G.edges = B.edges + b.me;
+    G.comp = B.comp + b.vo;
+    G.cloud = B.clouds + (size_t)gi * B.tsize;
+    G.cloud_mask = B.tsize - 1;
+    G.cloud_cap = B.cap;
+    G.ctl = B.gctl + (size_t)gi * kCtlPerGraph;
+    const int32_t n = b.n, nw = b.nwords;
+    const int32_t* rp = G.row_ptr;
+    const int32_t* cix = B.cidx + b.vo;
+    const int nvalid = (int)min<int64_t>(64, B.trees - tb);
+    const uint64_t valid = nvalid == 64 ? ~0ull : ((1ull << nvalid) - 1);
+    const bool vlane = lane < nvalid;
+    const KeyMix km = key_mix(tree_salt(B.seed, (uint64_t)(tb + lane)));
+
+    // ---- reset
+    for (int32_t v = tid; v < n; v += NT) {
+      S.nbw[0][v] = 0;
+      S.nbw[1][v] = 0;
+      S.stw[v] = 0;
+      S.vis[v] = 0;
+    }
+    for (int32_t w = wave; w < nw; w += NW) {
+      const int32_t v = w * 64 + lane;
+      const uint64_t m = __ballot(v < n && rp[v + 1] > rp[v]);
+      if (lane == 0) S.unf[w] = m;
+    }
+    __syncthreads();
+
+    // ---- roots, kRootRows components per pass: each wave scans a range of
+    // vertices keeping per-lane minima by component, then one wave per
+    // component writes its roots
+    for (int32_t r0 = 0; r0 < b.ncomp; r0 += kRootRows) {
+      const int32_t rows = min(kRootRows, b.ncomp - r0);
+      const int32_t chunk = (n + NW - 1) / NW;
+      const int32_t v0 = wave * chunk, v1 = min(n, v0 + chunk);
+      int32_t cur = -1;
+      uint64_t best = kUnvisited;
+      for (int32_t c = v0; c < v1; c += 64) {
+        const int32_t vv = c + lane;
+        const int32_t ci = vv < v1 ? cix[vv] : -1;
+        const uint32_t hm = fmix32((uint32_t)vv);
+        const int cnt = min(64, v1 - c);
+        for (int j = 0; j < cnt; ++j) {
+          const int32_t cj = __builtin_amdgcn_readlane(ci, j);
+          if (cj < r0 || cj >= r0 + rows) continue;
+          if (cj != cur) {
+            if (cur >= 0 && vlane && best != kUnvisited)
+              mt::amin64(table + (size_t)(cur - r0) * 64 + lane, best);
+            cur = cj;
+            best = kUnvisited;
+          }
+          const uint64_t k = root_candidate(vkey_of(km, (uint32_t)__builtin_amdgcn_readlane((int)hm, j)),
+                                            (uint32_t)(c + j));
+          best = k < best ? k : best;
+        }
+      }
+      if (cur >= 0 && vlane && best != kUnvisited)
+        mt::amin64(table + (size_t)(cur - r0) * 64 + lane, best);
+      __syncthreads();
+      for (int32_t row = wave; row < rows; row += NW) {
+        uint64_t* tr = table + (size_t)row * 64;
+        const uint64_t bk = vlane ? tr[lane] : kUnvisited;
+        if (vlane) tr[lane] = kUnvisited;
+        const bool ok = vlane && bk != kUnvisited;
+        const uint32_t r = (uint32_t)word_vertex(bk);
+        uint64_t rem = __ballot(ok);
+        while (rem) {
+          const int j = __builtin_ctzll(rem);
+          const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)r, j);
+          const uint64_t msk = __ballot(ok && r == r1);
+          rem &= ~msk;
+          if (lane == 0) {
+            S.nbw[0][r1] = msk;
+            S.vis[r1] = msk;
+            if (msk == valid) mt::aand64(S.unf + (r1 >> 6), ~(1ull << (r1 & 63)));
+          }
+        }
+      }
+      __syncthreads();
+    }
+
+    // ---- levels
+    if (tid == 0) {
+      s_any[0] = 0;
+      s_any[1] = 0;
+    }
+    for (uint32_t L = 1;; ++L) {
+      const int pp = (int)((L - 1) & 1), p = (int)(L & 1);
+      __syncthreads();
+      // the other parity's flag was last read before the barrier above
+      if (tid == 0) s_any[pp] = 0;
+      if (L > kMaxLevel) {
+        if (tid == 0) atomicOr((unsigned long long*)(G.ctl + C_ERR), (unsigned long long)E_DEPTH);
+        break;
+      }
+      uint64_t cnt = 0, deg = 0, fin = 0;
+      for (int32_t w = wave; w < nw; w += NW) {
+        const uint64_t bits = S.unf[w];
+        if (!bits) continue;
+        const int32_t v = w * 64 + lane;
+        const int d = ((bits >> lane) & 1) ? rp[v + 1] - rp[v] : 0;
+        const uint64_t small = __ballot(((bits >> lane) & 1) && d <= 64);
+        const int ne = (int)__popcll(small);
+        if (ne) {
+          const int src = mt::select_lane(small, lane < ne ? lane : 0);
+          const int32_t vk = __shfl(v, src);
+          mt::pull_small(G, S, vk, ne, pp, p, valid, km, false, cnt, deg, fin);
+        }
+        uint64_t big = bits & ~small;
+        while (big) {
+          const int j = __builtin_ctzll(big);
+          big &= big - 1;
+          const int32_t vj = w * 64 + j;
+          const uint64_t vis = S.vis[vj], st = S.stw[vj];
+          const uint64_t want = valid & ~vis;
+          uint64_t best = kUnvisited;
+          if (want) best = mt::pull_edges(G.adj, S.nbw[pp], S.stw, rp[vj], rp[vj + 1], pp, want, km, best);
+          mt::settle(S, vj, vis, st, rp[vj + 1] - rp[vj], best, p, valid, cnt, deg, fin);
+        }
+      }
+      if (lane == 0 && cnt) s_any[p] = 1;
+      __syncthreads();
+      if (!s_any[p]) break;
+    }
+
+    // ---- counts and canonical keys of the trees of the item
+    if (tid < 192) (&s_acc[0][0])[tid] = 0;
+    __syncthreads();
+    {
+      uint64_t c[kPlanes];
+#pragma unroll
+      for (int q = 0; q < kPlanes; ++q) c[q] = 0;
+      uint64_t myS = 0;
+      int it = 0;
+      auto flush = [&]() {
+        for (int t = 0; t < 64; ++t) {
+          uint32_t tot = 0;
+#pragma unroll
+          for (int q = 0; q < kPlanes; ++q) tot += (uint32_t)__popcll(__ballot((c[q] >> t) & 1)) << q;
+          if (lane == t) myS += tot;
+        }
+#pragma unroll
+        for (int q = 0; q < kPlanes; ++q) c[q] = 0;
+      };
+      for (int64_t e0 = 0; e0 < G.m; e0 += NT) {
+        const int64_t e = e0 + tid;
+        uint64_t x = 0;
+        if (e < G.m) {
+          const uint2 uv = G.edges[e];
+          x = S.stw[uv.x] ^ S.stw[uv.y & kVertexMask];
+          if (uv.y >> 31) x = ~x;
+        }
+#pragma unroll
+        for (int q = 0; q < kPlanes; ++q) {
+          const uint64_t carry = c[q] & x;
+          c[q] ^= x;
+          x = carry;
+        }
+        if (++it == 255) {
+          flush();
+          it = 0;
+        }
+      }
+      flush();
+      uint64_t khi = 0, klo = 0;
+      for (int32_t i = wave; i < nw; i += NW) {
+        const int32_t v = i * 64 + lane;
+        uint64_t cs = 0;
+        if (v < n) cs = S.stw[v] ^ S.stw[G.comp[v]];
+        uint64_t W = 0;
+        for (int t = 0; t < 64; ++t) {
+          const uint64_t bb = __ballot((cs >> t) & 1);
+          if (lane == t) W = bb;
+        }
+        key_terms((uint64_t)i, W, khi, klo);
+      }
+      atomicAdd((unsigned long long*)&s_acc[0][lane], (unsigned long long)myS);
+      atomicAdd((unsigned long long*)&s_acc[1][lane], (unsigned long long)khi);
+      atomicAdd((unsigned long long*)&s_acc[2][lane], (unsigned long long)klo);
+    }
+    __syncthreads();
+    if (tid < nvalid) cloud_insert(G, s_acc[1][tid], s_acc[2][tid], s_acc[0][tid], (uint64_t)(tb + tid));
+    __syncthreads();
+  }
+}
+
+template <int NT>
+hipError_t batch_mt_occupancy(BatchInfo* bi) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(&bi->mt_per_cu[nt_index(NT)], k_batch_multi<NT>,
+                                                      NT, 0);
+}
+
+template <int NT>
+void launch_mt_batch(fi_graph* h, const BatchMArgs& a, hipStream_t s) {
+  const BatchInfo* bi = (const BatchInfo*)h->batch;
+  int64_t grid = (int64_t)std::max(1, bi->mt_per_cu[nt_index(NT)]) * h->cu_count;
+  if (h->sched.grid > 0) grid = std::min<int64_t>(grid, h->sched.grid);
+  grid = std::min<int64_t>(grid, (int64_t)bi->L.nmslots);
+  grid = std::max<int64_t>(1, std::min<int64_t>(grid, (int64_t)a.G * a.groups));
+  hipLaunchKernelGGL((k_batch_multi<NT>), dim3((int)grid), dim3(NT), 0, s, a);
+}
+
 bool host_offsets_ok(int32_t G, const int64_t* vo, const int64_t* no, int32_t* n_max) {
   if (G < 1 || !vo || !no || vo[0] != 0 || no[0] != 0) return false;
   *n_max = 0;
@@ -424,7 +755,7 @@ int fi_batch_workspace_size(int32_t G, const int64_t* h_vertex_offsets,
     const int32_t n = (int32_t)(h_vertex_offsets[g + 1] - h_vertex_offsets[g]);
     if (n > kLdsMaxN) n_max_large = std::max(n_max_large, n);
   }
-  *out_bytes = batch_layout(G, h_vertex_offsets[G], h_nnz_offsets[G], n_max_large,
+  *out_bytes = batch_layout(G, h_vertex_offsets[G], h_nnz_offsets[G], n_max_large, n_max,
                             table_size_for(cloud_capacity_per_graph)).total;
   return FI_OK;
 }
@@ -477,7 +808,7 @@ int fi_batch_create(int32_t G, const int64_t* h_vertex_offsets, const int64_t* h
   std::sort(small.begin(), small.end(), by_size);
   std::sort(large.begin(), large.end(), by_size);
   const uint64_t tsize = table_size_for(cloud_capacity_per_graph);
-  BatchLayout L = batch_layout(G, n_total, nnz_total, n_max_large, tsize);
+  BatchLayout L = batch_layout(G, n_total, nnz_total, n_max_large, n_max, tsize);
   if (!d_workspace || ws_bytes < L.total || ((uintptr_t)d_workspace % kAlign)) return FI_EWORKSPACE;
 
   fi_graph* h = new (std::nothrow) fi_graph();
@@ -593,8 +924,61 @@ int fi_batch_create(int32_t G, const int64_t* h_vertex_offsets, const int64_t* h
                        G, n_total, (int32_t*)(ws + L.comp));
   }
   if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess) return fail(FI_EDEVICE);
+
+  // multi-tree sweep: every graph's components numbered in id order of their
+  // anchors (component index per vertex), graphs largest first, root tables
+  {
+    std::vector<int32_t> anchors;
+    if (n_total > 0) {
+      int32_t* alist = (int32_t*)(ws + L.ustart);  // free again after union-find
+      uint64_t zero = 0, count = 0;
+      if (hipMemcpyAsync(ctl + C_NANCH, &zero, 8, hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(FI_EDEVICE);
+      hipLaunchKernelGGL(k_b_anchors, dim3(grid_for(n_total, B)), dim3(B), 0, s, rp, d_meta, d_vo, G,
+                         n_total, (const int32_t*)(ws + L.comp), alist, (uint32_t*)(ctl + C_NANCH));
+      if (hipMemcpyAsync(&count, ctl + C_NANCH, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return fail(FI_EDEVICE);
+      anchors.resize(count);
+      if (count && (hipMemcpyAsync(anchors.data(), alist, 4 * count, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                    hipStreamSynchronize(s) != hipSuccess))
+        return fail(FI_EDEVICE);
+      std::sort(anchors.begin(), anchors.end());
+    }
+    for (int32_t g = 0; g < G; ++g) {
+      const auto lo = std::lower_bound(anchors.begin(), anchors.end(), (int32_t)meta[g].vo);
+      const auto hi = std::lower_bound(anchors.begin(), anchors.end(), (int32_t)(meta[g].vo + meta[g].n));
+      meta[g].cs = (int32_t)(lo - anchors.begin());
+      meta[g].ncomp = (int32_t)(hi - lo);
+    }
+    std::vector<int32_t> order(G);
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(), by_size);
+    if (hipMemcpyAsync(d_meta, meta.data(), sizeof(BatchGraph) * G, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(ws + L.order, order.data(), 4 * (size_t)G, hipMemcpyHostToDevice, s) != hipSuccess)
+      return fail(FI_EDEVICE);
+    if (!anchors.empty()) {
+      int32_t* sorted = (int32_t*)(ws + L.eoff);  // free after packing
+      int32_t* slot = (int32_t*)(ws + L.ustart);
+      if (hipMemcpyAsync(sorted, anchors.data(), 4 * anchors.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(FI_EDEVICE);
+      hipLaunchKernelGGL(k_b_scatter_slot, dim3(grid_for((int64_t)anchors.size(), B)), dim3(B), 0, s, sorted,
+                         (int64_t)anchors.size(), slot);
+      hipLaunchKernelGGL(k_b_cidx, dim3(grid_for(n_total, B)), dim3(B), 0, s, rp, d_meta, d_vo, G, n_total,
+                         (const int32_t*)(ws + L.comp), (const int32_t*)slot, (int32_t*)(ws + L.cidx));
+    } else if (n_total > 0) {
+      hipLaunchKernelGGL(k_b_cidx_none, dim3(grid_for(n_total, B)), dim3(B), 0, s, (int32_t*)(ws + L.cidx),
+                         n_total);
+    }
+    const size_t nm = (size_t)std::max(n_max, 1);
+    hipLaunchKernelGGL(k_b_mt_tables, dim3(grid_for((int64_t)L.nmslots * 64 * kRootRows, B)), dim3(B), 0, s,
+                       ws + L.mslots, L.mslot_stride, L.nmslots, 32 * nm + 8 * (nm / 64 + 2));
+    bi->n_max = n_max;
+  }
+  if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess) return fail(FI_EDEVICE);
   if (batch_occupancy<256>(bi) != hipSuccess || batch_occupancy<512>(bi) != hipSuccess ||
-      batch_occupancy<1024>(bi) != hipSuccess)
+      batch_occupancy<1024>(bi) != hipSuccess || batch_mt_occupancy<256>(bi) != hipSuccess ||
+      batch_mt_occupancy<512>(bi) != hipSuccess || batch_mt_occupancy<1024>(bi) != hipSuccess)
     return fail(FI_EDEVICE);
   *out = h;
   return FI_OK;
@@ -629,7 +1013,39 @@ int fi_batch_sweep(fi_graph* h, int64_t trees_per_graph, uint64_t seed, uint64_t
                      (CloudSlot*)(ws + L.clouds), (int64_t)bi->tsize * bi->G, (uint64_t*)(ws + L.gctl),
                      bi->G, ctl);
   hipError_t e = hipGetLastError();
-  for (int cls = 0; cls < 2 && e == hipSuccess; ++cls) {
+  // 64 trees of a graph per workgroup pass, unless a per-tree schedule is
+  // asked for or there are too few trees per graph to share a pass
+  const bool multi = h->sched.path == 4 || (h->sched.path == 0 && trees_per_graph >= 16);
+  if (multi && e == hipSuccess) {
+    BatchMArgs m{};
+    m.meta = a.meta;
+    m.row_ptr = a.row_ptr;
+    m.adj = a.adj;
+    m.edges = a.edges;
+    m.comp = a.comp;
+    m.cidx = (const int32_t*)(ws + L.cidx);
+    m.clouds = a.clouds;
+    m.gctl = a.gctl;
+    m.order = (const int32_t*)(ws + L.order);
+    m.ticket = ctl + kTicket0;
+    m.G = bi->G;
+    m.groups = (int32_t)((trees_per_graph + 63) / 64);
+    m.trees = trees_per_graph;
+    m.seed = seed;
+    m.tsize = bi->tsize;
+    m.cap = (uint64_t)bi->cap;
+    m.slots = ws + L.mslots;
+    m.slot_stride = L.mslot_stride;
+    m.n_max = bi->n_max;
+    void* tok = nullptr;
+    if (prof_begin(h, s, &tok)) return FI_EDEVICE;
+    if (nt == 1024) launch_mt_batch<1024>(h, m, s);
+    else if (nt == 512) launch_mt_batch<512>(h, m, s);
+    else launch_mt_batch<256>(h, m, s);
+    e = hipGetLastError();
+    prof_end(h, s, tok, 0);
+  }
+  for (int cls = 0; cls < 2 && e == hipSuccess && !multi; ++cls) {
     const bool lds = cls == 0;
     a.order = (const int32_t*)(ws + (lds ? L.small : L.large));
     a.nitems = (int64_t)(lds ? bi->n_small : bi->n_large) * trees_per_graph;

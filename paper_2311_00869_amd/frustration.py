@@ -387,14 +387,17 @@ class BatchGraph:
     def status(self, stream=None):
         _check(self.lib.fi_graph_status(self.handle, _stream_ptr(stream)), "batch_status")
 
-    def set_schedule(self, block=256, grid=0):
-        s = Schedule(0, block, grid, 512, 1)
+    def set_schedule(self, block=256, grid=0, path=0):
+        """path 0: 64 trees of a graph per workgroup pass when at least 16 trees
+        per graph are swept, else one workgroup per tree; 1: one workgroup per
+        tree; 4: 64 trees per pass."""
+        s = Schedule(path, block, grid, 512, 1)
         _check(self.lib.fi_set_schedule(self.handle, ctypes.byref(s)), "set_schedule")
 
     def get_schedule(self):
         s = Schedule()
         _check(self.lib.fi_get_schedule(self.handle, ctypes.byref(s)), "get_schedule")
-        return dict(block=s.block, grid=s.grid)
+        return dict(block=s.block, grid=s.grid, path=s.path)
 
     def prof_enable(self, on=True):
         _check(self.lib.fi_prof_enable(self.handle, 1 if on else 0), "prof_enable")

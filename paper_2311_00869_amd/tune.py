@@ -96,7 +96,7 @@ def default_batch_schedule(batch):
     cache = _load()
     if _batch_key(batch) in cache:
         return dict(cache[_batch_key(batch)])
-    return dict(block=512, grid=0)
+    return dict(block=512, grid=0, path=0)
 
 
 def autotune_batch(batch, trees: int = 4, seed: int = 12345, save: bool = True, verbose=False):
@@ -106,14 +106,14 @@ def autotune_batch(batch, trees: int = 4, seed: int = 12345, save: bool = True, 
 
     best, results = None, []
     for b in (256, 512, 1024):
-        batch.set_schedule(block=b)
+        batch.set_schedule(block=b, path=0)
         batch.sweep(1, seed)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         batch.sweep(trees, seed)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        s = dict(block=b, grid=0)
+        s = dict(block=b, grid=0, path=0)
         results.append((el, s))
         if verbose:
             print(f"# tune batch {s}: {trees * batch.G / el:.1f} trees/s", flush=True)

@@ -25,6 +25,7 @@ def _mixed():
         synth.random_tree(200, 1),
         synth.cycle_graph(33, (0, 5, 9)),
         synth.random_small(300, 280, 3, p_pos=0.6),
+        synth.random_small(1000, 300, 7, p_pos=0.5),  # hundreds of small components
         synth.chung_lu(2000, 3000, 2.1, 5, p_pos=0.7),
         synth.erdos_renyi_connected(6144, 20000, 0.75, 11),
         synth.erdos_renyi_connected(6145, 15000, 0.8, 12),
@@ -47,11 +48,24 @@ def test_mixed_batch_matches_oracle_per_graph():
     K, seed = 40, 4242
     want_min, want_distinct = _expect(graphs, K, seed)
     B = fr.BatchGraph(graphs, cloud_capacity_per_graph=K)
-    for block in (256, 512, 1024):
-        B.set_schedule(block=block)
-        mn, ds = B.sweep(K, seed)
-        assert np.array_equal(mn.cpu().numpy(), want_min), block
-        assert np.array_equal(ds.cpu().numpy(), want_distinct), block
+    # path 1: one workgroup per tree; path 4: 64 trees per workgroup pass
+    for path in (1, 4):
+        for block in (256, 512, 1024):
+            B.set_schedule(block=block, path=path)
+            mn, ds = B.sweep(K, seed)
+            assert np.array_equal(mn.cpu().numpy(), want_min), (path, block)
+            assert np.array_equal(ds.cpu().numpy(), want_distinct), (path, block)
+    # more than one pass of 64 trees per graph, and a partial one
+    K2 = 150
+    w2_min, w2_distinct = _expect(graphs, K2, seed + 1)
+    B2 = fr.BatchGraph(graphs, cloud_capacity_per_graph=K2)
+    for path in (1, 4):
+        B2.set_schedule(block=512, path=path)
+        mn, ds = B2.sweep(K2, seed + 1)
+        assert np.array_equal(mn.cpu().numpy(), w2_min), path
+        assert np.array_equal(ds.cpu().numpy(), w2_distinct), path
+    B2.close()
+    B.set_schedule(block=256)
     # a second call starts from empty clouds
     mn, ds = B.sweep(K, seed)
     assert np.array_equal(mn.cpu().numpy(), want_min)
@@ -66,10 +80,11 @@ def test_uneven_batch_sampled_graphs():
     graphs = synth.config_batch(G, seed=3, n_lo=100, n_hi=12000)
     want_min, want_distinct = _expect(graphs, K, seed)
     B = fr.BatchGraph(graphs, cloud_capacity_per_graph=K)
-    B.set_schedule(block=512, grid=96)
-    mn, ds = B.sweep(K, seed)
-    assert np.array_equal(mn.cpu().numpy(), want_min)
-    assert np.array_equal(ds.cpu().numpy(), want_distinct)
+    for path in (1, 4):
+        B.set_schedule(block=512, grid=96, path=path)
+        mn, ds = B.sweep(K, seed)
+        assert np.array_equal(mn.cpu().numpy(), want_min), path
+        assert np.array_equal(ds.cpu().numpy(), want_distinct), path
     B.close()
 
 

@@ -84,7 +84,7 @@ def test_uneven_batch_full_size_sampled():
     B = fr.BatchGraph(graphs, cloud_capacity_per_graph=K)
     ms = [g.nnz // 2 for g in graphs]
     del graphs
-    for sched in [tune.default_batch_schedule(B), dict(block=256), dict(block=1024)]:
+    for sched in [tune.default_batch_schedule(B), dict(block=256, path=4), dict(block=1024, path=1)]:
         B.set_schedule(**sched)
         mn, ds = B.sweep(K, gold["seed"])
         mn, ds = mn.cpu().numpy(), ds.cpu().numpy()
