@@ -37,7 +37,8 @@ def algorithmic_bytes_per_tree(n: int, nnz: int) -> int:
 
 def kernel_source_sha() -> str:
     h = hashlib.sha256()
-    for f in ("sweep.hip", "sweep_grid.hip", "sweep_multi.hip", "fi_prims.h", "fi_internal.h"):
+    for f in ("sweep.hip", "sweep_grid.hip", "sweep_multi.hip", "fi_multi.h", "fi_prims.h",
+              "fi_internal.h"):
         with open(os.path.join(ROOT, "paper_2311_00869_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
