@@ -15,9 +15,9 @@
  *
  * Tree sampler (the paper's best, BFS, Section "Tree-Sampling techniques"),
  * made reproducible: tree t of a sweep with seed s takes as salt output t of
- * the SplitMix64 stream seeded with s; vertex u gets the key
- * (h_t(u), u) with h_t(u) = fmix32(u * (salt_hi | 1) + salt_lo) >> 12
- * (MurmurHash3 finalizer, 32-bit arithmetic).  The root of every connected
+ * the SplitMix64 stream seeded with s; vertex u gets the 32-bit key
+ * (fmix32(u) xor salt_lo) * (salt_hi | 1) mod 2^32 (fmix32: the MurmurHash3
+ * finalizer), a bijection of u, so keys never tie.  The root of every connected
  * component is its minimum-key vertex, and the parent of every other vertex
  * is its minimum-key neighbour one BFS level closer to the root.  Vertex
  * states: root +1, child = parent * sign(tree edge); by Theorem t:HararyCut
@@ -64,7 +64,8 @@ enum {
   FI_EDEVICE = -9,     /* a HIP runtime call failed */
   FI_EDEPTH = -10,     /* a BFS tree deeper than 4094 levels */
   FI_ECOLLISION = -11, /* two different states met under one 64-bit key half */
-  FI_EWORKSPACE = -12  /* workspace missing, too small or misaligned (256 B) */
+  FI_EWORKSPACE = -12, /* workspace missing, too small or misaligned (256 B) */
+  FI_EORDER = -13      /* a bounded-cloud merge whose trees do not follow the last one's */
 };
 
 /* Opaque handle: views of the caller's workspace plus host-side settings. */
@@ -226,6 +227,76 @@ int fi_batch_create(int32_t G, const int64_t* h_vertex_offsets, const int64_t* h
  * it may be recorded into a HIP graph on `stream`. */
 int fi_batch_sweep(fi_graph* b, int64_t trees_per_graph, uint64_t seed, uint64_t* d_min_per_graph,
                    uint64_t* d_distinct_per_graph, void* stream);
+
+/* ---------------------------------------------------------------- memory-bound cloud */
+
+/* Alg. alg-scale (appendix, scaling graphBpp for large signed graphs): a
+ * frustration cloud of at most F_max states that keeps the best ones.
+ * Readings of the printed algorithm, which is garbled: the state replaced
+ * when the cloud is full is the worst one (largest S, and among equal S the
+ * one whose first tree is latest), not the argmin printed; a repeat of a
+ * held state always counts (C is the count through all k trees); below
+ * F_max every new state is kept; a new state replaces the worst only if its
+ * S is strictly smaller.  The result is the F_max best distinct states by
+ * (S, first tree), each with its count over every tree swept, and
+ * Fr = min S is the same as with an unbounded cloud.
+ *
+ * The table lives in a caller-owned workspace (fi_bcloud_workspace_size
+ * bytes, 256-byte aligned, kept until fi_bcloud_destroy) of about 160 B per
+ * entry.  Trees are swept in chunks into a graph's own cloud, which serves
+ * as the staging table, and merged here in tree order; `staging` (1 ..
+ * 8192) bounds the distinct states one merge takes, so a graph merged into
+ * this cloud needs cloud_capacity <= staging. */
+typedef struct fi_bcloud fi_bcloud;
+
+/* Bytes of workspace for F_max entries (1 .. 2^31) and `staging` candidates
+ * per merge.  Pure host arithmetic. */
+int fi_bcloud_workspace_size(int64_t f_max, int64_t staging, size_t* out_bytes);
+
+/* The largest F_max whose workspace fits in cap_bytes (line "Determine
+ * F_max" of Alg. alg-scale, with the device memory the caller grants as
+ * CAP).  FI_EWORKSPACE if not even one entry fits.  Pure host arithmetic. */
+int fi_bcloud_fmax_for(size_t cap_bytes, int64_t staging, int64_t* out_fmax);
+
+/* Empty table in d_workspace (blocks).  *out owns host memory only. */
+int fi_bcloud_create(int64_t f_max, int64_t staging, void* d_workspace, size_t ws_bytes,
+                     void* stream, fi_bcloud** out);
+void fi_bcloud_destroy(fi_bcloud* c);
+
+/* Empty the table, its counters and its sticky error; the next merge may
+ * start at any tree. */
+int fi_bcloud_reset(fi_bcloud* c, void* stream);
+
+/* Merge the states in g's cloud, which must hold exactly trees t0 .. t1-1
+ * (swept with fi_sweep_range after an empty cloud), into c, then empty g's
+ * cloud.  t0 must equal the previous merge's t1 (FI_EORDER otherwise; a
+ * staged state whose first tree lies outside [t0, t1) sets the sticky
+ * FI_EORDER).  FI_EINVAL if g's cloud_capacity exceeds c's staging.  A
+ * sticky error of g's cloud (capacity, depth, collision) moves into c.
+ * Kernels only. */
+int fi_bcloud_merge(fi_graph* g, fi_bcloud* c, int64_t t0, int64_t t1, void* stream);
+
+/* Alg. alg-scale over trees t0 .. t1-1: empties g's cloud, then sweeps and
+ * merges chunks of `chunk` trees (0: min(cloud_capacity, staging); larger
+ * is FI_EINVAL).  Results do not depend on the chunk size or schedule. */
+int fi_sweep_bounded(fi_graph* g, fi_bcloud* c, int64_t t0, int64_t t1, uint64_t seed,
+                     int64_t chunk, void* stream);
+
+/* Entries held (blocks); returns the sticky error, if any. */
+int fi_bcloud_size(fi_bcloud* c, int64_t* out, void* stream);
+
+/* Copy the entries to host memory sorted by (key_hi, key_lo) (blocks);
+ * writes min(size, cap) and sets *written to the size. */
+int fi_bcloud_read(fi_bcloud* c, fi_cloud_entry* h_out, int64_t cap, int64_t* written,
+                   void* stream);
+
+/* Fr = min S over the trees merged and the first tree reaching it (blocks);
+ * FI_EINVAL if empty. */
+int fi_bcloud_min(fi_bcloud* c, uint64_t* out_switches, uint64_t* out_first_tree, void* stream);
+
+/* Trees merged since the last reset, and the entries dropped (states
+ * replaced or turned away, once per merge that dropped them) (blocks). */
+int fi_bcloud_stats(fi_bcloud* c, int64_t* out_trees, int64_t* out_dropped, void* stream);
 
 /* ---------------------------------------------------------------- schedule */
 

@@ -540,6 +540,7 @@ const char* fi_strerror(int code) {
     case FI_EDEPTH: return "BFS tree deeper than 4094 levels";
     case FI_ECOLLISION: return "state key collision";
     case FI_EWORKSPACE: return "workspace missing, too small or misaligned";
+    case FI_EORDER: return "bounded-cloud merge out of tree order";
     default: return "unknown error";
   }
 }

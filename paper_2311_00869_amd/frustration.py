@@ -21,6 +21,7 @@ ERRORS = {
     0: "FI_OK", -1: "FI_EINVAL", -2: "FI_EASYM", -3: "FI_ESELFLOOP", -4: "FI_EDUP",
     -5: "FI_ESIGN", -6: "FI_ERANGE", -7: "FI_EUNSORTED", -8: "FI_ECAPACITY",
     -9: "FI_EDEVICE", -10: "FI_EDEPTH", -11: "FI_ECOLLISION", -12: "FI_EWORKSPACE",
+    -13: "FI_EORDER",
 }
 SYMBOLS = (
     "fi_graph_workspace_size", "fi_graph_create", "fi_graph_destroy", "fi_graph_info",
@@ -29,6 +30,9 @@ SYMBOLS = (
     "fi_graphl_forward", "fi_graphl_backward", "fi_graphl_step", "fi_round_count",
     "fi_batch_workspace_size", "fi_batch_create", "fi_batch_sweep", "fi_set_schedule",
     "fi_get_schedule", "fi_prof_enable", "fi_prof_read", "fi_strerror",
+    "fi_bcloud_workspace_size", "fi_bcloud_fmax_for", "fi_bcloud_create", "fi_bcloud_destroy",
+    "fi_bcloud_reset", "fi_bcloud_merge", "fi_sweep_bounded", "fi_bcloud_size", "fi_bcloud_read",
+    "fi_bcloud_min", "fi_bcloud_stats",
 )
 
 
@@ -93,6 +97,17 @@ def load_library(path: str = LIB_PATH):
             "fi_prof_enable": ([vp, c.c_int], c.c_int),
             "fi_prof_read": ([vp, c.c_int, P(c.c_double), P(i64)], c.c_int),
             "fi_strerror": ([c.c_int], c.c_char_p),
+            "fi_bcloud_workspace_size": ([i64, i64, P(sz)], c.c_int),
+            "fi_bcloud_fmax_for": ([sz, i64, P(i64)], c.c_int),
+            "fi_bcloud_create": ([i64, i64, vp, sz, vp, P(vp)], c.c_int),
+            "fi_bcloud_destroy": ([vp], None),
+            "fi_bcloud_reset": ([vp, vp], c.c_int),
+            "fi_bcloud_merge": ([vp, vp, i64, i64, vp], c.c_int),
+            "fi_sweep_bounded": ([vp, vp, i64, i64, u64, i64, vp], c.c_int),
+            "fi_bcloud_size": ([vp, P(i64), vp], c.c_int),
+            "fi_bcloud_read": ([vp, vp, i64, P(i64), vp], c.c_int),
+            "fi_bcloud_min": ([vp, P(u64), P(u64), vp], c.c_int),
+            "fi_bcloud_stats": ([vp, P(i64), P(i64), vp], c.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -224,6 +239,14 @@ class Graph:
         arr = np.ctypeslib.as_array(buf).view(np.uint64).reshape(-1, 5)[:size].copy()
         return arr
 
+    def sweep_bounded(self, cloud: "BoundedCloud", t0: int, t1: int, seed: int, chunk: int = 0,
+                      stream=None):
+        """Alg. alg-scale over trees t0 .. t1-1 into ``cloud`` (empties this
+        graph's own cloud, which stages each chunk)."""
+        _check(self.lib.fi_sweep_bounded(self.handle, cloud.handle, int(t0), int(t1),
+                                         seed & (2**64 - 1), int(chunk), _stream_ptr(stream)),
+               "sweep_bounded")
+
     def cloud_reset(self, stream=None):
         _check(self.lib.fi_cloud_reset(self.handle, _stream_ptr(stream)), "cloud_reset")
 
@@ -300,6 +323,89 @@ class Graph:
         ms, k = ctypes.c_double(), ctypes.c_int64()
         _check(self.lib.fi_prof_read(self.handle, kernel, ctypes.byref(ms), ctypes.byref(k)), "prof_read")
         return float(ms.value), int(k.value)
+
+
+class BoundedCloud:
+    """Memory-bound frustration cloud of Alg. alg-scale: the F_max best
+    states by (switch count, first tree), each with its full count.
+
+    Fill it with ``graph.sweep_bounded(cloud, t0, t1, seed)``, or with
+    ``graph.sweep_range`` over consecutive chunks and ``merge``.  The graph's
+    cloud_capacity must not exceed ``staging``.
+    """
+
+    def __init__(self, f_max: int, staging: int = 8192, device="cuda", stream=None):
+        _require_gpu()
+        self.lib = load_library()
+        self.device = torch.device(device)
+        self.f_max, self.staging = int(f_max), int(staging)
+        size = ctypes.c_size_t(0)
+        _check(self.lib.fi_bcloud_workspace_size(self.f_max, self.staging, ctypes.byref(size)),
+               "bcloud_workspace_size")
+        self.ws_bytes = int(size.value)
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self.workspace.data_ptr() + 255) // 256 * 256
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = self.lib.fi_bcloud_create(self.f_max, self.staging, ctypes.c_void_p(ptr),
+                                           self.ws_bytes, _stream_ptr(stream), ctypes.byref(h))
+        _check(rc, "bcloud_create")
+        self.handle = h
+
+    @staticmethod
+    def fmax_for(cap_bytes: int, staging: int = 8192) -> int:
+        """Largest F_max whose workspace fits in cap_bytes."""
+        out = ctypes.c_int64()
+        _check(load_library().fi_bcloud_fmax_for(int(cap_bytes), int(staging), ctypes.byref(out)),
+               "bcloud_fmax_for")
+        return int(out.value)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            torch.cuda.synchronize(self.device)
+            self.lib.fi_bcloud_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reset(self, stream=None):
+        _check(self.lib.fi_bcloud_reset(self.handle, _stream_ptr(stream)), "bcloud_reset")
+
+    def merge(self, graph: "Graph", t0: int, t1: int, stream=None):
+        _check(self.lib.fi_bcloud_merge(graph.handle, self.handle, int(t0), int(t1),
+                                        _stream_ptr(stream)), "bcloud_merge")
+
+    def size(self, stream=None) -> int:
+        k = ctypes.c_int64()
+        _check(self.lib.fi_bcloud_size(self.handle, ctypes.byref(k), _stream_ptr(stream)),
+               "bcloud_size")
+        return int(k.value)
+
+    def entries(self, stream=None) -> np.ndarray:
+        """uint64 [E, 5]: key_hi, key_lo, freq, switches, first_tree (sorted by key)."""
+        size = self.size(stream)
+        buf = (CloudEntry * max(size, 1))()
+        written = ctypes.c_int64()
+        _check(self.lib.fi_bcloud_read(self.handle, buf, size, ctypes.byref(written),
+                                       _stream_ptr(stream)), "bcloud_read")
+        return np.ctypeslib.as_array(buf).view(np.uint64).reshape(-1, 5)[:size].copy()
+
+    def min_frustration(self, stream=None):
+        s, t = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(self.lib.fi_bcloud_min(self.handle, ctypes.byref(s), ctypes.byref(t),
+                                      _stream_ptr(stream)), "bcloud_min")
+        return int(s.value), int(t.value)
+
+    def stats(self, stream=None):
+        """(trees merged, entries dropped)."""
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(self.lib.fi_bcloud_stats(self.handle, ctypes.byref(a), ctypes.byref(b),
+                                        _stream_ptr(stream)), "bcloud_stats")
+        return int(a.value), int(b.value)
 
 
 class BatchGraph:

@@ -1,0 +1,134 @@
+"""Parity of the memory-bound cloud (Alg. alg-scale) with the oracle: every
+held entry (key, count, switch count, first tree) bit-exact, for bounds that
+bite and bounds that do not, ragged chunks, every schedule, sweeps that start
+past tree 0 or are split over calls, and the error paths."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import alg_scale
+from paper_2311_00869_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+fr = pytest.importorskip("paper_2311_00869_amd.frustration")
+
+
+def _want(r, t0, fmax):
+    c = alg_scale.bounded_cloud(r.trees, fmax, t0)
+    rows = np.array(alg_scale.as_rows(c), dtype=np.uint64).reshape(-1, 5)
+    return rows, alg_scale.frustration_index(c)
+
+
+def _graphs():
+    return [
+        # every tree a new state: the bound bites on every merge
+        ("small", synth.config_small(0)),
+        # few states, each reached many times, with ties in S
+        ("complete9", synth.complete_graph(9, -1)),
+        ("cycle33", synth.cycle_graph(33, (0, 5, 9))),
+        # many components; some states repeat
+        ("components", synth.random_small(400, 330, 4, p_pos=0.5)),
+        ("powerlaw", synth.chung_lu(2000, 3000, 2.1, 5, p_pos=0.7)),
+        ("er20k", synth.erdos_renyi_connected(20000, 60000, 0.85, 13)),
+    ]
+
+
+@pytest.mark.parametrize("name,g", _graphs(), ids=[n for n, _ in _graphs()])
+def test_bounded_cloud_matches_oracle(name, g):
+    K, seed = 300, 31
+    G = fr.Graph(g.row_ptr, g.col, g.sign, cloud_capacity=256)
+    r = oracle.sweep(g, seed, 0, K, checks=False)
+    distinct = len(r.cloud)
+    bounds = sorted({1, 7, 64, max(1, distinct - 1), distinct, 5000})
+    scheds = [dict(path=0), dict(path=4, block=1024), dict(path=3, block=512, batch=4)]
+    if G.n <= 12000:
+        scheds.append(dict(path=1, block=256))
+    for fmax in bounds:
+        want, best = _want(r, 0, fmax)
+        C = fr.BoundedCloud(fmax, staging=256)
+        for sched, chunk in zip(scheds * 2, (0, 64, 37, 256, 1, 100, 99, 255)):
+            G.set_schedule(**sched)
+            C.reset()
+            G.sweep_bounded(C, 0, K, seed, chunk=chunk)
+            got = C.entries()
+            assert np.array_equal(got, want), (name, fmax, sched, chunk)
+            assert C.min_frustration() == best, (name, fmax, sched, chunk)
+            trees, dropped = C.stats()
+            assert trees == K
+            assert (dropped == 0) == (fmax >= distinct), (fmax, distinct, dropped)
+        C.close()
+    G.close()
+
+
+def test_offset_start_and_split_calls():
+    g = synth.chung_lu(3000, 6000, 2.2, 8, p_pos=0.65)
+    seed, fmax = 5, 20
+    G = fr.Graph(g.row_ptr, g.col, g.sign, cloud_capacity=128)
+    C = fr.BoundedCloud(fmax, staging=128)
+    want, best = _want(oracle.sweep(g, seed, 1000, 1400, checks=False), 1000, fmax)
+    G.sweep_bounded(C, 1000, 1400, seed, chunk=77)
+    assert np.array_equal(C.entries(), want)
+    assert C.min_frustration() == best
+    # the same trees over three calls, and by hand with sweep_range + merge
+    C.reset()
+    G.sweep_bounded(C, 1000, 1130, seed)
+    G.sweep_bounded(C, 1130, 1131, seed)
+    G.sweep_bounded(C, 1131, 1400, seed, chunk=128)
+    assert np.array_equal(C.entries(), want)
+    C.reset()
+    G.cloud_reset()
+    for a in range(1000, 1400, 50):
+        G.sweep_range(a, a + 50, seed)
+        C.merge(G, a, a + 50)
+    assert np.array_equal(C.entries(), want)
+    assert G.cloud_size() == 0  # each merge empties the staging cloud
+    C.close()
+    G.close()
+
+
+def test_bounded_cloud_errors():
+    g = synth.random_small(300, 700, 5, p_pos=0.6)
+    G = fr.Graph(g.row_ptr, g.col, g.sign, cloud_capacity=64)
+    C = fr.BoundedCloud(8, staging=64)
+    with pytest.raises(fr.FrustrationError) as e:  # chunk above the staging cloud
+        G.sweep_bounded(C, 0, 100, 1, chunk=65)
+    assert e.value.code == -1
+    G.sweep_bounded(C, 0, 100, 1)
+    with pytest.raises(fr.FrustrationError) as e:  # not following tree 100
+        G.sweep_bounded(C, 50, 150, 1)
+    assert e.value.code == -13
+    with pytest.raises(fr.FrustrationError) as e:
+        C.merge(G, 101, 120)
+    assert e.value.code == -13
+    # staged trees outside the merge's range: sticky FI_EORDER
+    G.sweep_range(300, 310, 1)
+    C.merge(G, 100, 110)
+    with pytest.raises(fr.FrustrationError) as e:
+        C.size()
+    assert e.value.code == -13
+    C.reset()
+    assert C.size() == 0
+    with pytest.raises(fr.FrustrationError):
+        C.min_frustration()  # empty
+    # a staging overflow of the graph's cloud moves into the bounded cloud
+    G1 = fr.Graph(g.row_ptr, g.col, g.sign, cloud_capacity=1)
+    G1.sweep_range(0, 40, 1)
+    C.merge(G1, 0, 40)
+    with pytest.raises(fr.FrustrationError) as e:
+        C.entries()
+    assert e.value.code == -8
+    G1.close()
+    # a graph whose cloud is larger than the staging bound
+    C2 = fr.BoundedCloud(4, staging=16)
+    with pytest.raises(fr.FrustrationError) as e:
+        C2.merge(G, 0, 10)
+    assert e.value.code == -1
+    for bad in (0, -3):
+        with pytest.raises(fr.FrustrationError):
+            fr.BoundedCloud(bad)
+    with pytest.raises(fr.FrustrationError):
+        fr.BoundedCloud(4, staging=8193)
+    C2.close()
+    C.close()
+    G.close()

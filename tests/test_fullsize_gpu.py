@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 import torch
 
+from oracle import alg_scale
 from paper_2311_00869_amd import synth, tune
 
 pytestmark = pytest.mark.gpu
@@ -40,7 +41,7 @@ def test_large_graph_bench_configuration():
     gold = _golden("large")
     g = synth.config_large(0)
     assert (g.n, g.nnz) == (gold["n"], gold["nnz"])
-    G = fr.Graph(g.row_ptr, g.col, g.sign, cloud_capacity=64)
+    G = fr.Graph(g.row_ptr, g.col, g.sign, cloud_capacity=256)
     _check(G, gold, tune.default_schedule(G.n, G.nnz))
     _check(G, gold, dict(path=3, block=512, heavy=256, batch=1))
     _check(G, gold, dict(path=4, block=1024))
@@ -48,7 +49,34 @@ def test_large_graph_bench_configuration():
     words, s0 = G.tree_state(gold["seed"], gold["t0"])
     got = int(G.count(torch.from_numpy(words.view(np.int64))).item())
     assert got == s0 == gold["trees"][0][0]
+    _check_bounded(G, gold, fmax=1, chunk=1)
+    # more trees than the oracle can run here: the bounded cloud is the
+    # F_max best states by (S, first tree) of the unbounded one, same counts
+    G.set_schedule(path=4, block=1024)
+    G.cloud_reset()
+    G.sweep_range(0, 192, 7)
+    full = G.cloud()
+    C = fr.BoundedCloud(50, staging=256)
+    G.sweep_bounded(C, 0, 192, 7, chunk=64)
+    best = full[np.lexsort((full[:, 4], full[:, 3]))][:50]
+    best = best[np.lexsort((best[:, 1], best[:, 0]))]
+    assert np.array_equal(C.entries(), best)
+    trees, dropped = C.stats()
+    assert trees == 192 and dropped >= len(full) - 50
+    C.close()
     G.close()
+
+
+def _check_bounded(G, gold, fmax, chunk):
+    """Alg. alg-scale on the oracle's stored per-tree results."""
+    t0, t1, seed = gold["t0"], gold["t1"], gold["seed"]
+    c = alg_scale.bounded_cloud(gold["trees"], fmax, t0)
+    want = np.array(alg_scale.as_rows(c), dtype=np.uint64).reshape(-1, 5)
+    C = fr.BoundedCloud(fmax, staging=G.cloud_capacity)
+    G.sweep_bounded(C, t0, t1, seed, chunk=chunk)
+    assert np.array_equal(C.entries(), want)
+    assert C.min_frustration() == alg_scale.frustration_index(c)
+    C.close()
 
 
 def test_planted_powerlaw_all_paths():
@@ -66,6 +94,8 @@ def test_planted_powerlaw_all_paths():
     w = np.zeros(G.nwords, np.uint64)
     np.bitwise_or.at(w, idx // 64, np.left_shift(np.uint64(1), (idx % 64).astype(np.uint64)))
     assert int(G.count(torch.from_numpy(w.view(np.int64))).item()) == gold["planted_flipped"]
+    G.set_schedule(path=4, block=1024)
+    _check_bounded(G, gold, fmax=3, chunk=3)
     G.close()
 
 

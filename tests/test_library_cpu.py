@@ -39,6 +39,29 @@ def test_strerror_and_workspace_arithmetic():
     assert lib.fi_graph_workspace_size(10, 2**31, 0, ctypes.byref(size)) == -6
 
 
+def test_bounded_cloud_sizing_is_host_arithmetic():
+    lib = fr.load_library()
+    size = ctypes.c_size_t()
+    assert lib.fi_bcloud_workspace_size(1000, 256, ctypes.byref(size)) == 0
+    one = size.value
+    assert lib.fi_bcloud_workspace_size(2000, 256, ctypes.byref(size)) == 0
+    assert size.value > one > 1000 * 128  # two entry arrays and the index
+    for fmax, staging in ((0, 16), (-1, 16), (2**31 + 1, 16), (8, 0), (8, 8193)):
+        assert lib.fi_bcloud_workspace_size(fmax, staging, ctypes.byref(size)) == -1
+    # F_max from a memory cap (Alg. alg-scale): the largest table that fits
+    fmax = ctypes.c_int64()
+    for cap in (1 << 20, 10 << 20, 1 << 30):
+        assert lib.fi_bcloud_fmax_for(cap, 1024, ctypes.byref(fmax)) == 0
+        assert lib.fi_bcloud_workspace_size(fmax.value, 1024, ctypes.byref(size)) == 0
+        assert size.value <= cap
+        assert lib.fi_bcloud_workspace_size(fmax.value + 1, 1024, ctypes.byref(size)) == 0
+        assert size.value > cap
+    assert lib.fi_bcloud_fmax_for(1000, 1024, ctypes.byref(fmax)) == -12
+    assert lib.fi_bcloud_create(0, 16, None, 0, None, ctypes.byref(ctypes.c_void_p())) == -1
+    assert lib.fi_bcloud_create(8, 16, None, 0, None, ctypes.byref(ctypes.c_void_p())) == -12
+    assert b"order" in lib.fi_strerror(-13)
+
+
 def test_create_rejects_bad_arguments_without_touching_the_device():
     lib = fr.load_library()
     out = ctypes.c_void_p()
