@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--cpu-trees", type=int, default=2)
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch leg")
     ap.add_argument("--no-planted", action="store_true", help="skip the 10^4-tree planted leg")
+    ap.add_argument("--no-bounded", action="store_true",
+                    help="skip the memory-bound cloud leg (Alg. alg-scale)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy this many MiB device to device (a kernel of known traffic "
                          "for scaling hardware byte counters)")
@@ -176,6 +178,8 @@ def main():
 
     sched_used = G.get_schedule()
     extra = {}
+    if not args.no_bounded:
+        extra["bounded"] = bench_bounded(fr, torch, G, T, args.steps, best)
     if not args.no_plain:
         # the plain per-tree path: one launch per tree, one tree in flight
         # (whole-grid path, no batching of trees)
@@ -224,6 +228,47 @@ def main():
     out.update(extra)
     G.close()
     print(json.dumps(out), flush=True)
+
+
+def bench_bounded(fr, torch, G, T, steps, unbounded_best, fmax=100, chunk=250):
+    """Alg. alg-scale on the same graph and trees as the main leg: a cloud of
+    at most F_max states, merged every `chunk` trees; then the merges alone,
+    timed with events on the stream they run on."""
+    C = fr.BoundedCloud(fmax, staging=G.cloud_capacity)
+    G.sweep_bounded(C, 0, chunk, 999)
+    C.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    best = None
+    for s in range(steps):
+        C.reset()
+        G.sweep_bounded(C, 0, T, s, chunk=chunk)
+        best = C.min_frustration()
+    el = time.perf_counter() - t0
+    held = C.size()
+    C.reset()
+    G.cloud_reset()
+    ev = []
+    for a in range(0, T, chunk):
+        b = min(T, a + chunk)
+        G.sweep_range(a, b, steps - 1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        C.merge(G, a, b)
+        e1.record()
+        ev.append((e0, e1))
+    torch.cuda.synchronize()
+    merge_ms = [a.elapsed_time(b) for a, b in ev]
+    out = {
+        "workload": f"the main leg's graph and trees, F_max={fmax}, a merge every {chunk} trees",
+        "trees_per_s": round(T * steps / el, 2), "ms_per_step": round(el / steps * 1e3, 3),
+        "merges_per_step": len(merge_ms), "merge_ms_avg": round(sum(merge_ms) / len(merge_ms), 4),
+        "entries_held": held, "min_switches": best[0],
+        "min_equals_unbounded": best == tuple(unbounded_best),
+    }
+    C.close()
+    G.cloud_reset()
+    return out
 
 
 def bench_graphl(fr, synth, torch):
