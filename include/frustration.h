@@ -228,6 +228,39 @@ int fi_batch_create(int32_t G, const int64_t* h_vertex_offsets, const int64_t* h
 int fi_batch_sweep(fi_graph* b, int64_t trees_per_graph, uint64_t seed, uint64_t* d_min_per_graph,
                    uint64_t* d_distinct_per_graph, void* stream);
 
+/* ---------------------------------------------------------------- switch lists and statistics */
+
+/* The upper-triangle edge list: d_uv_out int32[2m] receives (u, v) with
+ * u < v for every undirected edge, in increasing (u, v) order.  Edge e of
+ * fi_sweep_stats and the order of fi_switch_list refer to this list. */
+int fi_edge_list(fi_graph* g, int32_t* d_uv_out, void* stream);
+
+/* The balanced state Sigma' as the list of edges to switch (the paper's
+ * concluding remarks: the method yields the edges to switch).  For a state
+ * d_bits (n bits as uint64[ceil(n/64)], vertex v is bit v%64 of word v/64,
+ * set = -1), every undirected edge (u, v) with sign(u, v) * s_u * s_v = -1:
+ * for a tree's state (fi_tree_state) these are exactly the edges
+ * Alg. alg-balance switches, for a rounded graphL state (fi_round_count)
+ * the edges Alg. alg-gradient flips.  Writes the first min(count, cap)
+ * pairs (u, v), u < v, in edge-list order to d_uv_out int32[2 cap] and the
+ * count to *d_count (device uint64).  Uses the graph's workspace: calls on
+ * one handle must not overlap. */
+int fi_switch_list(fi_graph* g, const uint64_t* d_bits, int32_t* d_uv_out, int64_t cap,
+                   uint64_t* d_count, void* stream);
+
+/* Cloud statistics over trees t0 .. t1-1, each tree counted once, so each
+ * state of the cloud weighs its count C (the frequencies the frustration
+ * cloud keeps for consensus features, Section "The graphL Proof of Concept"):
+ * d_vertex_minus uint64[n] (may be NULL) gets, added to what it holds, the
+ * number of trees whose canonical state (each component's smallest vertex
+ * at +1) puts v at -1; d_edge_switched uint64[m] (may be NULL) gets the
+ * number of trees whose balanced state switches edge e (fi_edge_list
+ * order).  The trees also enter the cloud, as with fi_sweep_range.  Runs on
+ * the multi-tree schedule whatever fi_set_schedule chose (results are the
+ * same on every schedule). */
+int fi_sweep_stats(fi_graph* g, int64_t t0, int64_t t1, uint64_t seed, uint64_t* d_vertex_minus,
+                   uint64_t* d_edge_switched, void* stream);
+
 /* ---------------------------------------------------------------- memory-bound cloud */
 
 /* Alg. alg-scale (appendix, scaling graphBpp for large signed graphs): a

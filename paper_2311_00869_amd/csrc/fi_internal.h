@@ -158,6 +158,10 @@ struct SweepArgs {
   uint64_t* tree_switches;  // [t1 - t0] or null
   uint64_t* bits_out;       // canonical words of the single tree, or null
   int insert;               // 0: compute only, leave the cloud alone
+  // cloud statistics (multi-tree path only): per vertex, trees whose canonical
+  // state puts it at -1; per upper-triangle edge, trees that switch it
+  uint64_t* vminus;
+  uint64_t* eswitch;
   // one-workgroup-per-tree scratch in workspace memory: [slots][slot_stride bytes]
   uint64_t* pw;
   size_t slot_stride;
@@ -182,6 +186,7 @@ struct Layout {
   // multi-tree path: 32-byte per-vertex records, split-row partial minima,
   // vertices listed by component, and root-finding tasks
   size_t mrec, mhslot, mhcap, mreach, aslot, cverts, ccount, cptr, mtasks, mtcap, rootbig, nbigcap;
+  size_t swtile;       // switch lists: per-tile counts and offsets (8 bytes each)
   size_t total;
 };
 
@@ -191,6 +196,7 @@ constexpr int kBigComp = 1024;    // components larger than this find their root
 constexpr int kRootChunk = 1024;  // vertices per root-finding task of a big component
 
 Layout make_layout(int32_t n, int64_t nnz, int64_t cloud_capacity, uint64_t table_size);
+int64_t switch_tiles(int64_t m);  // tiles of the switch-list compaction over m edges
 uint64_t table_size_for(int64_t cloud_capacity);
 
 constexpr int kGraphLMaxR = 64;

@@ -455,6 +455,7 @@ Layout make_layout(int32_t n, int64_t nnz, int64_t cloud_capacity, uint64_t tabl
   L.mtasks = take(16 * L.mtcap);
   L.nbigcap = nn / kBigComp + 1;
   L.rootbig = take(8 * 64 * L.nbigcap);
+  L.swtile = take(16 * ((size_t)switch_tiles((int64_t)m) + 1));
   L.total = off;
   return L;
 }

@@ -88,8 +88,10 @@ int pick_path(fi_graph* g) {
 hipError_t launch_sweep(fi_graph* g, const SweepArgs& a, hipStream_t s) {
   if (a.t1 <= a.t0) return hipSuccess;
   int path = pick_path(g);
-  // the multi-tree path keeps no per-tree state words to hand out
+  // the multi-tree path keeps no per-tree state words to hand out; it alone
+  // gathers the cloud statistics
   if (path == 4 && a.bits_out) path = 3;
+  if (a.vminus || a.eswitch) path = 4;
   const int nt = g->sched.block;
   void* tok = nullptr;
   if (prof_begin(g, s, &tok)) return hipErrorUnknown;
@@ -124,6 +126,22 @@ int fi_sweep_range(fi_graph* g, int64_t t0, int64_t t1, uint64_t seed, uint64_t*
   a.tree_switches = d_tree_switches;
   a.bits_out = nullptr;
   a.insert = 1;
+  return launch_sweep(g, a, (hipStream_t)stream) == hipSuccess ? FI_OK : FI_EDEVICE;
+}
+
+int fi_sweep_stats(fi_graph* g, int64_t t0, int64_t t1, uint64_t seed, uint64_t* d_vertex_minus,
+                   uint64_t* d_edge_switched, void* stream) {
+  if (!g || g->is_batch || t0 < 0 || t1 < t0 || (!d_vertex_minus && !d_edge_switched))
+    return FI_EINVAL;
+  if (t1 > ((int64_t)1 << 32)) return FI_ERANGE;
+  if (t1 == t0) return FI_OK;
+  SweepArgs a{};
+  a.seed = seed;
+  a.t0 = (uint64_t)t0;
+  a.t1 = (uint64_t)t1;
+  a.insert = 1;
+  a.vminus = d_vertex_minus;
+  a.eswitch = d_edge_switched;
   return launch_sweep(g, a, (hipStream_t)stream) == hipSuccess ? FI_OK : FI_EDEVICE;
 }
 

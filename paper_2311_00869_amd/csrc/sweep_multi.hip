@@ -75,6 +75,8 @@ static_assert(kMCtlWords <= kGridSlots * kGridCtlWords, "control block");
 struct MArgs {
   uint64_t seed, t0, t1;
   uint64_t* tree_switches;
+  uint64_t* vminus;      // [n] statistics, or null
+  uint64_t* eswitch;     // [m] statistics, or null
   int insert;
   int32_t ntasks, nbig;
   MState S;              // per-vertex words and bitmaps of the pass
@@ -217,7 +219,7 @@ __device__ __forceinline__ void set_roots(uint64_t best, bool vlane, uint64_t va
   deg += wave_sum_u64(leader ? (uint64_t)dv : 0ull);
 }
 
-template <int NT>
+template <int NT, bool STATS>
 __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
   __shared__ MS<NT> sh;
   constexpr int NW = NT / 64;
@@ -617,6 +619,9 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
           const uint2 uv = G.edges[e];
           x = A.S.stw[uv.x] ^ A.S.stw[uv.y & kVertexMask];
           if (uv.y >> 31) x = ~x;
+          // one owner per edge word in every pass
+          if constexpr (STATS)
+            if (A.eswitch) A.eswitch[e] += (uint64_t)__popcll(x & valid);
         }
 #pragma unroll
         for (int b = 0; b < kPlanes; ++b) {
@@ -636,6 +641,8 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
         const int64_t v = i * 64 + lane;
         uint64_t cs = 0;
         if (v < n) cs = A.S.stw[v] ^ A.S.stw[G.comp[v]];
+        if constexpr (STATS)
+          if (A.vminus && v < n) A.vminus[v] += (uint64_t)__popcll(cs & valid);
         uint64_t W = 0;
         for (int t = 0; t < 64; ++t) {
           const uint64_t b = __ballot((cs >> t) & 1);
@@ -668,10 +675,11 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
   }
 }
 
-template <int NT>
+template <int NT, bool STATS>
 hipError_t launch_mt(fi_graph* g, const MArgs& a, hipStream_t s) {
   int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_multi<NT>, NT, 0);
+  hipError_t e =
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_multi<NT, STATS>, NT, 0);
   if (e != hipSuccess) return e;
   if (per_cu < 1) return hipErrorInvalidConfiguration;
   const int maxg = per_cu * g->cu_count;
@@ -680,7 +688,8 @@ hipError_t launch_mt(fi_graph* g, const MArgs& a, hipStream_t s) {
   DevGraph G = g->dg;
   MArgs A = a;
   void* args[] = {(void*)&G, (void*)&A};
-  e = hipLaunchCooperativeKernel((const void*)k_sweep_multi<NT>, dim3(grid), dim3(NT), args, 0, s);
+  e = hipLaunchCooperativeKernel((const void*)k_sweep_multi<NT, STATS>, dim3(grid), dim3(NT), args,
+                                 0, s);
   if (e != hipSuccess) return e;
   return hipGetLastError();
 }
@@ -695,6 +704,8 @@ hipError_t launch_multi(fi_graph* g, const SweepArgs& sa, hipStream_t s) {
   a.t0 = sa.t0;
   a.t1 = sa.t1;
   a.tree_switches = sa.tree_switches;
+  a.vminus = sa.vminus;
+  a.eswitch = sa.eswitch;
   a.insert = sa.insert;
   a.ntasks = g->mtasks;
   a.nbig = g->mnbig;
@@ -721,8 +732,11 @@ hipError_t launch_multi(fi_graph* g, const SweepArgs& sa, hipStream_t s) {
   a.ctl = (uint64_t*)(ws + L.gctl);
   a.bar = (uint64_t*)(ws + L.gbar);
   const int nt = g->sched.block;
-  return nt == 1024 ? launch_mt<1024>(g, a, s) : nt == 512 ? launch_mt<512>(g, a, s)
-                                                           : launch_mt<256>(g, a, s);
+  if (a.vminus || a.eswitch)
+    return nt == 1024 ? launch_mt<1024, true>(g, a, s) : nt == 512 ? launch_mt<512, true>(g, a, s)
+                                                                   : launch_mt<256, true>(g, a, s);
+  return nt == 1024 ? launch_mt<1024, false>(g, a, s) : nt == 512 ? launch_mt<512, false>(g, a, s)
+                                                                  : launch_mt<256, false>(g, a, s);
 }
 
 }  // namespace fi

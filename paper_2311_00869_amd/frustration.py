@@ -32,7 +32,7 @@ SYMBOLS = (
     "fi_get_schedule", "fi_prof_enable", "fi_prof_read", "fi_strerror",
     "fi_bcloud_workspace_size", "fi_bcloud_fmax_for", "fi_bcloud_create", "fi_bcloud_destroy",
     "fi_bcloud_reset", "fi_bcloud_merge", "fi_sweep_bounded", "fi_bcloud_size", "fi_bcloud_read",
-    "fi_bcloud_min", "fi_bcloud_stats",
+    "fi_bcloud_min", "fi_bcloud_stats", "fi_edge_list", "fi_switch_list", "fi_sweep_stats",
 )
 
 
@@ -108,6 +108,9 @@ def load_library(path: str = LIB_PATH):
             "fi_bcloud_read": ([vp, vp, i64, P(i64), vp], c.c_int),
             "fi_bcloud_min": ([vp, P(u64), P(u64), vp], c.c_int),
             "fi_bcloud_stats": ([vp, P(i64), P(i64), vp], c.c_int),
+            "fi_edge_list": ([vp, vp, vp], c.c_int),
+            "fi_switch_list": ([vp, vp, vp, i64, vp, vp], c.c_int),
+            "fi_sweep_stats": ([vp, i64, i64, u64, vp, vp, vp], c.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -246,6 +249,37 @@ class Graph:
         _check(self.lib.fi_sweep_bounded(self.handle, cloud.handle, int(t0), int(t1),
                                          seed & (2**64 - 1), int(chunk), _stream_ptr(stream)),
                "sweep_bounded")
+
+    def edge_list(self, stream=None):
+        """int32 [m, 2]: the undirected edges (u < v) in increasing order."""
+        out = torch.empty((max(self.m, 1), 2), dtype=torch.int32, device=self.device)
+        _check(self.lib.fi_edge_list(self.handle, _ptr(out), _stream_ptr(stream)), "edge_list")
+        return out[: self.m]
+
+    def switch_list(self, bits, cap=None, stream=None):
+        """Edges a state frustrates (the edges to switch), int32 [k, 2] in
+        edge-list order.  ``bits``: int64 device words, set bit = -1."""
+        b = bits.to(device=self.device, dtype=torch.int64).contiguous()
+        cap = self.m if cap is None else int(cap)
+        out = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=self.device)
+        cnt = torch.zeros(1, dtype=torch.int64, device=self.device)
+        _check(self.lib.fi_switch_list(self.handle, _ptr(b), _ptr(out), cap, _ptr(cnt),
+                                       _stream_ptr(stream)), "switch_list")
+        k = int(cnt.item())
+        return out[: min(k, cap)], k
+
+    def sweep_stats(self, t0: int, t1: int, seed: int, vertex_minus=None, edge_switched=None,
+                    stream=None):
+        """Trees t0 .. t1-1 into the cloud, adding per-vertex and per-edge
+        counts to the given int64 tensors (new zero tensors if None)."""
+        if vertex_minus is None:
+            vertex_minus = torch.zeros(max(self.n, 1), dtype=torch.int64, device=self.device)
+        if edge_switched is None:
+            edge_switched = torch.zeros(max(self.m, 1), dtype=torch.int64, device=self.device)
+        _check(self.lib.fi_sweep_stats(self.handle, int(t0), int(t1), seed & (2**64 - 1),
+                                       _ptr(vertex_minus), _ptr(edge_switched),
+                                       _stream_ptr(stream)), "sweep_stats")
+        return vertex_minus[: self.n], edge_switched[: self.m]
 
     def cloud_reset(self, stream=None):
         _check(self.lib.fi_cloud_reset(self.handle, _stream_ptr(stream)), "cloud_reset")

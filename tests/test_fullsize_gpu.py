@@ -64,6 +64,24 @@ def test_large_graph_bench_configuration():
     trees, dropped = C.stats()
     assert trees == 192 and dropped >= len(full) - 50
     C.close()
+    # cloud statistics and the switch list at full size, by properties
+    G.cloud_reset()
+    sw = G.sweep_range(0, 64, 3, tree_switches=True)
+    G.cloud_reset()
+    vm, es = G.sweep_stats(0, 64, 3)
+    assert int(es.sum()) == int(sw.sum())
+    assert int(vm[0]) == 0 and int(vm.max()) <= 64 and int(es.max()) <= 64
+    lst, k = G.switch_list(torch.from_numpy(words.view(np.int64)).cuda())
+    assert k == gold["trees"][0][0] == len(lst)
+    lst = lst.cpu().numpy().astype(np.int64)
+    assert np.all(np.diff(lst[:, 0] * g.n + lst[:, 1]) > 0)
+    pick = np.random.default_rng(0).choice(len(lst), 2000, replace=False)
+    bit = lambda x: (words[x // 64] >> (x % 64).astype(np.uint64)) & np.uint64(1)
+    u, v = lst[pick, 0], lst[pick, 1]
+    rows = [np.searchsorted(g.col[g.row_ptr[a]:g.row_ptr[a + 1]], b) + g.row_ptr[a]
+            for a, b in zip(u, v)]
+    neg = (g.sign[rows] < 0).astype(np.uint64)
+    assert np.all(neg ^ bit(u) ^ bit(v) == 1)
     G.close()
 
 
