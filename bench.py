@@ -77,6 +77,8 @@ def main():
     ap.add_argument("--no-planted", action="store_true", help="skip the 10^4-tree planted leg")
     ap.add_argument("--no-bounded", action="store_true",
                     help="skip the memory-bound cloud leg (Alg. alg-scale)")
+    ap.add_argument("--no-switches", action="store_true",
+                    help="skip the switch-list and cloud-statistics leg")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy this many MiB device to device (a kernel of known traffic "
                          "for scaling hardware byte counters)")
@@ -180,6 +182,8 @@ def main():
     extra = {}
     if not args.no_bounded:
         extra["bounded"] = bench_bounded(fr, torch, G, T, args.steps, best)
+    if not args.no_switches:
+        extra["switches"] = bench_switches(fr, torch, G, T, args.steps, elapsed / args.steps)
     if not args.no_plain:
         # the plain per-tree path: one launch per tree, one tree in flight
         # (whole-grid path, no batching of trees)
@@ -269,6 +273,50 @@ def bench_bounded(fr, torch, G, T, steps, unbounded_best, fmax=100, chunk=250):
     C.close()
     G.cloud_reset()
     return out
+
+
+def bench_switches(fr, torch, G, T, steps, plain_step_s):
+    """The balanced state as a list of edges to switch (one tree's state, the
+    whole edge list compacted in order), and a sweep that also gathers the
+    per-vertex and per-edge tree counts, against the plain sweep's step."""
+    import numpy as np
+    words, s0 = G.tree_state(0, 0)
+    bits = torch.from_numpy(words.view(np.int64)).cuda()
+    out = torch.empty((s0 + 1, 2), dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    lib, st = G.lib, fr._stream_ptr()
+    call = lambda: lib.fi_switch_list(G.handle, fr._ptr(bits), fr._ptr(out), s0 + 1, fr._ptr(cnt), st)
+    call()
+    torch.cuda.synchronize()
+    reps = 20
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        call()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    assert int(cnt.item()) == s0
+    # two passes over the 8-byte edge list, the pairs written, the state read twice
+    nbytes = 2 * 8 * G.m + 8 * s0 + 2 * G.n // 8
+    vm = torch.zeros(G.n, dtype=torch.int64, device="cuda")
+    es = torch.zeros(G.m, dtype=torch.int64, device="cuda")
+    G.cloud_reset()
+    G.sweep_stats(0, 64, 999, vm, es)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        G.cloud_reset()
+        G.sweep_stats(0, T, s, vm, es)
+    G.min_frustration()
+    el = (time.perf_counter() - t0) / steps
+    G.cloud_reset()
+    return {
+        "switch_list": {"edges_switched": s0, "ms": round(ms, 3),
+                        "algorithmic_bytes": nbytes, "GB_per_s": round(nbytes / ms / 1e6, 1)},
+        "stats_sweep": {"trees_per_s": round(T / el, 2), "ms_per_step": round(el * 1e3, 3),
+                        "vs_plain_sweep": round(plain_step_s / el, 4)},
+    }
 
 
 def bench_graphl(fr, synth, torch):

@@ -32,16 +32,35 @@ __device__ __forceinline__ uint32_t frustrated(const uint2 uv, const uint64_t* b
   return (uv.y >> 31) ^ bu ^ bv;
 }
 
+// Bit r of the result: edge base + r * kBlock + threadIdx.x is frustrated.
+// All kRounds edge loads are issued before the state gathers that depend on
+// them, so each thread has kRounds independent chains in flight.
+__device__ __forceinline__ uint32_t tile_flags(const uint2* edges, int64_t m, int64_t base,
+                                               const uint64_t* bits, uint2* uv) {
+  // the edge list streams once: non-temporal loads keep the state bitmap,
+  // which every edge gathers from twice, resident in L2
+  const uint64_t* ev = reinterpret_cast<const uint64_t*>(edges);
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const int64_t e = base + r * kBlock + threadIdx.x;
+    const uint64_t w = e < m ? __builtin_nontemporal_load(ev + e) : 0ull;
+    uv[r] = make_uint2((uint32_t)w, (uint32_t)(w >> 32));
+  }
+  uint32_t f = 0;
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const int64_t e = base + r * kBlock + threadIdx.x;
+    if (e < m) f |= frustrated(uv[r], bits) << r;
+  }
+  return f;
+}
+
 __global__ void __launch_bounds__(kBlock) k_sw_count(const uint2* edges, int64_t m,
                                                       const uint64_t* bits, uint32_t* tile_cnt) {
   __shared__ uint64_t s_tmp[kBlock / 64];
-  const int64_t base = (int64_t)blockIdx.x * kTile;
-  uint64_t c = 0;
-  for (int r = 0; r < kRounds; ++r) {
-    const int64_t e = base + r * kBlock + threadIdx.x;
-    if (e < m) c += frustrated(edges[e], bits);
-  }
-  const uint64_t tot = block_sum_u64<kBlock>(c, s_tmp);
+  uint2 uv[kRounds];
+  const uint32_t f = tile_flags(edges, m, (int64_t)blockIdx.x * kTile, bits, uv);
+  const uint64_t tot = block_sum_u64<kBlock>((uint64_t)__popc(f), s_tmp);
   if (threadIdx.x == 0) tile_cnt[blockIdx.x] = (uint32_t)tot;
 }
 
@@ -84,33 +103,33 @@ __global__ void __launch_bounds__(kScanThreads) k_sw_scan(const uint32_t* tile_c
 __global__ void __launch_bounds__(kBlock) k_sw_write(const uint2* edges, int64_t m,
                                                       const uint64_t* bits, const uint64_t* tile_off,
                                                       int32_t* out, int64_t cap) {
-  __shared__ uint32_t s_w[kBlock / 64];
-  const int64_t base = (int64_t)blockIdx.x * kTile;
+  __shared__ uint32_t s_w[kRounds][kBlock / 64];
   const int lane = lane_id(), w = threadIdx.x >> 6;
-  uint64_t off = tile_off[blockIdx.x];
+  uint2 uv[kRounds];
+  const uint32_t f = tile_flags(edges, m, (int64_t)blockIdx.x * kTile, bits, uv);
+  uint64_t mask[kRounds];
+#pragma unroll
   for (int r = 0; r < kRounds; ++r) {
-    const int64_t e = base + r * kBlock + threadIdx.x;
-    uint2 uv = make_uint2(0, 0);
-    uint32_t f = 0;
-    if (e < m) {
-      uv = edges[e];
-      f = frustrated(uv, bits);
-    }
-    const uint64_t mask = __ballot(f);
-    if (lane == 0) s_w[w] = (uint32_t)__popcll(mask);
-    __syncthreads();
+    mask[r] = __ballot((f >> r) & 1u);
+    if (lane == 0) s_w[r][w] = (uint32_t)__popcll(mask[r]);
+  }
+  __syncthreads();
+  // edges are ordered by (round, wave, lane) inside the tile
+  uint64_t off = tile_off[blockIdx.x];
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
     uint32_t before = 0, round = 0;
+#pragma unroll
     for (int i = 0; i < kBlock / 64; ++i) {
-      const uint32_t c = s_w[i];
-      if (i < w) before += c;
+      const uint32_t c = s_w[r][i];
+      before += i < w ? c : 0u;
       round += c;
     }
-    __syncthreads();  // s_w is rewritten next round
-    if (f) {
-      const uint64_t at = off + before + lanes_below(mask);
+    if ((f >> r) & 1u) {
+      const uint64_t at = off + before + lanes_below(mask[r]);
       if ((int64_t)at < cap) {
-        out[2 * at] = (int32_t)uv.x;
-        out[2 * at + 1] = (int32_t)(uv.y & kVertexMask);
+        out[2 * at] = (int32_t)uv[r].x;
+        out[2 * at + 1] = (int32_t)(uv[r].y & kVertexMask);
       }
     }
     off += round;
