@@ -39,6 +39,19 @@ def grad(g, gamma):
     return out
 
 
+def grad_rows(g, gamma, rows):
+    """dL/dG for the given vertices only, [len(rows), R], from their CSR rows
+    (the same gradient, for sampling outputs of a large graph)."""
+    G = np.asarray(gamma)
+    out = np.zeros((len(rows), G.shape[1]), np.float64)
+    for k, i in enumerate(rows):
+        a, b = int(g.row_ptr[i]), int(g.row_ptr[i + 1])
+        nb = g.col[a:b].astype(np.int64)
+        e = g.sign[a:b].astype(np.float64)
+        out[k] = -0.5 * (e[:, None] * G[nb].astype(np.float64)).sum(axis=0)
+    return out
+
+
 def descent(g, gamma0, steps: int, alpha: float):
     """The update loop of Alg. alg-gradient; returns the final G (float64)."""
     G = np.asarray(gamma0, dtype=np.float64).copy()

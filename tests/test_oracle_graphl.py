@@ -61,3 +61,34 @@ def test_gradient_symmetric_operator(g200):
 def test_rounding_threshold_at_zero():
     G = np.array([[0.0], [-0.0], [1e-30], [-1e-30], [5.0]])
     assert graphl.round_states(G)[:, 0].tolist() == [1, 1, 1, -1, 1]
+
+
+def test_sampled_rows_are_the_central_differences(g200):
+    # the row form of the gradient, pinned the same way as the full one
+    G = synth.graphl_init(g200.n, 4, 9).astype(np.float64)
+    rows = [0, 3, 57, 123, 199]
+    gr = graphl.grad_rows(g200, G, rows)
+    h = 2.0 ** -8
+    for k, i in enumerate(rows):
+        Gp, Gm = G.copy(), G.copy()
+        Gp[i] += h
+        Gm[i] -= h
+        fd = (graphl.loss(g200, Gp) - graphl.loss(g200, Gm)) / (2 * h)
+        np.testing.assert_allclose(fd, gr[k], rtol=0, atol=1e-9)
+
+
+def test_descent_growth_bound_and_scale_invariance():
+    # each update is G <- (I + alpha/2 A) G with A the signed adjacency, so
+    # |G| grows at most by (1 + alpha * rho(A) / 2) per step, and scaling
+    # G_0 by a power of two scales every iterate by it exactly
+    g = synth.chung_lu(3000, 15000, 2.1, 4, p_pos=0.6)
+    G0 = synth.graphl_init(g.n, 3, 2).astype(np.float64)
+    alpha, steps = 0.05, 40
+    Gk = graphl.descent(g, G0, steps, alpha)
+    A = graphl.signed_adjacency(g)
+    rho = np.abs(np.linalg.eigvalsh(A.toarray() if hasattr(A, "toarray") else A)).max()
+    bound = (1 + alpha * rho / 2) ** steps
+    assert np.linalg.norm(Gk, axis=0).max() <= bound * np.linalg.norm(G0, axis=0).max() * (1 + 1e-9)
+    assert np.linalg.norm(Gk, axis=0).max() > 1e6  # the hub makes it grow fast
+    G2 = graphl.descent(g, np.ldexp(G0, -20), steps, alpha)
+    assert np.array_equal(np.ldexp(G2, 20), Gk)
