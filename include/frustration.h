@@ -183,6 +183,37 @@ int fi_graphl_backward(fi_graph* g, const float* d_gamma, int32_t R, const doubl
 int fi_graphl_step(fi_graph* g, const float* d_gamma_in, int32_t R, float alpha,
                    float* d_gamma_out, void* stream);
 
+/* Bytes of the caller's buffer that fi_graphl_descend keeps its scales in,
+ * for R restarts: 16 B per (component with an edge, restart). */
+int fi_graphl_aux_size(fi_graph* g, int32_t R, size_t* out_bytes);
+
+/* Alg. alg-gradient's update loop, `steps` steps for all restarts, with an
+ * overflow policy for large graphs.  Each step multiplies Gamma by
+ * (I + alpha/2 * A_signed), which grows by up to (1 + alpha * lambda_max / 2)
+ * per step; power-law hubs make lambda_max large enough to overflow float32
+ * in a few hundred steps, while small components barely grow.  Every
+ * (connected component, restart) pair keeps its own power-of-two scale:
+ * whenever the pair's largest |Gamma| reached 2^rescale_log2 (0 = 64;
+ * 1 .. 100) after a step, the next step reads the pair scaled by
+ * 2^-rescale_log2 and adds rescale_log2 to its log2 scale.  The true
+ * iterate is d_gamma[i][r] * 2^scale(i, r) (fi_graphl_scales); scaling by a
+ * power of two is exact, so the stored iterates are the plain descent's bit
+ * for bit up to that factor (unless an entry falls 2^-149 below its own
+ * component's largest), and the rounded states of the final loop are
+ * unchanged.  d_gamma float32[n][R] holds Gamma_0 on entry and the result
+ * on return; d_work is a buffer of the same size (no overlap); d_aux
+ * (fi_graphl_aux_size bytes, 256-byte aligned) receives the scales and is
+ * overwritten by each call.  Rows of more than 1,024 entries are summed by a
+ * whole workgroup in a fixed order; results are deterministic.  Kernels and
+ * one device copy only. */
+int fi_graphl_descend(fi_graph* g, float* d_gamma, float* d_work, int32_t R, float alpha,
+                      int64_t steps, int32_t rescale_log2, void* d_aux, size_t aux_bytes,
+                      void* stream);
+
+/* The log2 scale of every vertex and restart after fi_graphl_descend:
+ * d_out int32[n][R] (0 for vertices without edges). */
+int fi_graphl_scales(fi_graph* g, const void* d_aux, int32_t R, int32_t* d_out, void* stream);
+
 /* Alg. alg-gradient's final loop: theta = +1 where Gamma >= 0 else -1, then
  * the exact frustration count of every restart: d_counts uint64[R].
  * d_bits_out (uint64[R][ceil(n/64)], set = -1) receives the rounded states

@@ -187,6 +187,8 @@ struct Layout {
   // vertices listed by component, and root-finding tasks
   size_t mrec, mhslot, mhcap, mreach, aslot, cverts, ccount, cptr, mtasks, mtcap, rootbig, nbigcap;
   size_t swtile;       // switch lists: per-tile counts and offsets (8 bytes each)
+  size_t glheavy;      // graphL: rows longer than kGLHeavy
+  size_t glctl;        // graphL: the heavy-row count
   size_t total;
 };
 
@@ -201,6 +203,7 @@ uint64_t table_size_for(int64_t cloud_capacity);
 
 constexpr int kGraphLMaxR = 64;
 constexpr int kGraphLBlocks = 1024;
+constexpr int kGLHeavy = 1024;  // graphL rows longer than this go one per workgroup
 
 // profiling events around one launch (no-ops unless profiling is on)
 void batch_info_free(void* p);
@@ -227,6 +230,8 @@ struct fi_graph {
   uint64_t table_size;
   int32_t ncomp, nisolated, nanch;
   int32_t mtasks, mnbig;  // multi-tree path: root-finding tasks, big components
+  bool gl_heavy_built;    // graphL heavy-row list is in the workspace
+  int32_t gl_main_slot;   // slot of the component with the most vertices (-1: none)
   fi_schedule sched;
   int cu_count;
   int max_shared;

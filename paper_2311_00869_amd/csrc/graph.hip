@@ -456,6 +456,8 @@ Layout make_layout(int32_t n, int64_t nnz, int64_t cloud_capacity, uint64_t tabl
   L.nbigcap = nn / kBigComp + 1;
   L.rootbig = take(8 * 64 * L.nbigcap);
   L.swtile = take(16 * ((size_t)switch_tiles((int64_t)m) + 1));
+  L.glheavy = take(4 * ((size_t)nnz / kGLHeavy + 2));
+  L.glctl = take(64);
   L.total = off;
   return L;
 }
@@ -477,6 +479,7 @@ int build_components(fi_graph* g, hipStream_t s) {
   const int32_t nanch = (int32_t)nanch64;
   int32_t* aslot = (int32_t*)(ws + L.aslot);
   int32_t* count = (int32_t*)(ws + L.ccount);
+  g->gl_main_slot = -1;
   int32_t* cptr = (int32_t*)(ws + L.cptr);
   std::vector<int32_t> cnt(nanch), ptr(nanch + 1, 0);
   std::vector<int4> tasks;
@@ -490,6 +493,7 @@ int build_components(fi_graph* g, hipStream_t s) {
         hipStreamSynchronize(s) != hipSuccess)
       return FI_EDEVICE;
     for (int32_t i = 0; i < nanch; ++i) {
+      if (g->gl_main_slot < 0 || cnt[i] > cnt[g->gl_main_slot]) g->gl_main_slot = i;
       ptr[i + 1] = ptr[i] + cnt[i];
       if (cnt[i] <= kBigComp) {
         tasks.push_back(make_int4(ptr[i], ptr[i + 1], -1, 0));

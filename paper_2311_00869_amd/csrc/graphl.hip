@@ -63,30 +63,182 @@ __global__ void k_gl_forward_final(const double* part, int nblocks, int R, doubl
   loss[r] = s;
 }
 
-// Row gather: g[i][r] = -1/2 * w_r * sum over the row of e_ij G[j][r]
-// (float32 accumulation along the row, in CSR order).  With `alpha` != 0
-// the kernel writes the descent update G - alpha * g instead of g.
+// Row gathers: g[i][r] = -1/2 * w_r * sum over the row of e_ij G[j][r].
+// With `update` the kernels write the descent update G - alpha * g instead.
+// Rows of up to kGLHeavy entries: one row per group of lanes, float32
+// accumulation in CSR order.  Longer rows (power-law hubs): one row per
+// workgroup, the groups striding over the row and their partial sums added
+// in group order.  Either way every row's summation order is fixed, so the
+// result is bit-reproducible.
+//
+// Overflow policy of the descent (graphs whose hubs make the update grow by
+// up to (1 + alpha * lambda_max / 2) per step).  The update never mixes
+// connected components, and components grow at very different rates (a hub
+// component by many orders of magnitude more than a two-vertex one), so
+// each (component, restart) pair keeps its own power-of-two scale: when the
+// pair's largest |G| reached 2^shift after the previous step, this step
+// reads the pair's entries scaled by 2^-shift and adds shift to its log2
+// scale.  Scaling by a power of two is exact in floating point, so each
+// component's stored iterates are the plain descent's times 2^-scale, bit
+// for bit, unless an entry falls 2^-149 below its own component's largest.
+// Vertices without edges never change and keep scale 0.
+struct RowArgs {
+  const double* w;          // gradient weights per restart, or null (1)
+  float alpha;
+  int update;
+  // descent with scaling (all null for a plain step or gradient)
+  const int32_t* comp;      // anchor of each vertex's component
+  const int32_t* aslot;     // component slot of each anchor
+  const uint32_t* max_in;   // [C][R] float bits of max |G_in|
+  uint32_t* max_out;        // [C][R] max |G_out| (atomic max)
+  uint32_t* max_clear;      // [C][R] the buffer the step after next fills
+  int32_t* exps;            // [C][R] log2 scales
+  int64_t ncr;              // C * R
+  int32_t main_slot;        // the largest component: its maxima are combined per block
+  int shift;                // rescale threshold and step, log2
+};
+
+__device__ __forceinline__ float pair_scale(const RowArgs& A, int32_t c, int R, int sub) {
+  if (c < 0) return 1.0f;
+  const uint32_t thresh = (uint32_t)(127 + A.shift) << 23;  // 2^shift
+  return A.max_in[(size_t)c * R + sub] >= thresh ? __uint_as_float((uint32_t)(127 - A.shift) << 23)
+                                                 : 1.0f;
+}
+
+// After a row's output v of restart `sub`: its component's maximum and, on
+// the component's anchor row, the scale.
+__device__ __forceinline__ void note_row(const RowArgs& A, int64_t i, int32_t c, int R, int sub,
+                                         float sc, float v, float& mx_main) {
+  if (c < 0) return;
+  const float a = fabsf(v);
+  if (c == A.main_slot) mx_main = fmaxf(mx_main, a);
+  else atomicMax((unsigned int*)&A.max_out[(size_t)c * R + sub], __float_as_uint(a));
+  if (A.comp[i] == i && sc != 1.0f) A.exps[(size_t)c * R + sub] += A.shift;
+}
+
+__device__ __forceinline__ void block_max_main(const RowArgs& A, float mx, float* s_mx, int P,
+                                               int R, int sub, int grp, int gpb, bool active) {
+  s_mx[threadIdx.x] = mx;
+  __syncthreads();
+  if (grp == 0 && active && A.main_slot >= 0) {
+    float m = 0.0f;
+    for (int g = 0; g < gpb; ++g) m = fmaxf(m, s_mx[g * P + sub]);
+    if (m > 0.0f)
+      atomicMax((unsigned int*)&A.max_out[(size_t)A.main_slot * R + sub], __float_as_uint(m));
+  }
+}
+
+__device__ __forceinline__ int32_t row_slot(const RowArgs& A, int64_t i, int64_t e0, int64_t e1) {
+  return e1 > e0 ? A.aslot[A.comp[i]] : -1;
+}
+
 __global__ void __launch_bounds__(kGLBlock) k_gl_rows(const int32_t* rp, const uint32_t* adj,
                                                       int32_t n, const float* gamma, int R,
-                                                      const double* w, float alpha, int update,
-                                                      float* out) {
+                                                      RowArgs A, float* out) {
+  __shared__ float s_mx[kGLBlock];
   const int P = lanes_for(R);
   const int sub = threadIdx.x % P;
   const int grp = threadIdx.x / P;
   const int gpb = kGLBlock / P;
-  if (sub >= R) return;
-  const float wr = w ? (float)w[sub] : 1.0f;
-  for (int64_t i = (int64_t)blockIdx.x * gpb + grp; i < n; i += (int64_t)gridDim.x * gpb) {
-    float acc = 0.0f;
-    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
-      const uint32_t a = adj[e];
-      const float gj = gamma[(size_t)(a & kVertexMask) * R + sub];
-      acc += (a >> 31) ? -gj : gj;
+  const bool active = sub < R;
+  const bool scaled = A.max_in != nullptr;
+  const float wr = (A.w && active) ? (float)A.w[sub] : 1.0f;
+  if (scaled)
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < A.ncr;
+         k += (int64_t)gridDim.x * blockDim.x)
+      A.max_clear[k] = 0;
+  float mx_main = 0.0f;
+  if (active) {
+    for (int64_t i = (int64_t)blockIdx.x * gpb + grp; i < n; i += (int64_t)gridDim.x * gpb) {
+      const int64_t e0 = rp[i], e1 = rp[i + 1];
+      if (e1 - e0 > kGLHeavy) continue;
+      const int32_t c = scaled ? row_slot(A, i, e0, e1) : -1;
+      const float sc = scaled ? pair_scale(A, c, R, sub) : 1.0f;
+      float acc = 0.0f;
+      for (int64_t e = e0; e < e1; ++e) {
+        const uint32_t a = adj[e];
+        const float gj = gamma[(size_t)(a & kVertexMask) * R + sub] * sc;
+        acc += (a >> 31) ? -gj : gj;
+      }
+      const float g = -0.5f * acc * wr;
+      const size_t o = (size_t)i * R + sub;
+      const float v = A.update ? gamma[o] * sc - A.alpha * g : g;
+      out[o] = v;
+      if (scaled) note_row(A, i, c, R, sub, sc, v, mx_main);
     }
-    const float g = -0.5f * acc * wr;
-    const size_t o = (size_t)i * R + sub;
-    out[o] = update ? gamma[o] - alpha * g : g;
   }
+  if (scaled) block_max_main(A, mx_main, s_mx, P, R, sub, grp, gpb, active);
+}
+
+__global__ void __launch_bounds__(kGLBlock) k_gl_heavy(const int32_t* rp, const uint32_t* adj,
+                                                       const int32_t* list, const uint32_t* count,
+                                                       const float* gamma, int R, RowArgs A,
+                                                       float* out) {
+  __shared__ float s_part[kGLBlock];
+  const int P = lanes_for(R);
+  const int sub = threadIdx.x % P;
+  const int grp = threadIdx.x / P;
+  const int gpb = kGLBlock / P;
+  const bool active = sub < R;
+  const bool scaled = A.max_in != nullptr;
+  const float wr = (A.w && active) ? (float)A.w[sub] : 1.0f;
+  const uint32_t cnt = *count;
+  float mx_main = 0.0f;
+  for (uint32_t h = blockIdx.x; h < cnt; h += gridDim.x) {
+    const int64_t i = list[h];
+    const int64_t e0 = rp[i], e1 = rp[i + 1];
+    const int32_t c = scaled ? row_slot(A, i, e0, e1) : -1;
+    const float sc = (scaled && active) ? pair_scale(A, c, R, sub) : 1.0f;
+    float acc = 0.0f;
+    if (active) {
+      for (int64_t e = e0 + grp; e < e1; e += gpb) {
+        const uint32_t a = adj[e];
+        const float gj = gamma[(size_t)(a & kVertexMask) * R + sub] * sc;
+        acc += (a >> 31) ? -gj : gj;
+      }
+    }
+    s_part[threadIdx.x] = acc;
+    __syncthreads();
+    if (grp == 0 && active) {
+      float tot = 0.0f;
+      for (int g = 0; g < gpb; ++g) tot += s_part[g * P + sub];
+      const float g = -0.5f * tot * wr;
+      const size_t o = (size_t)i * R + sub;
+      const float v = A.update ? gamma[o] * sc - A.alpha * g : g;
+      out[o] = v;
+      if (scaled) note_row(A, i, c, R, sub, sc, v, mx_main);
+    }
+    __syncthreads();
+  }
+  if (scaled) block_max_main(A, mx_main, s_part, P, R, sub, grp, gpb, active);
+}
+
+// Per-vertex log2 scales of a descent: out[i][r] = the scale of (component
+// of i, r), 0 for vertices without edges.
+__global__ void k_gl_scales(const int32_t* rp, const int32_t* comp, const int32_t* aslot,
+                            int32_t n, const int32_t* exps, int R, int32_t* out) {
+  const int64_t total = (int64_t)n * R;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < total;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = k / R;
+    const int r = (int)(k - i * R);
+    out[k] = rp[i + 1] > rp[i] ? exps[(size_t)aslot[comp[i]] * R + r] : 0;
+  }
+}
+
+// Rows longer than kGLHeavy, in any order (each is summed on its own).
+__global__ void k_gl_heavy_list(const int32_t* rp, int32_t n, int32_t* list, uint32_t* count) {
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x; b < n; b += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = b + threadIdx.x;
+    const bool heavy = i < n && rp[i + 1] - rp[i] > kGLHeavy;
+    wave_append(heavy, (int32_t)i, list, count);
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t len, uint32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
 }
 
 // theta = +1 where Gamma >= 0, else -1; bit set = -1.  One wave per
@@ -119,11 +271,46 @@ int rows_grid(int32_t n, int R) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, 65536));
 }
 
+// graphL control words in the workspace: the heavy-row count
+uint32_t* gl_ctl(fi_graph* g) { return (uint32_t*)(g->ws + g->L.glctl); }
+
+// Descent scales in the caller's buffer: exponents, then three max buffers,
+// each [C][R] 32-bit words (C = components with an edge, at least 1).
+size_t aux_part(const fi_graph* g, int R) {
+  const size_t c = (size_t)std::max<int32_t>(g->nanch, 1);
+  return (4 * c * (size_t)R + 255) / 256 * 256;
+}
+
+hipError_t launch_rows(fi_graph* g, const float* gin, int R, const RowArgs& A, float* out,
+                       hipStream_t s) {
+  const int64_t hcap = g->dg.nnz / kGLHeavy + 1;
+  int32_t* list = (int32_t*)(g->ws + g->L.glheavy);
+  uint32_t* count = gl_ctl(g);
+  if (!g->gl_heavy_built) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, count, (int64_t)1, 0u);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)g->dg.n + 255) / 256, 16384));
+    hipLaunchKernelGGL(k_gl_heavy_list, dim3(grid), dim3(256), 0, s, g->dg.row_ptr, g->dg.n, list,
+                       count);
+    g->gl_heavy_built = true;
+  }
+  hipLaunchKernelGGL(k_gl_rows, dim3(rows_grid(g->dg.n, R)), dim3(kGLBlock), 0, s, g->dg.row_ptr,
+                     g->dg.adj, g->dg.n, gin, R, A, out);
+  const int hgrid = (int)std::min<int64_t>(hcap, 2048);
+  hipLaunchKernelGGL(k_gl_heavy, dim3(hgrid), dim3(kGLBlock), 0, s, g->dg.row_ptr, g->dg.adj, list,
+                     count, gin, R, A, out);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 }  // namespace fi
 
 using namespace fi;
+
+#define FI_HIP(call)                              \
+  do {                                            \
+    if ((call) != hipSuccess) return FI_EDEVICE;  \
+  } while (0)
 
 extern "C" {
 
@@ -144,10 +331,11 @@ int fi_graphl_backward(fi_graph* g, const float* d_gamma, int32_t R, const doubl
   if (!g || g->is_batch || R < 1 || R > kGraphLMaxR) return FI_EINVAL;
   if (g->dg.n == 0) return FI_OK;
   if (!d_gamma || !d_grad_gamma) return FI_EINVAL;
-  hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_gl_rows, dim3(rows_grid(g->dg.n, R)), dim3(kGLBlock), 0, s, g->dg.row_ptr,
-                     g->dg.adj, g->dg.n, d_gamma, (int)R, d_grad_loss, 0.0f, 0, d_grad_gamma);
-  return hipGetLastError() == hipSuccess ? FI_OK : FI_EDEVICE;
+  RowArgs A{};
+  A.w = d_grad_loss;
+  A.update = 0;
+  return launch_rows(g, d_gamma, R, A, d_grad_gamma, (hipStream_t)stream) == hipSuccess ? FI_OK
+                                                                                        : FI_EDEVICE;
 }
 
 int fi_graphl_step(fi_graph* g, const float* d_gamma_in, int32_t R, float alpha,
@@ -155,10 +343,66 @@ int fi_graphl_step(fi_graph* g, const float* d_gamma_in, int32_t R, float alpha,
   if (!g || g->is_batch || R < 1 || R > kGraphLMaxR) return FI_EINVAL;
   if (g->dg.n == 0) return FI_OK;
   if (!d_gamma_in || !d_gamma_out || d_gamma_in == d_gamma_out) return FI_EINVAL;
+  RowArgs A{};
+  A.alpha = alpha;
+  A.update = 1;
+  return launch_rows(g, d_gamma_in, R, A, d_gamma_out, (hipStream_t)stream) == hipSuccess
+             ? FI_OK
+             : FI_EDEVICE;
+}
+
+int fi_graphl_aux_size(fi_graph* g, int32_t R, size_t* out_bytes) {
+  if (!g || g->is_batch || R < 1 || R > kGraphLMaxR || !out_bytes) return FI_EINVAL;
+  *out_bytes = 4 * aux_part(g, R);
+  return FI_OK;
+}
+
+int fi_graphl_descend(fi_graph* g, float* d_gamma, float* d_work, int32_t R, float alpha,
+                      int64_t steps, int32_t rescale_log2, void* d_aux, size_t aux_bytes,
+                      void* stream) {
+  if (!g || g->is_batch || R < 1 || R > kGraphLMaxR || steps < 0) return FI_EINVAL;
+  if (rescale_log2 == 0) rescale_log2 = 64;
+  if (rescale_log2 < 1 || rescale_log2 > 100) return FI_EINVAL;
+  const size_t part = aux_part(g, R);
+  if (!d_aux || aux_bytes < 4 * part || ((uintptr_t)d_aux % 256)) return FI_EWORKSPACE;
+  if (g->dg.n > 0 && (!d_gamma || !d_work || d_gamma == d_work)) return FI_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_gl_rows, dim3(rows_grid(g->dg.n, R)), dim3(kGLBlock), 0, s, g->dg.row_ptr,
-                     g->dg.adj, g->dg.n, d_gamma_in, (int)R, (const double*)nullptr, alpha, 1,
-                     d_gamma_out);
+  char* aux = (char*)d_aux;
+  // exponents and all three max buffers start at zero
+  hipLaunchKernelGGL(k_fill_u32, dim3(256), dim3(256), 0, s, (uint32_t*)aux,
+                     (int64_t)(part), 0u);
+  if (g->dg.n == 0 || steps == 0) return hipGetLastError() == hipSuccess ? FI_OK : FI_EDEVICE;
+  float* buf[2] = {d_gamma, d_work};
+  for (int64_t k = 0; k < steps; ++k) {
+    RowArgs A{};
+    A.alpha = alpha;
+    A.update = 1;
+    A.comp = g->dg.comp;
+    A.aslot = (const int32_t*)(g->ws + g->L.aslot);
+    A.exps = (int32_t*)aux;
+    A.max_in = (const uint32_t*)(aux + (1 + k % 3) * part);
+    A.max_out = (uint32_t*)(aux + (1 + (k + 1) % 3) * part);
+    A.max_clear = (uint32_t*)(aux + (1 + (k + 2) % 3) * part);
+    A.ncr = (int64_t)std::max<int32_t>(g->nanch, 1) * R;
+    A.main_slot = g->gl_main_slot;
+    A.shift = rescale_log2;
+    if (launch_rows(g, buf[k & 1], R, A, buf[(k + 1) & 1], s) != hipSuccess) return FI_EDEVICE;
+  }
+  if (steps & 1)
+    FI_HIP(hipMemcpyAsync(d_gamma, d_work, sizeof(float) * (size_t)g->dg.n * R,
+                          hipMemcpyDeviceToDevice, s));
+  return FI_OK;
+}
+
+int fi_graphl_scales(fi_graph* g, const void* d_aux, int32_t R, int32_t* d_out, void* stream) {
+  if (!g || g->is_batch || R < 1 || R > kGraphLMaxR || !d_aux || (g->dg.n > 0 && !d_out))
+    return FI_EINVAL;
+  if (g->dg.n == 0) return FI_OK;
+  const int64_t total = (int64_t)g->dg.n * R;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 65536));
+  hipLaunchKernelGGL(k_gl_scales, dim3(grid), dim3(256), 0, (hipStream_t)stream, g->dg.row_ptr,
+                     g->dg.comp, (const int32_t*)(g->ws + g->L.aslot), g->dg.n,
+                     (const int32_t*)d_aux, (int)R, d_out);
   return hipGetLastError() == hipSuccess ? FI_OK : FI_EDEVICE;
 }
 

@@ -33,6 +33,7 @@ SYMBOLS = (
     "fi_bcloud_workspace_size", "fi_bcloud_fmax_for", "fi_bcloud_create", "fi_bcloud_destroy",
     "fi_bcloud_reset", "fi_bcloud_merge", "fi_sweep_bounded", "fi_bcloud_size", "fi_bcloud_read",
     "fi_bcloud_min", "fi_bcloud_stats", "fi_edge_list", "fi_switch_list", "fi_sweep_stats",
+    "fi_graphl_descend", "fi_graphl_aux_size", "fi_graphl_scales",
 )
 
 
@@ -111,6 +112,9 @@ def load_library(path: str = LIB_PATH):
             "fi_edge_list": ([vp, vp, vp], c.c_int),
             "fi_switch_list": ([vp, vp, vp, i64, vp, vp], c.c_int),
             "fi_sweep_stats": ([vp, i64, i64, u64, vp, vp, vp], c.c_int),
+            "fi_graphl_descend": ([vp, vp, vp, i32, c.c_float, i64, i32, vp, sz, vp], c.c_int),
+            "fi_graphl_aux_size": ([vp, i32, P(sz)], c.c_int),
+            "fi_graphl_scales": ([vp, vp, i32, vp, vp], c.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -330,6 +334,36 @@ class Graph:
         _check(self.lib.fi_graphl_step(self.handle, _ptr(g), R, float(alpha), _ptr(out),
                                        _stream_ptr(stream)), "graphl_step")
         return out
+
+    def graphl_descend(self, gamma0, steps: int, alpha: float = 0.001, rescale_log2: int = 0,
+                       out=None, stream=None):
+        """Alg. alg-gradient's update loop with the power-of-two overflow
+        policy.  Returns (Gamma, scales): the true iterate is
+        Gamma * 2**scales (``scales()`` turns the handle into int32 [n, R])."""
+        R = gamma0.shape[1]
+        g = out if out is not None else torch.empty((self.n, R), dtype=torch.float32,
+                                                    device=self.device)
+        g.copy_(gamma0)
+        work = torch.empty_like(g)
+        size = ctypes.c_size_t()
+        _check(self.lib.fi_graphl_aux_size(self.handle, R, ctypes.byref(size)), "graphl_aux_size")
+        raw = torch.empty(size.value + 256, dtype=torch.uint8, device=self.device)
+        ptr = (raw.data_ptr() + 255) // 256 * 256
+        _check(self.lib.fi_graphl_descend(self.handle, _ptr(g), _ptr(work), R, float(alpha),
+                                          int(steps), int(rescale_log2), ctypes.c_void_p(ptr),
+                                          size.value, _stream_ptr(stream)), "graphl_descend")
+        graph = self
+
+        class Scales:
+            def __call__(self_, stream=None):
+                o = torch.empty((max(graph.n, 1), R), dtype=torch.int32, device=graph.device)
+                _check(graph.lib.fi_graphl_scales(graph.handle, ctypes.c_void_p(ptr), R, _ptr(o),
+                                                  _stream_ptr(stream)), "graphl_scales")
+                return o[: graph.n]
+
+        sc = Scales()
+        sc.buffer = raw
+        return g, sc
 
     def round_count(self, gamma, return_bits: bool = False, stream=None):
         g = gamma.contiguous()

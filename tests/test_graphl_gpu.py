@@ -113,3 +113,78 @@ def test_fd_graph_float64_pin():
     ref = ogl.grad(g, gamma.cpu().numpy())
     assert _grad_err(G.graphl_backward(gamma).cpu().numpy(), ref) <= GRAD_RTOL
     G.close()
+
+
+# ------------------------------------------------- hubs and the overflow policy
+
+@pytest.fixture(scope="module")
+def hub():
+    # max degree 6,233 (17 rows above the 1,024-entry split), a giant
+    # component, 15 small ones and isolated vertices
+    g = synth.chung_lu(30000, 150000, 2.1, 4, p_pos=0.6)
+    return g, fr.Graph(g.row_ptr, g.col, g.sign, cloud_capacity=16)
+
+
+@pytest.mark.parametrize("R", [1, 5, 32, 64])
+def test_heavy_rows_gradient_and_step(hub, R):
+    g, G = hub
+    assert int(np.diff(g.row_ptr).max()) > 1024
+    gamma = torch.from_numpy(synth.graphl_init(g.n, R, 40 + R)).cuda()
+    ref = ogl.grad(g, gamma.cpu().numpy())
+    assert _grad_err(G.graphl_backward(gamma).cpu().numpy(), ref) <= GRAD_RTOL
+    out = G.graphl_step(gamma, 0.001).cpu().numpy()
+    want = gamma.cpu().numpy().astype(np.float64) - 0.001 * ref
+    assert _grad_err(out, want) <= GRAD_RTOL
+
+
+def test_descend_without_overflow_is_the_plain_loop(small):
+    g, G = small
+    gamma0 = torch.from_numpy(synth.graphl_init(g.n, 8, 3)).cuda()
+    plain = fr.graphl_descent(G, gamma0, 37, 0.001)
+    got, scales = G.graphl_descend(gamma0, 37, 0.001)
+    assert torch.equal(got, plain)
+    assert int(scales().abs().max()) == 0
+
+
+def _true(gamma, scales):
+    return np.ldexp(gamma.cpu().numpy().astype(np.float64), scales().cpu().numpy())
+
+
+def test_descend_scales_track_float64(hub):
+    # alpha = 0.05: the hub multiplies Gamma by ~2^1.4 per step, past float32
+    # in under 100 steps; float64 holds the 200-step trajectory exactly enough
+    g, G = hub
+    R, steps, alpha = 4, 200, 0.05
+    gamma0 = torch.from_numpy(synth.graphl_init(g.n, R, 11)).cuda()
+    got, scales = G.graphl_descend(gamma0, steps, alpha)
+    assert torch.isfinite(got).all()
+    sc = scales().cpu().numpy()
+    assert sc.max() >= 128  # the policy engaged on the hub component
+    ref = ogl.descent(g, gamma0.cpu().numpy(), steps, alpha)
+    true = _true(got, scales)
+    _, anchor = oracle.components(g)
+    deg = np.diff(g.row_ptr)
+    for a in np.unique(anchor[deg > 0]):
+        rows = anchor == a
+        for r in range(R):
+            top = np.abs(ref[rows, r]).max()
+            err = np.abs(true[rows, r] - ref[rows, r]).max()
+            assert err <= 1e-3 * top, (a, r, err / top)
+            big = np.abs(ref[rows, r]) > 1e-2 * top
+            assert np.array_equal(true[rows, r][big] >= 0, ref[rows, r][big] >= 0)
+    # vertices without edges keep Gamma_0 and scale 0
+    iso = deg == 0
+    assert np.array_equal(got.cpu().numpy()[iso], gamma0.cpu().numpy()[iso])
+    assert not sc[iso].any()
+
+
+def test_descend_exact_across_rescale_thresholds(hub):
+    g, G = hub
+    gamma0 = torch.from_numpy(synth.graphl_init(g.n, 6, 12)).cuda()
+    a, sa = G.graphl_descend(gamma0, 150, 0.05, rescale_log2=8)
+    b, sb = G.graphl_descend(gamma0, 150, 0.05, rescale_log2=64)
+    assert np.array_equal(_true(a, sa), _true(b, sb))
+    # and the rounded states and their exact counts agree
+    ca, ba = G.round_count(a, return_bits=True)
+    cb, bb = G.round_count(b, return_bits=True)
+    assert torch.equal(ca, cb) and torch.equal(ba, bb)
