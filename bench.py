@@ -79,6 +79,8 @@ def main():
                     help="skip the memory-bound cloud leg (Alg. alg-scale)")
     ap.add_argument("--no-switches", action="store_true",
                     help="skip the switch-list and cloud-statistics leg")
+    ap.add_argument("--no-graphl-large", action="store_true",
+                    help="skip graphL on the main graph (32 restarts x 500 steps)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy this many MiB device to device (a kernel of known traffic "
                          "for scaling hardware byte counters)")
@@ -184,6 +186,8 @@ def main():
         extra["bounded"] = bench_bounded(fr, torch, G, T, args.steps, best)
     if not args.no_switches:
         extra["switches"] = bench_switches(fr, torch, G, T, args.steps, elapsed / args.steps)
+    if not args.no_graphl_large:
+        extra["graphl_large"] = bench_graphl_large(synth, torch, G)
     if not args.no_plain:
         # the plain per-tree path: one launch per tree, one tree in flight
         # (whole-grid path, no batching of trees)
@@ -317,6 +321,35 @@ def bench_switches(fr, torch, G, T, steps, plain_step_s):
         "stats_sweep": {"trees_per_s": round(T / el, 2), "ms_per_step": round(el * 1e3, 3),
                         "vs_plain_sweep": round(plain_step_s / el, 4)},
     }
+
+
+def bench_graphl_large(synth, torch, G, R=32, steps=500, alpha=0.001):
+    """graphL on the main graph: R restarts x `steps` descent steps with the
+    overflow policy, then rounding and the exact count of every restart."""
+    gamma0 = torch.from_numpy(synth.graphl_init(G.n, R, 0)).cuda()
+    G.graphl_descend(gamma0, 4, alpha)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    out, scales = G.graphl_descend(gamma0, steps, alpha)
+    e1.record()
+    counts = G.round_count(out)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    step_ms = e0.elapsed_time(e1) / steps
+    # per step: row offsets and adjacency once, R floats gathered per CSR
+    # entry, each vertex's R floats read and written
+    nbytes = 4 * (G.n + 1) + 4 * G.nnz + 4 * G.nnz * R + 8 * G.n * R
+    res = {
+        "workload": f"the main graph, {R} restarts x {steps} steps, alpha={alpha}",
+        "steps_per_s": round(steps / el, 2), "restart_steps_per_s": round(steps * R / el, 1),
+        "step_ms": round(step_ms, 3), "algorithmic_bytes_per_step": nbytes,
+        "GB_per_s": round(nbytes / step_ms / 1e6, 1),
+        "best_rounded_frustration": int(counts.min()), "max_log2_scale": int(scales().max()),
+    }
+    del gamma0, out
+    return res
 
 
 def bench_graphl(fr, synth, torch):

@@ -188,7 +188,11 @@ struct Layout {
   size_t mrec, mhslot, mhcap, mreach, aslot, cverts, ccount, cptr, mtasks, mtcap, rootbig, nbigcap;
   size_t swtile;       // switch lists: per-tile counts and offsets (8 bytes each)
   size_t glheavy;      // graphL: rows longer than kGLHeavy
-  size_t glctl;        // graphL: the heavy-row count
+  size_t glfirst;      // graphL: first item of each of those rows, and the item count
+  size_t glitems;      // graphL: items (heavy row, chunk)
+  size_t glicap;       // graphL: item capacity
+  size_t glpart;       // graphL: [items][64] partial sums
+  size_t glctl;        // graphL: heavy-row and item counts
   size_t total;
 };
 
@@ -203,7 +207,8 @@ uint64_t table_size_for(int64_t cloud_capacity);
 
 constexpr int kGraphLMaxR = 64;
 constexpr int kGraphLBlocks = 1024;
-constexpr int kGLHeavy = 1024;  // graphL rows longer than this go one per workgroup
+constexpr int kGLHeavy = 256;   // graphL rows longer than this are cut into items
+constexpr int kGLChunk = 4096;  // CSR entries per item of a long graphL row
 
 // profiling events around one launch (no-ops unless profiling is on)
 void batch_info_free(void* p);

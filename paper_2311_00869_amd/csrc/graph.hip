@@ -457,6 +457,10 @@ Layout make_layout(int32_t n, int64_t nnz, int64_t cloud_capacity, uint64_t tabl
   L.rootbig = take(8 * 64 * L.nbigcap);
   L.swtile = take(16 * ((size_t)switch_tiles((int64_t)m) + 1));
   L.glheavy = take(4 * ((size_t)nnz / kGLHeavy + 2));
+  L.glfirst = take(4 * ((size_t)nnz / kGLHeavy + 3));
+  L.glicap = (size_t)nnz / kGLChunk + (size_t)nnz / kGLHeavy + 2;
+  L.glitems = take(8 * L.glicap);
+  L.glpart = take(4 * (size_t)kGraphLMaxR * L.glicap);
   L.glctl = take(64);
   L.total = off;
   return L;

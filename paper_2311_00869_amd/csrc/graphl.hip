@@ -132,6 +132,31 @@ __device__ __forceinline__ int32_t row_slot(const RowArgs& A, int64_t i, int64_t
   return e1 > e0 ? A.aslot[A.comp[i]] : -1;
 }
 
+// Sum of e_ij * G[j][sub] * sc over entries e0, e0 + step, ... < e1, added
+// in that order.  Eight entries are loaded before their gathers so that
+// eight gathers are in flight per lane.
+__device__ __forceinline__ float row_sum(const uint32_t* adj, int64_t e0, int64_t e1, int step,
+                                         const float* gamma, int R, int sub, float sc) {
+  float acc = 0.0f;
+  int64_t e = e0;
+  for (; e + 7 * (int64_t)step < e1; e += 8 * (int64_t)step) {
+    uint32_t a[8];
+    float x[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] = adj[e + k * step];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = gamma[(size_t)(a[k] & kVertexMask) * R + sub] * sc;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc += (a[k] >> 31) ? -x[k] : x[k];
+  }
+  for (; e < e1; e += step) {
+    const uint32_t a = adj[e];
+    const float gj = gamma[(size_t)(a & kVertexMask) * R + sub] * sc;
+    acc += (a >> 31) ? -gj : gj;
+  }
+  return acc;
+}
+
 __global__ void __launch_bounds__(kGLBlock) k_gl_rows(const int32_t* rp, const uint32_t* adj,
                                                       int32_t n, const float* gamma, int R,
                                                       RowArgs A, float* out) {
@@ -154,12 +179,7 @@ __global__ void __launch_bounds__(kGLBlock) k_gl_rows(const int32_t* rp, const u
       if (e1 - e0 > kGLHeavy) continue;
       const int32_t c = scaled ? row_slot(A, i, e0, e1) : -1;
       const float sc = scaled ? pair_scale(A, c, R, sub) : 1.0f;
-      float acc = 0.0f;
-      for (int64_t e = e0; e < e1; ++e) {
-        const uint32_t a = adj[e];
-        const float gj = gamma[(size_t)(a & kVertexMask) * R + sub] * sc;
-        acc += (a >> 31) ? -gj : gj;
-      }
+      const float acc = row_sum(adj, e0, e1, 1, gamma, R, sub, sc);
       const float g = -0.5f * acc * wr;
       const size_t o = (size_t)i * R + sub;
       const float v = A.update ? gamma[o] * sc - A.alpha * g : g;
@@ -170,10 +190,14 @@ __global__ void __launch_bounds__(kGLBlock) k_gl_rows(const int32_t* rp, const u
   if (scaled) block_max_main(A, mx_main, s_mx, P, R, sub, grp, gpb, active);
 }
 
-__global__ void __launch_bounds__(kGLBlock) k_gl_heavy(const int32_t* rp, const uint32_t* adj,
-                                                       const int32_t* list, const uint32_t* count,
-                                                       const float* gamma, int R, RowArgs A,
-                                                       float* out) {
+// Heavy rows (more than kGLHeavy entries) are cut into items of up to
+// kGLChunk entries spread over workgroups.  An item's groups stride over its
+// entries and their sums are added in group order into part[item][r]; a row
+// then adds its items in order.  Items of one row are consecutive.
+__global__ void __launch_bounds__(kGLBlock) k_gl_chunks(const int32_t* rp, const uint32_t* adj,
+                                                        const int32_t* list, const int2* items,
+                                                        const uint32_t* ctl, const float* gamma,
+                                                        int R, RowArgs A, float* part) {
   __shared__ float s_part[kGLBlock];
   const int P = lanes_for(R);
   const int sub = threadIdx.x % P;
@@ -181,36 +205,88 @@ __global__ void __launch_bounds__(kGLBlock) k_gl_heavy(const int32_t* rp, const 
   const int gpb = kGLBlock / P;
   const bool active = sub < R;
   const bool scaled = A.max_in != nullptr;
-  const float wr = (A.w && active) ? (float)A.w[sub] : 1.0f;
-  const uint32_t cnt = *count;
-  float mx_main = 0.0f;
-  for (uint32_t h = blockIdx.x; h < cnt; h += gridDim.x) {
-    const int64_t i = list[h];
-    const int64_t e0 = rp[i], e1 = rp[i + 1];
-    const int32_t c = scaled ? row_slot(A, i, e0, e1) : -1;
-    const float sc = (scaled && active) ? pair_scale(A, c, R, sub) : 1.0f;
+  const uint32_t nitems = ctl[1];
+  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int2 hc = items[it];
+    const int64_t i = list[hc.x];
+    const int64_t r0 = rp[i], r1 = rp[i + 1];
+    const int64_t e0 = r0 + (int64_t)hc.y * kGLChunk;
+    const int64_t e1 = min(r1, e0 + kGLChunk);
     float acc = 0.0f;
     if (active) {
-      for (int64_t e = e0 + grp; e < e1; e += gpb) {
-        const uint32_t a = adj[e];
-        const float gj = gamma[(size_t)(a & kVertexMask) * R + sub] * sc;
-        acc += (a >> 31) ? -gj : gj;
-      }
+      const int32_t c = scaled ? row_slot(A, i, r0, r1) : -1;
+      const float sc = scaled ? pair_scale(A, c, R, sub) : 1.0f;
+      acc = row_sum(adj, e0 + grp, e1, gpb, gamma, R, sub, sc);
     }
     s_part[threadIdx.x] = acc;
     __syncthreads();
     if (grp == 0 && active) {
       float tot = 0.0f;
       for (int g = 0; g < gpb; ++g) tot += s_part[g * P + sub];
+      part[(size_t)it * kGraphLMaxR + sub] = tot;
+    }
+    __syncthreads();
+  }
+}
+
+// One group of lanes per heavy row: its items in order, then the update.
+__global__ void __launch_bounds__(kGLBlock) k_gl_combine(const int32_t* rp, const int32_t* list,
+                                                         const int32_t* first, const uint32_t* ctl,
+                                                         const float* part, const float* gamma,
+                                                         int R, RowArgs A, float* out) {
+  __shared__ float s_mx[kGLBlock];
+  const int P = lanes_for(R);
+  const int sub = threadIdx.x % P;
+  const int grp = threadIdx.x / P;
+  const int gpb = kGLBlock / P;
+  const bool active = sub < R;
+  const bool scaled = A.max_in != nullptr;
+  const float wr = (A.w && active) ? (float)A.w[sub] : 1.0f;
+  const uint32_t cnt = ctl[0];
+  float mx_main = 0.0f;
+  if (active) {
+    for (int64_t h = (int64_t)blockIdx.x * gpb + grp; h < cnt; h += (int64_t)gridDim.x * gpb) {
+      const int64_t i = list[h];
+      const int32_t c = scaled ? row_slot(A, i, rp[i], rp[i + 1]) : -1;
+      const float sc = scaled ? pair_scale(A, c, R, sub) : 1.0f;
+      float tot = 0.0f;
+      for (int32_t it = first[h]; it < first[h + 1]; ++it) tot += part[(size_t)it * kGraphLMaxR + sub];
       const float g = -0.5f * tot * wr;
       const size_t o = (size_t)i * R + sub;
       const float v = A.update ? gamma[o] * sc - A.alpha * g : g;
       out[o] = v;
       if (scaled) note_row(A, i, c, R, sub, sc, v, mx_main);
     }
-    __syncthreads();
   }
-  if (scaled) block_max_main(A, mx_main, s_part, P, R, sub, grp, gpb, active);
+  if (scaled) block_max_main(A, mx_main, s_mx, P, R, sub, grp, gpb, active);
+}
+
+// Items of the heavy rows (one workgroup): first[h] = the first item of
+// heavy row h, first[count] = ctl[1] = the number of items.
+__global__ void __launch_bounds__(1024) k_gl_plan(const int32_t* rp, const int32_t* list,
+                                                  uint32_t* ctl, int32_t* first, int2* items) {
+  __shared__ int s_scan[1024 / 64 + 1];
+  const int64_t cnt = ctl[0];
+  const int64_t per = (cnt + 1023) / 1024;
+  const int64_t h0 = (int64_t)threadIdx.x * per, h1 = min(cnt, h0 + per);
+  int mine = 0;
+  for (int64_t h = h0; h < h1; ++h) {
+    const int64_t i = list[h];
+    mine += (int)((rp[i + 1] - rp[i] + kGLChunk - 1) / kGLChunk);
+  }
+  int total = 0;
+  int at = block_exclusive_scan<1024>(mine, total, s_scan);
+  for (int64_t h = h0; h < h1; ++h) {
+    const int64_t i = list[h];
+    const int nch = (int)((rp[i + 1] - rp[i] + kGLChunk - 1) / kGLChunk);
+    first[h] = at;
+    for (int c = 0; c < nch; ++c) items[at + c] = make_int2((int)h, c);
+    at += nch;
+  }
+  if (threadIdx.x == 0) {
+    first[cnt] = total;
+    ctl[1] = (uint32_t)total;
+  }
 }
 
 // Per-vertex log2 scales of a descent: out[i][r] = the scale of (component
@@ -271,7 +347,7 @@ int rows_grid(int32_t n, int R) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, 65536));
 }
 
-// graphL control words in the workspace: the heavy-row count
+// graphL control words in the workspace: heavy rows, their items
 uint32_t* gl_ctl(fi_graph* g) { return (uint32_t*)(g->ws + g->L.glctl); }
 
 // Descent scales in the caller's buffer: exponents, then three max buffers,
@@ -283,21 +359,30 @@ size_t aux_part(const fi_graph* g, int R) {
 
 hipError_t launch_rows(fi_graph* g, const float* gin, int R, const RowArgs& A, float* out,
                        hipStream_t s) {
-  const int64_t hcap = g->dg.nnz / kGLHeavy + 1;
-  int32_t* list = (int32_t*)(g->ws + g->L.glheavy);
-  uint32_t* count = gl_ctl(g);
+  const Layout& L = g->L;
+  int32_t* list = (int32_t*)(g->ws + L.glheavy);
+  int32_t* first = (int32_t*)(g->ws + L.glfirst);
+  int2* items = (int2*)(g->ws + L.glitems);
+  float* part = (float*)(g->ws + L.glpart);
+  uint32_t* ctl = gl_ctl(g);
   if (!g->gl_heavy_built) {
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, count, (int64_t)1, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, ctl, (int64_t)2, 0u);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)g->dg.n + 255) / 256, 16384));
     hipLaunchKernelGGL(k_gl_heavy_list, dim3(grid), dim3(256), 0, s, g->dg.row_ptr, g->dg.n, list,
-                       count);
+                       ctl);
+    hipLaunchKernelGGL(k_gl_plan, dim3(1), dim3(1024), 0, s, g->dg.row_ptr, list, ctl, first, items);
     g->gl_heavy_built = true;
   }
   hipLaunchKernelGGL(k_gl_rows, dim3(rows_grid(g->dg.n, R)), dim3(kGLBlock), 0, s, g->dg.row_ptr,
                      g->dg.adj, g->dg.n, gin, R, A, out);
-  const int hgrid = (int)std::min<int64_t>(hcap, 2048);
-  hipLaunchKernelGGL(k_gl_heavy, dim3(hgrid), dim3(kGLBlock), 0, s, g->dg.row_ptr, g->dg.adj, list,
-                     count, gin, R, A, out);
+  const int cgrid = (int)std::min<int64_t>((int64_t)L.glicap, 8192);
+  hipLaunchKernelGGL(k_gl_chunks, dim3(cgrid), dim3(kGLBlock), 0, s, g->dg.row_ptr, g->dg.adj, list,
+                     items, ctl, gin, R, A, part);
+  const int64_t hcap = g->dg.nnz / kGLHeavy + 1;
+  const int hgrid = (int)std::max<int64_t>(1, std::min<int64_t>(hcap / (kGLBlock / lanes_for(R)) + 1,
+                                                                4096));
+  hipLaunchKernelGGL(k_gl_combine, dim3(hgrid), dim3(kGLBlock), 0, s, g->dg.row_ptr, list, first,
+                     ctl, part, gin, R, A, out);
   return hipGetLastError();
 }
 

@@ -82,7 +82,35 @@ def test_large_graph_bench_configuration():
             for a, b in zip(u, v)]
     neg = (g.sign[rows] < 0).astype(np.uint64)
     assert np.all(neg ^ bit(u) ^ bit(v) == 1)
+    _check_graphl_large(g, G)
     G.close()
+
+
+def _check_graphl_large(g, G):
+    """graphL on the 16M graph: one step against the oracle on sampled rows
+    (the hubs among them), then 500 steps with the overflow policy."""
+    from oracle import graphl as ogl
+    R = 8
+    gamma0 = torch.from_numpy(synth.graphl_init(g.n, R, 5)).cuda()
+    step = G.graphl_step(gamma0, 0.001).cpu().numpy()
+    deg = np.diff(g.row_ptr)
+    rows = np.concatenate([np.argsort(deg)[-16:],
+                           np.random.default_rng(1).choice(g.n, 2000, replace=False)])
+    g0 = gamma0.cpu().numpy()
+    want = g0[rows].astype(np.float64) - 0.001 * ogl.grad_rows(g, g0, rows)
+    err = np.abs(step[rows] - want).max() / np.abs(want).max()
+    assert err <= 1e-4, err
+    a, sa = G.graphl_descend(gamma0, 500, 0.001)
+    assert torch.isfinite(a).all()
+    assert int(sa().max()) > 0  # the hub component needed rescaling
+    b, sb = G.graphl_descend(gamma0, 500, 0.001, rescale_log2=32)
+    ta = torch.ldexp(a.double(), sa().double())
+    tb = torch.ldexp(b.double(), sb().double())
+    assert torch.equal(ta, tb)
+    del ta, tb
+    ca = G.round_count(a)
+    assert torch.equal(ca, G.round_count(b))
+    assert int(ca.max()) <= G.m
 
 
 def _check_bounded(G, gold, fmax, chunk):
