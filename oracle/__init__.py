@@ -60,7 +60,8 @@ def lib():
             L.orc_tree_salt.restype = c.c_uint64
             L.orc_vertex_key.argtypes = [c.c_uint64, c.c_int32]
             L.orc_vertex_key.restype = c.c_uint64
-            L.orc_tree.argtypes = [c.c_int32, i32p, i32p, i8p, c.c_uint64, c.c_int64, i32p, i32p, i8p]
+            L.orc_tree.argtypes = [c.c_int32, i32p, i32p, i8p, c.c_uint64, c.c_int64, c.c_int,
+                                   i32p, i32p, i8p]
             L.orc_tree.restype = c.c_int
             L.orc_balance.argtypes = [c.c_int32, i32p, i32p, i8p, i32p, i32p, i8p]
             L.orc_balance.restype = c.c_int64
@@ -74,9 +75,13 @@ def lib():
             L.orc_splitmix.restype = c.c_uint64
             L.orc_fmix32.argtypes = [c.c_uint32]
             L.orc_fmix32.restype = c.c_uint32
+            L.orc_hybrid_coin.argtypes = [c.c_uint64]
+            L.orc_hybrid_coin.restype = c.c_int
+            L.orc_kruskal_weight.argtypes = [c.c_uint64, c.c_int32, c.c_int32]
+            L.orc_kruskal_weight.restype = c.c_uint32
             L.orc_sweep.argtypes = [c.c_int32, i32p, i32p, i8p, c.c_uint64, c.c_int64, c.c_int64,
                                     c.c_int, c.c_void_p, c.c_void_p, c.c_int64,
-                                    c.POINTER(c.c_int64), c.c_void_p]
+                                    c.POINTER(c.c_int64), c.c_void_p, c.c_int]
             L.orc_sweep.restype = c.c_int
             _lib = L
     return _lib
@@ -116,13 +121,33 @@ def fmix32(x: int) -> int:
     return int(lib().orc_fmix32(x & 0xFFFFFFFF))
 
 
-def tree(g, seed: int, t: int):
-    """(level, parent, state +1/-1) of tree t."""
+SAMPLERS = {"bfs": 0, "rdfs": 1, "hybrid": 2, "kruskal": 3}
+
+
+def _sampler(s) -> int:
+    return SAMPLERS[s] if isinstance(s, str) else int(s)
+
+
+def hybrid_coin(salt: int) -> int:
+    """Alg. alg-hybrid's 0/1 for a tree's salt (0: BFS, 1: RDFS)."""
+    return int(lib().orc_hybrid_coin(salt & (2**64 - 1)))
+
+
+def kruskal_weight(salt: int, u: int, v: int) -> int:
+    """Random weight of edge (u, v), u < v, in the tree with this salt."""
+    return int(lib().orc_kruskal_weight(salt & (2**64 - 1), u, v))
+
+
+def tree(g, seed: int, t: int, sampler="bfs"):
+    """(level, parent, state +1/-1) of tree t with the given sampler."""
     n, rp, col, sg = _g(g)
     level = np.empty(n, np.int32)
     parent = np.empty(n, np.int32)
     state = np.empty(n, np.int8)
-    lib().orc_tree(n, rp, col, sg, seed & (2**64 - 1), t, level, parent, state)
+    rc = lib().orc_tree(n, rp, col, sg, seed & (2**64 - 1), t, _sampler(sampler), level, parent,
+                        state)
+    if rc != 0:
+        raise RuntimeError(f"oracle tree failed: {ERRORS.get(rc, rc)}")
     return level, parent, state
 
 
@@ -167,8 +192,9 @@ class SweepResult:
 
 
 def sweep(g, seed: int, t0: int, t1: int, checks: bool = True, paper_strings: bool = False,
-          cloud_cap: int | None = None) -> SweepResult:
-    """Alg. alg-index over trees t0..t1-1.  Raises on any failed self-check."""
+          cloud_cap: int | None = None, sampler="bfs") -> SweepResult:
+    """Alg. alg-index over trees t0..t1-1 with the given tree sampler.
+    Raises on any failed self-check."""
     n, rp, col, sg = _g(g)
     T = t1 - t0
     trees = np.zeros((max(T, 0), 3), np.uint64)
@@ -179,7 +205,7 @@ def sweep(g, seed: int, t0: int, t1: int, checks: bool = True, paper_strings: bo
     flags = (1 if checks else 0) | (2 if paper_strings else 0)
     rc = lib().orc_sweep(n, rp, col, sg, seed & (2**64 - 1), t0, t1, flags,
                          trees.ctypes.data, cloud.ctypes.data, cap, ctypes.byref(size),
-                         best.ctypes.data)
+                         best.ctypes.data, _sampler(sampler))
     if rc != 0:
         raise RuntimeError(f"oracle sweep failed: {ERRORS.get(rc, rc)}")
     return SweepResult(trees, cloud[: size.value].copy(), (int(best[0]), int(best[1])))

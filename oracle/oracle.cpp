@@ -24,12 +24,14 @@
 //     edges exactly across the two colour classes.
 //
 // Readings where the paper leaves a choice open (listed in the design notes):
-//   * Tree sampler: BFS.  Each tree t of a sweep with seed s gets a salt from
-//     the SplitMix64 stream seeded with s; every vertex u gets a 51-bit key
-//     (20-bit mixed hash, then u).  The root of each connected component is
-//     its minimum-key vertex, and the parent of every other vertex is its
-//     minimum-key neighbour on the previous BFS level.  Disconnected graphs
-//     get a spanning forest.
+//   * Tree sampler: BFS by default.  Each tree t of a sweep with seed s gets a
+//     salt from the SplitMix64 stream seeded with s; every vertex u gets a
+//     32-bit key, a bijection of u (see vertex_key).  The root of each
+//     connected component is its minimum-key vertex, and the parent of every
+//     other vertex is its minimum-key neighbour on the previous BFS level.
+//     Disconnected graphs get a spanning forest.  The other samplers
+//     (randomized DFS, the RDFS-BFS hybrid, Kruskal on random weights) take
+//     their randomness from the same salt; see build_sampled_tree.
 //   * Vertex state s (+1/-1): root +1, child = parent * sign(tree edge).
 //   * Cloud key: the canonical vertex state (each component flipped so that
 //     its smallest vertex is +1), which determines the balanced graph one to
@@ -211,6 +213,141 @@ void build_tree(const Graph& g, const std::vector<int32_t>& comp, uint64_t seed,
     }
 }
 
+// ---------------------------------------------------------------- other samplers
+// Section "Tree-Sampling techniques for graphBpp" and Alg. alg-hybrid, made
+// reproducible like BFS: all randomness comes from tree t's salt.
+enum { SAMPLER_BFS = 0, SAMPLER_RDFS = 1, SAMPLER_HYBRID = 2, SAMPLER_KRUSKAL = 3 };
+
+// Alg. alg-hybrid's uniformly distributed 0 or 1: the top bit of the
+// SplitMix64 finalizer applied to the tree's salt (0: BFS, 1: RDFS).
+int hybrid_coin(uint64_t salt) { return (int)(splitmix_output(salt) >> 63); }
+
+// Minimum-key vertex of every component (indexed by the component label).
+std::vector<int32_t> min_key_roots(const Graph& g, const std::vector<int32_t>& comp, uint64_t salt) {
+    std::vector<uint64_t> best(g.n, UINT64_MAX);
+    std::vector<int32_t> arg(g.n, -1);
+    for (int32_t v = 0; v < g.n; ++v) {
+        uint64_t k = vertex_key(salt, v);
+        if (k < best[comp[v]]) { best[comp[v]] = k; arg[comp[v]] = v; }
+    }
+    return arg;
+}
+
+void reset_tree(int32_t n, Tree& T) {
+    T.level.assign(n, -1);
+    T.parent.assign(n, -1);
+    T.parent_sign.assign(n, 1);
+    T.state.assign(n, 0);
+    T.order.clear();
+}
+
+// Randomized DFS: the shuffled adjacency of the paper's RDFS is the order of
+// the neighbours' keys, so from the current vertex the search moves to its
+// unvisited neighbour of smallest key and backtracks when there is none.
+// One search per component from its minimum-key vertex; states propagate
+// along the discovery edges.
+void build_rdfs(const Graph& g, const std::vector<int32_t>& comp, uint64_t salt, Tree& T) {
+    reset_tree(g.n, T);
+    std::vector<int32_t> root = min_key_roots(g, comp, salt);
+    std::vector<int32_t> stack;
+    for (int32_t c = 0; c < g.n; ++c) {
+        if (root[c] < 0) continue;
+        int32_t r = root[c];
+        T.level[r] = 0;
+        T.state[r] = 1;
+        T.order.push_back(r);
+        stack.assign(1, r);
+        while (!stack.empty()) {
+            int32_t u = stack.back();
+            int32_t pick = -1;
+            int8_t psign = 1;
+            uint64_t pk = UINT64_MAX;
+            for (int64_t e = g.begin(u); e < g.end(u); ++e) {
+                int32_t v = g.col[e];
+                if (T.level[v] >= 0) continue;
+                uint64_t k = vertex_key(salt, v);
+                if (k < pk) { pk = k; pick = v; psign = g.sign[e]; }
+            }
+            if (pick < 0) { stack.pop_back(); continue; }
+            T.parent[pick] = u;
+            T.parent_sign[pick] = psign;
+            T.level[pick] = T.level[u] + 1;
+            T.state[pick] = (int8_t)(T.state[u] * psign);
+            T.order.push_back(pick);
+            stack.push_back(pick);
+        }
+    }
+}
+
+// Random weight of the undirected edge (u, v), u < v, in tree t: the high
+// half of the SplitMix64 finalizer of salt xor (u << 32 | v).
+uint32_t kruskal_weight(uint64_t salt, int32_t u, int32_t v) {
+    return (uint32_t)(splitmix_output(salt ^ ((uint64_t)(uint32_t)u << 32 | (uint32_t)v)) >> 32);
+}
+
+// Kruskal's algorithm on random edge weights: edges in increasing order of
+// (weight, position in the sorted (u, v) edge list), each kept when it joins
+// two trees of the forest.  The order is total, so the forest is the unique
+// minimum spanning forest.  Each tree is then rooted at its smallest vertex
+// and walked breadth-first along its edges for levels and states.
+void build_kruskal(const Graph& g, const std::vector<int32_t>& comp, uint64_t salt, Tree& T) {
+    reset_tree(g.n, T);
+    struct E { uint64_t key; int32_t u, v; int8_t s; };
+    std::vector<E> edges;
+    uint64_t idx = 0;
+    for (int32_t u = 0; u < g.n; ++u)
+        for (int64_t e = g.begin(u); e < g.end(u); ++e)
+            if (u < g.col[e]) {
+                uint64_t w = kruskal_weight(salt, u, g.col[e]);
+                edges.push_back({w << 32 | idx, u, g.col[e], g.sign[e]});
+                ++idx;
+            }
+    std::sort(edges.begin(), edges.end(), [](const E& a, const E& b) { return a.key < b.key; });
+    std::vector<int32_t> uf(g.n);
+    for (int32_t v = 0; v < g.n; ++v) uf[v] = v;
+    auto find = [&](int32_t x) {
+        while (uf[x] != x) { uf[x] = uf[uf[x]]; x = uf[x]; }
+        return x;
+    };
+    std::vector<std::vector<std::pair<int32_t, int8_t>>> tadj(g.n);
+    for (const E& e : edges) {
+        int32_t a = find(e.u), b = find(e.v);
+        if (a == b) continue;
+        uf[a] = b;
+        tadj[e.u].push_back({e.v, e.s});
+        tadj[e.v].push_back({e.u, e.s});
+    }
+    std::queue<int32_t> q;
+    for (int32_t r = 0; r < g.n; ++r) {
+        if (comp[r] != r) continue;
+        T.level[r] = 0;
+        T.state[r] = 1;
+        q.push(r);
+        while (!q.empty()) {
+            int32_t u = q.front(); q.pop();
+            T.order.push_back(u);
+            for (auto& [v, sg] : tadj[u]) {
+                if (T.level[v] >= 0) continue;
+                T.level[v] = T.level[u] + 1;
+                T.parent[v] = u;
+                T.parent_sign[v] = sg;
+                T.state[v] = (int8_t)(T.state[u] * sg);
+                q.push(v);
+            }
+        }
+    }
+}
+
+// Tree t with the chosen sampler.
+void build_sampled_tree(const Graph& g, const std::vector<int32_t>& comp, uint64_t seed, int64_t t,
+                        int sampler, Tree& T) {
+    const uint64_t salt = tree_salt(seed, t);
+    if (sampler == SAMPLER_HYBRID) sampler = hybrid_coin(salt) ? SAMPLER_RDFS : SAMPLER_BFS;
+    if (sampler == SAMPLER_RDFS) build_rdfs(g, comp, salt, T);
+    else if (sampler == SAMPLER_KRUSKAL) build_kruskal(g, comp, salt, T);
+    else build_tree(g, comp, seed, t, T);
+}
+
 bool is_tree_edge(const Tree& T, int32_t u, int32_t v) {
     return T.parent[v] == u || T.parent[u] == v;
 }
@@ -384,12 +521,14 @@ uint64_t orc_vertex_key(uint64_t salt, int32_t u) { return vertex_key(salt, u); 
 // Tree t of the sweep with this seed: level, parent (-1 at roots), parent
 // edge sign, and the propagated +1/-1 state.
 int orc_tree(int32_t n, const int32_t* row_ptr, const int32_t* col, const int8_t* sign,
-             uint64_t seed, int64_t t, int32_t* level_out, int32_t* parent_out, int8_t* state_out) {
+             uint64_t seed, int64_t t, int sampler, int32_t* level_out, int32_t* parent_out,
+             int8_t* state_out) {
+    if (sampler < SAMPLER_BFS || sampler > SAMPLER_KRUSKAL) return ORC_EINVAL;
     Graph g{n, row_ptr, col, sign};
     std::vector<int32_t> comp;
     label_components(g, comp);
     Tree T;
-    build_tree(g, comp, seed, t, T);
+    build_sampled_tree(g, comp, seed, t, sampler, T);
     for (int32_t v = 0; v < n; ++v) {
         level_out[v] = T.level[v];
         parent_out[v] = T.parent[v];
@@ -443,9 +582,13 @@ void orc_hash128(int64_t nwords, const uint64_t* words, uint64_t* out2) {
 }
 
 uint64_t orc_splitmix(uint64_t x) { return splitmix_output(x); }
+int orc_hybrid_coin(uint64_t salt) { return hybrid_coin(salt); }
+uint32_t orc_kruskal_weight(uint64_t salt, int32_t u, int32_t v) { return kruskal_weight(salt, u, v); }
 uint32_t orc_fmix32(uint32_t x) { return murmur_fmix32(x); }
 
-// One graphBpp sweep over trees t0 .. t1-1 (Alg. alg-index).
+// One graphBpp sweep over trees t0 .. t1-1 (Alg. alg-index) with the given
+// tree sampler (0 BFS, 1 randomized DFS, 2 the RDFS-BFS hybrid, 3 Kruskal on
+// random weights).
 //   flags bit 0: run the independent cross-checks on every tree;
 //   flags bit 1: also key a second cloud by the paper's string form and
 //                check that string keys and state keys pair up one to one.
@@ -457,7 +600,9 @@ uint32_t orc_fmix32(uint32_t x) { return murmur_fmix32(x); }
 //   best_out[0..1] = minimum switches and the first tree reaching it.
 int orc_sweep(int32_t n, const int32_t* row_ptr, const int32_t* col, const int8_t* sign,
               uint64_t seed, int64_t t0, int64_t t1, int flags, uint64_t* tree_out,
-              uint64_t* cloud_out, int64_t cloud_cap, int64_t* cloud_size, uint64_t* best_out) {
+              uint64_t* cloud_out, int64_t cloud_cap, int64_t* cloud_size, uint64_t* best_out,
+              int sampler) {
+    if (sampler < SAMPLER_BFS || sampler > SAMPLER_KRUSKAL) return ORC_EINVAL;
     Graph g{n, row_ptr, col, sign};
     std::vector<int32_t> comp;
     int32_t ncomp = label_components(g, comp);
@@ -468,7 +613,7 @@ int orc_sweep(int32_t n, const int32_t* row_ptr, const int32_t* col, const int8_
     Tree T;
     std::vector<int8_t> flip;
     for (int64_t t = t0; t < t1; ++t) {
-        build_tree(g, comp, seed, t, T);
+        build_sampled_tree(g, comp, seed, t, sampler, T);
         int64_t s = balance_by_cycles(g, T, flip);  // s = number of sign differences
         if (flags & 1) {
             int rc = cross_check(g, comp, ncomp, T, flip);
