@@ -259,6 +259,29 @@ int fi_batch_create(int32_t G, const int64_t* h_vertex_offsets, const int64_t* h
 int fi_batch_sweep(fi_graph* b, int64_t trees_per_graph, uint64_t seed, uint64_t* d_min_per_graph,
                    uint64_t* d_distinct_per_graph, void* stream);
 
+/* ---------------------------------------------------------------- tree samplers */
+
+/* The spanning-tree sampler of the sweep (Section "Tree-Sampling techniques
+ * for graphBpp"), made reproducible like BFS: every random choice comes from
+ * tree t's salt.
+ *   0  BFS (default): the min-key rule above.
+ *   1  randomized DFS: from each component's minimum-key vertex, move to the
+ *      unvisited neighbour of smallest key (the shuffled adjacency order),
+ *      back up when there is none.
+ *   2  the RDFS-BFS hybrid of Alg. alg-hybrid: per tree a uniformly
+ *      distributed 0/1 (the top bit of the SplitMix64 finalizer of the salt)
+ *      picks BFS (0) or randomized DFS (1).
+ *   3  Kruskal on random weights: edge (u, v), u < v, weighs the high half
+ *      of the SplitMix64 finalizer of salt xor (u << 32 | v); ties go to the
+ *      earlier edge of the sorted edge list; the tree is the unique minimum
+ *      spanning forest (computed here by Boruvka rounds).
+ * Samplers other than BFS run one tree per workgroup (schedule paths 1 and
+ * 2, whatever fi_set_schedule chose), so they need the tree in LDS (n up to
+ * about 8,000 for Kruskal, 10,000 for DFS) or a workspace slot (n <= 10^6):
+ * FI_ERANGE otherwise.  fi_sweep_stats takes BFS only (FI_EINVAL). */
+int fi_set_sampler(fi_graph* g, int32_t sampler);
+int fi_get_sampler(fi_graph* g, int32_t* out);
+
 /* ---------------------------------------------------------------- switch lists and statistics */
 
 /* The upper-triangle edge list: d_uv_out int32[2m] receives (u, v) with

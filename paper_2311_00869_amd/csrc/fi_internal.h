@@ -162,10 +162,15 @@ struct SweepArgs {
   // state puts it at -1; per upper-triangle edge, trees that switch it
   uint64_t* vminus;
   uint64_t* eswitch;
+  int sampler;              // kSampler*: the tree sampler (paths 1 and 2)
+  const int32_t* cptr;      // component offsets (randomized DFS stacks)
   // one-workgroup-per-tree scratch in workspace memory: [slots][slot_stride bytes]
   uint64_t* pw;
   size_t slot_stride;
 };
+
+// tree samplers (Section "Tree-Sampling techniques for graphBpp")
+enum : int { kSamplerBfs = 0, kSamplerRdfs = 1, kSamplerHybrid = 2, kSamplerKruskal = 3 };
 
 // ----------------------------------------------------------------- layout
 constexpr int kGridSlots = 8;  // trees in flight on the whole-grid path (max)
@@ -236,6 +241,7 @@ struct fi_graph {
   int32_t ncomp, nisolated, nanch;
   int32_t mtasks, mnbig;  // multi-tree path: root-finding tasks, big components
   bool gl_heavy_built;    // graphL heavy-row list is in the workspace
+  int32_t sampler;        // kSampler*
   int32_t gl_main_slot;   // slot of the component with the most vertices (-1: none)
   fi_schedule sched;
   int cu_count;

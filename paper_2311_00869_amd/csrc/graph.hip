@@ -433,7 +433,7 @@ Layout make_layout(int32_t n, int64_t nnz, int64_t cloud_capacity, uint64_t tabl
   L.gctl = take(8 * S * kGridCtlWords);
   L.gbar = take(8 * S * kGridBarWords);
   // per-workgroup tree scratch (a tree word and a queue entry per vertex)
-  L.slot_stride = align_up(12 * nn);
+  L.slot_stride = align_up(16 * nn);  // tree words, queue, and Kruskal's hooks
   L.nslots = 0;
   if (n > 0 && n <= 1000000) {
     size_t budget = (size_t)8 << 30;

@@ -26,7 +26,7 @@ namespace fi {
 namespace {
 
 using wg::WgShared;
-using wg::wg_tree;
+using wg::wg_tree_sampled;
 
 template <int NT, bool IN_LDS>
 __global__ void __launch_bounds__(NT) k_sweep_wg(DevGraph G, SweepArgs A) {
@@ -42,10 +42,15 @@ __global__ void __launch_bounds__(NT) k_sweep_wg(DevGraph G, SweepArgs A) {
     pw = (uint64_t*)slot;
     q = (int32_t*)(slot + 8 * (size_t)G.n);
   }
-  for (uint64_t t = A.t0 + blockIdx.x; t < A.t1; t += gridDim.x) wg_tree<NT>(G, A, t, pw, q, sh);
+  int32_t* d = q + G.n;  // Kruskal's hooks (its LDS and slots have room)
+  for (uint64_t t = A.t0 + blockIdx.x; t < A.t1; t += gridDim.x)
+    wg_tree_sampled<NT>(G, A, t, pw, q, d, sh);
 }
 
-size_t wg_lds_bytes(int32_t n) { return 12 * (size_t)n; }
+// tree words and queue; Kruskal also keeps a hook per vertex
+size_t wg_lds_bytes(int32_t n, int sampler = kSamplerBfs) {
+  return (sampler == kSamplerKruskal ? 16 : 12) * (size_t)n;
+}
 
 template <int NT>
 hipError_t launch_wg(fi_graph* g, const SweepArgs& a, int path, hipStream_t s) {
@@ -53,7 +58,7 @@ hipError_t launch_wg(fi_graph* g, const SweepArgs& a, int path, hipStream_t s) {
   const DevGraph& G = g->dg;
   int grid = g->sched.grid;
   if (path == 1) {
-    const size_t lds = wg_lds_bytes(G.n);
+    const size_t lds = wg_lds_bytes(G.n, a.sampler);
     hipError_t ea = hipFuncSetAttribute((const void*)k_sweep_wg<NT, true>,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (ea != hipSuccess) return ea;
@@ -76,9 +81,17 @@ hipError_t launch_wg(fi_graph* g, const SweepArgs& a, int path, hipStream_t s) {
 }
 
 int pick_path(fi_graph* g) {
-  if (g->sched.path != 0) return g->sched.path;
   const int32_t n = g->dg.n;
-  if (wg_lds_bytes(n) + 32768 <= (size_t)g->max_shared) return 1;
+  const bool fits = wg_lds_bytes(n, g->sampler) + 32768 <= (size_t)g->max_shared;
+  if (g->sampler != kSamplerBfs) {
+    // the other samplers run one tree per workgroup only
+    if (g->sched.path == 1 && fits) return 1;
+    if (g->sched.path == 2 && g->L.nslots > 0) return 2;
+    if (fits) return 1;
+    return g->L.nslots > 0 ? 2 : 0;
+  }
+  if (g->sched.path != 0) return g->sched.path;
+  if (fits) return 1;
   if (n <= 200000 && g->L.nslots > 0) return 2;
   return 3;
 }
@@ -88,10 +101,11 @@ int pick_path(fi_graph* g) {
 hipError_t launch_sweep(fi_graph* g, const SweepArgs& a, hipStream_t s) {
   if (a.t1 <= a.t0) return hipSuccess;
   int path = pick_path(g);
+  if (path == 0) return hipErrorInvalidValue;  // a sampler other than BFS above 1M vertices
   // the multi-tree path keeps no per-tree state words to hand out; it alone
   // gathers the cloud statistics
   if (path == 4 && a.bits_out) path = 3;
-  if (a.vminus || a.eswitch) path = 4;
+  if (a.vminus || a.eswitch) path = 4;  // (BFS only: checked by the caller)
   const int nt = g->sched.block;
   void* tok = nullptr;
   if (prof_begin(g, s, &tok)) return hipErrorUnknown;
@@ -112,6 +126,16 @@ hipError_t launch_sweep(fi_graph* g, const SweepArgs& a, hipStream_t s) {
 
 using namespace fi;
 
+namespace {
+SweepArgs base_args(fi_graph* g, uint64_t seed) {
+  SweepArgs a{};
+  a.seed = seed;
+  a.sampler = g->sampler;
+  a.cptr = (const int32_t*)(g->ws + g->L.cptr);
+  return a;
+}
+}  // namespace
+
 extern "C" {
 
 int fi_sweep_range(fi_graph* g, int64_t t0, int64_t t1, uint64_t seed, uint64_t* d_tree_switches,
@@ -119,8 +143,7 @@ int fi_sweep_range(fi_graph* g, int64_t t0, int64_t t1, uint64_t seed, uint64_t*
   if (!g || g->is_batch || t0 < 0 || t1 < t0) return FI_EINVAL;
   if (t1 > ((int64_t)1 << 32)) return FI_ERANGE;
   if (t1 == t0) return FI_OK;
-  SweepArgs a{};
-  a.seed = seed;
+  SweepArgs a = base_args(g, seed);
   a.t0 = (uint64_t)t0;
   a.t1 = (uint64_t)t1;
   a.tree_switches = d_tree_switches;
@@ -131,18 +154,35 @@ int fi_sweep_range(fi_graph* g, int64_t t0, int64_t t1, uint64_t seed, uint64_t*
 
 int fi_sweep_stats(fi_graph* g, int64_t t0, int64_t t1, uint64_t seed, uint64_t* d_vertex_minus,
                    uint64_t* d_edge_switched, void* stream) {
-  if (!g || g->is_batch || t0 < 0 || t1 < t0 || (!d_vertex_minus && !d_edge_switched))
+  if (!g || g->is_batch || t0 < 0 || t1 < t0 || (!d_vertex_minus && !d_edge_switched) ||
+      g->sampler != kSamplerBfs)
     return FI_EINVAL;
   if (t1 > ((int64_t)1 << 32)) return FI_ERANGE;
   if (t1 == t0) return FI_OK;
-  SweepArgs a{};
-  a.seed = seed;
+  SweepArgs a = base_args(g, seed);
   a.t0 = (uint64_t)t0;
   a.t1 = (uint64_t)t1;
   a.insert = 1;
   a.vminus = d_vertex_minus;
   a.eswitch = d_edge_switched;
   return launch_sweep(g, a, (hipStream_t)stream) == hipSuccess ? FI_OK : FI_EDEVICE;
+}
+
+int fi_set_sampler(fi_graph* g, int32_t sampler) {
+  if (!g || g->is_batch || sampler < kSamplerBfs || sampler > kSamplerKruskal) return FI_EINVAL;
+  if (sampler != kSamplerBfs && g->L.nslots == 0) {
+    // one tree per workgroup needs the tree in LDS or in a workspace slot
+    const size_t lds = (sampler == kSamplerKruskal ? 16 : 12) * (size_t)g->dg.n;
+    if (lds + 32768 > (size_t)g->max_shared) return FI_ERANGE;
+  }
+  g->sampler = sampler;
+  return FI_OK;
+}
+
+int fi_get_sampler(fi_graph* g, int32_t* out) {
+  if (!g || g->is_batch || !out) return FI_EINVAL;
+  *out = g->sampler;
+  return FI_OK;
 }
 
 int fi_sweep(fi_graph* g, int64_t K, uint64_t seed, void* stream) {
@@ -153,8 +193,7 @@ int fi_tree_state(fi_graph* g, uint64_t seed, int64_t t, uint64_t* d_bits_out,
                   uint64_t* d_switches_out, void* stream) {
   if (!g || g->is_batch || t < 0 || !d_bits_out) return FI_EINVAL;
   if (t >= ((int64_t)1 << 32)) return FI_ERANGE;
-  SweepArgs a{};
-  a.seed = seed;
+  SweepArgs a = base_args(g, seed);
   a.t0 = (uint64_t)t;
   a.t1 = (uint64_t)t + 1;
   a.tree_switches = d_switches_out;

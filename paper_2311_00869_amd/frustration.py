@@ -33,7 +33,8 @@ SYMBOLS = (
     "fi_bcloud_workspace_size", "fi_bcloud_fmax_for", "fi_bcloud_create", "fi_bcloud_destroy",
     "fi_bcloud_reset", "fi_bcloud_merge", "fi_sweep_bounded", "fi_bcloud_size", "fi_bcloud_read",
     "fi_bcloud_min", "fi_bcloud_stats", "fi_edge_list", "fi_switch_list", "fi_sweep_stats",
-    "fi_graphl_descend", "fi_graphl_aux_size", "fi_graphl_scales",
+    "fi_graphl_descend", "fi_graphl_aux_size", "fi_graphl_scales", "fi_set_sampler",
+    "fi_get_sampler",
 )
 
 
@@ -115,6 +116,8 @@ def load_library(path: str = LIB_PATH):
             "fi_graphl_descend": ([vp, vp, vp, i32, c.c_float, i64, i32, vp, sz, vp], c.c_int),
             "fi_graphl_aux_size": ([vp, i32, P(sz)], c.c_int),
             "fi_graphl_scales": ([vp, vp, i32, vp, vp], c.c_int),
+            "fi_set_sampler": ([vp, i32], c.c_int),
+            "fi_get_sampler": ([vp, P(i32)], c.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -373,6 +376,18 @@ class Graph:
         _check(self.lib.fi_round_count(self.handle, _ptr(g), R, _ptr(counts), _ptr(bits),
                                        _stream_ptr(stream)), "round_count")
         return (counts, bits) if return_bits else counts
+
+    SAMPLERS = {"bfs": 0, "rdfs": 1, "hybrid": 2, "kruskal": 3}
+
+    def set_sampler(self, sampler="bfs"):
+        """Tree sampler: "bfs", "rdfs", "hybrid" (Alg. alg-hybrid) or "kruskal"."""
+        code = self.SAMPLERS[sampler] if isinstance(sampler, str) else int(sampler)
+        _check(self.lib.fi_set_sampler(self.handle, code), "set_sampler")
+
+    def get_sampler(self) -> str:
+        out = ctypes.c_int32()
+        _check(self.lib.fi_get_sampler(self.handle, ctypes.byref(out)), "get_sampler")
+        return {v: k for k, v in self.SAMPLERS.items()}[out.value]
 
     # ---------------------------------------------------------------- tuning / timing
     def set_schedule(self, path=0, block=256, grid=0, heavy=512, batch=4):
