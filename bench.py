@@ -79,6 +79,8 @@ def main():
                     help="skip the memory-bound cloud leg (Alg. alg-scale)")
     ap.add_argument("--no-switches", action="store_true",
                     help="skip the switch-list and cloud-statistics leg")
+    ap.add_argument("--no-samplers", action="store_true",
+                    help="skip the leg timing the other tree samplers")
     ap.add_argument("--no-graphl-large", action="store_true",
                     help="skip graphL on the main graph (32 restarts x 500 steps)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -208,6 +210,8 @@ def main():
         del batch_graphs
     if not args.no_planted:
         extra["planted"] = bench_planted(fr, synth, tune, torch)
+    if not args.no_samplers:
+        extra["samplers"] = bench_samplers(fr, synth, torch)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -511,6 +515,31 @@ def bench_planted(fr, synth, tune, torch, trees=10_000):
         "distinct_states": G.cloud_size(),
     }
     G.close()
+    return out
+
+
+def bench_samplers(fr, synth, torch):
+    """Trees per second of every sampler (one tree per workgroup) on the
+    1,000-vertex graph and on a 100,000-vertex graph, with the best switch
+    count each reached."""
+    out = {}
+    for name, g, K in (("n=1,000 m=5,000", synth.config_small(0), 8192),
+                       ("n=100,000 m=500,000", synth.erdos_renyi_connected(100000, 500000, 0.8, 7), 512)):
+        G = fr.Graph(g.row_ptr, g.col, g.sign, cloud_capacity=K)
+        row = {}
+        for smp in ("bfs", "rdfs", "hybrid", "kruskal"):
+            G.set_sampler(smp)
+            G.cloud_reset()
+            G.sweep(64, 99)
+            torch.cuda.synchronize()
+            G.cloud_reset()
+            t0 = time.perf_counter()
+            G.sweep(K, 0)
+            best = G.min_frustration()
+            el = time.perf_counter() - t0
+            row[smp] = {"trees_per_s": round(K / el, 1), "min_switches": best[0]}
+        out[f"{name}, {K} trees"] = row
+        G.close()
     return out
 
 
