@@ -80,6 +80,28 @@ typedef struct {
   uint64_t first_tree;
 } fi_cloud_entry;
 
+/* ---------------------------------------------------------------- input cleaning */
+
+/* Bytes of device workspace for fi_clean of E raw entries.  FI_ERANGE if
+ * 2E >= 2^31. */
+int fi_clean_workspace_size(int32_t n, int64_t E, size_t* out_bytes);
+
+/* The paper's input cleaning (Section "Implementation": duplicates,
+ * inconsistencies, self-loops and invalid signs are eliminated) on the GPU,
+ * producing the symmetric sorted CSR that fi_graph_create takes.  Raw entry
+ * i is (d_src[i], d_dst[i], d_sign[i]), int32 each, in any order and either
+ * direction.  An entry with an endpoint outside 0 .. n-1 or a sign other
+ * than +1 / -1 is invalid and dropped; self-loops are dropped; a vertex pair
+ * met with one sign keeps one edge (the other entries are duplicates); a
+ * pair met with both signs is inconsistent and dropped.  Outputs: d_row_ptr
+ * int32[n+1], d_col int32 and d_sign_out int8 with room for 2E entries (the
+ * first row_ptr[n] are written, rows sorted), and h_counts int64[5] (host) =
+ * kept edges, invalid entries, self-loops, duplicate entries, inconsistent
+ * pairs.  Blocks. */
+int fi_clean(int32_t n, int64_t E, const int32_t* d_src, const int32_t* d_dst, const int32_t* d_sign,
+             void* d_workspace, size_t ws_bytes, int32_t* d_row_ptr, int32_t* d_col,
+             int8_t* d_sign_out, int64_t* h_counts, void* stream);
+
 /* ---------------------------------------------------------------- graph */
 
 /* Bytes of device workspace for a graph with n vertices, nnz CSR entries
