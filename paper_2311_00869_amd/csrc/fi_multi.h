@@ -73,7 +73,7 @@ __device__ __forceinline__ uint64_t pull_edges(const uint32_t* adj, const uint64
     uint32_t H = 0;
     uint64_t F = 0, S = 0;
     if (e < e1) {
-      const uint32_t a = __builtin_nontemporal_load(adj + e);
+      const uint32_t a = adj[e];
       const uint32_t u = a & kVertexMask;
       F = nbw[u] & want;
       if (F) S = stw[u] ^ ((a >> 31) ? ~0ull : 0ull);
@@ -190,7 +190,7 @@ __device__ __forceinline__ uint64_t pull_small(const DevGraph& G, const MState& 
     uint32_t H = 0;
     uint64_t F = 0, S = 0;
     if (lane < total) {
-      const uint32_t a = __builtin_nontemporal_load(G.adj + (int64_t)sk + (eb + lane - ek));
+      const uint32_t a = G.adj[(int64_t)sk + (eb + lane - ek)];
       const uint32_t u = a & kVertexMask;
       F = A.nbw[pp][u] & wk;
       if (F) S = A.stw[u] ^ ((a >> 31) ? ~0ull : 0ull);

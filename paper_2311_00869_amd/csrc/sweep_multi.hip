@@ -616,9 +616,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
         const int64_t e = e0 + tid;
         uint64_t x = 0;
         if (e < G.m) {
-          // streamed once per pass: keep it from evicting the gathered state words
-          const uint64_t w = __builtin_nontemporal_load((const uint64_t*)G.edges + e);
-          const uint2 uv = make_uint2((uint32_t)w, (uint32_t)(w >> 32));
+          const uint2 uv = G.edges[e];
           x = A.S.stw[uv.x] ^ A.S.stw[uv.y & kVertexMask];
           if (uv.y >> 31) x = ~x;
           // one owner per edge word in every pass
