@@ -227,6 +227,7 @@ hipError_t launch_grid(fi_graph* g, const SweepArgs& a, hipStream_t s);
 hipError_t launch_multi(fi_graph* g, const SweepArgs& a, hipStream_t s);
 hipError_t launch_count(const DevGraph& dg, const uint64_t* bits, int32_t B, uint64_t* counts,
                         hipStream_t s);
+hipError_t graphl_setup(fi_graph* g, hipStream_t s);
 
 }  // namespace fi
 
@@ -240,7 +241,7 @@ struct fi_graph {
   uint64_t table_size;
   int32_t ncomp, nisolated, nanch;
   int32_t mtasks, mnbig;  // multi-tree path: root-finding tasks, big components
-  bool gl_heavy_built;    // graphL heavy-row list is in the workspace
+  int32_t gl_nheavy;      // graphL rows longer than kGLHeavy (their items are planned at upload)
   int32_t sampler;        // kSampler*
   int32_t gl_main_slot;   // slot of the component with the most vertices (-1: none)
   fi_schedule sched;

@@ -673,6 +673,7 @@ int fi_graph_create(int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int3
                        (uint64_t*)(ws + L.grootkey), nroot, kUnvisited);
   }
   if (build_components(g, s) != FI_OK) return fail(FI_EDEVICE);
+  if (graphl_setup(g, s) != hipSuccess) return fail(FI_EDEVICE);
   hipLaunchKernelGGL(k_fill_u64, dim3(64), dim3(B), 0, s, (uint64_t*)(ws + L.gbar),
                      (int64_t)kGridSlots * kGridBarWords, 0ull);
   hipLaunchKernelGGL(k_fill_u64, dim3(4), dim3(B), 0, s, (uint64_t*)(ws + L.gctl),

@@ -190,6 +190,102 @@ __global__ void __launch_bounds__(kGLBlock) k_gl_rows(const int32_t* rp, const u
   if (scaled) block_max_main(A, mx_main, s_mx, P, R, sub, grp, gpb, active);
 }
 
+// The same for R divisible by 4: each lane owns four consecutive restarts and
+// gathers them as one 16-byte load, so a wave covers 64 / (R / 4) rows per
+// load instead of 64 / R and keeps that many more row gathers in flight.
+// Every restart's sum runs over the row in the same order as in k_gl_rows,
+// so the results are the same bit for bit.
+__global__ void __launch_bounds__(kGLBlock) k_gl_rows4(const int32_t* rp, const uint32_t* adj,
+                                                       int32_t n, const float* gamma, int R,
+                                                       RowArgs A, float* out) {
+  __shared__ float s_mx[kGLBlock][4];
+  const int RV = R / 4;
+  const int P = lanes_for(RV);
+  const int sub = threadIdx.x % P;
+  const int grp = threadIdx.x / P;
+  const int gpb = kGLBlock / P;
+  const bool active = sub < RV;
+  const bool scaled = A.max_in != nullptr;
+  const int r0 = 4 * sub;
+  float wr[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) wr[k] = (A.w && active) ? (float)A.w[r0 + k] : 1.0f;
+  if (scaled)
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < A.ncr;
+         k += (int64_t)gridDim.x * blockDim.x)
+      A.max_clear[k] = 0;
+  float mx_main[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  if (active) {
+    for (int64_t i = (int64_t)blockIdx.x * gpb + grp; i < n; i += (int64_t)gridDim.x * gpb) {
+      const int64_t e0 = rp[i], e1 = rp[i + 1];
+      if (e1 - e0 > kGLHeavy) continue;
+      const int32_t c = scaled ? row_slot(A, i, e0, e1) : -1;
+      float sc[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) sc[k] = scaled ? pair_scale(A, c, R, r0 + k) : 1.0f;
+      float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+      int64_t e = e0;
+      for (; e + 7 < e1; e += 8) {
+        uint32_t a[8];
+        float4 x[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a[j] = adj[e + j];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          x[j] = *reinterpret_cast<const float4*>(gamma + (size_t)(a[j] & kVertexMask) * R + r0);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const bool ng = (a[j] >> 31) != 0;
+          const float x0 = x[j].x * sc[0], x1 = x[j].y * sc[1], x2 = x[j].z * sc[2],
+                      x3 = x[j].w * sc[3];
+          acc[0] += ng ? -x0 : x0;
+          acc[1] += ng ? -x1 : x1;
+          acc[2] += ng ? -x2 : x2;
+          acc[3] += ng ? -x3 : x3;
+        }
+      }
+      for (; e < e1; ++e) {
+        const uint32_t a = adj[e];
+        const float4 x = *reinterpret_cast<const float4*>(gamma + (size_t)(a & kVertexMask) * R + r0);
+        const bool ng = (a >> 31) != 0;
+        const float x0 = x.x * sc[0], x1 = x.y * sc[1], x2 = x.z * sc[2], x3 = x.w * sc[3];
+        acc[0] += ng ? -x0 : x0;
+        acc[1] += ng ? -x1 : x1;
+        acc[2] += ng ? -x2 : x2;
+        acc[3] += ng ? -x3 : x3;
+      }
+      const size_t o = (size_t)i * R + r0;
+      const float4 self = *reinterpret_cast<const float4*>(gamma + o);
+      const float sv[4] = {self.x, self.y, self.z, self.w};
+      float v[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float g = -0.5f * acc[k] * wr[k];
+        v[k] = A.update ? sv[k] * sc[k] - A.alpha * g : g;
+      }
+      *reinterpret_cast<float4*>(out + o) = make_float4(v[0], v[1], v[2], v[3]);
+      if (scaled)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) note_row(A, i, c, R, r0 + k, sc[k], v[k], mx_main[k]);
+    }
+  }
+  if (scaled) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s_mx[threadIdx.x][k] = mx_main[k];
+    __syncthreads();
+    if (grp == 0 && active && A.main_slot >= 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        float m = 0.0f;
+        for (int g = 0; g < gpb; ++g) m = fmaxf(m, s_mx[g * P + sub][k]);
+        if (m > 0.0f)
+          atomicMax((unsigned int*)&A.max_out[(size_t)A.main_slot * R + r0 + k],
+                    __float_as_uint(m));
+      }
+    }
+  }
+}
+
 // Heavy rows (more than kGLHeavy entries) are cut into items of up to
 // kGLChunk entries spread over workgroups.  An item's groups stride over its
 // entries and their sums are added in group order into part[item][r]; a row
@@ -365,16 +461,13 @@ hipError_t launch_rows(fi_graph* g, const float* gin, int R, const RowArgs& A, f
   int2* items = (int2*)(g->ws + L.glitems);
   float* part = (float*)(g->ws + L.glpart);
   uint32_t* ctl = gl_ctl(g);
-  if (!g->gl_heavy_built) {
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, ctl, (int64_t)2, 0u);
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)g->dg.n + 255) / 256, 16384));
-    hipLaunchKernelGGL(k_gl_heavy_list, dim3(grid), dim3(256), 0, s, g->dg.row_ptr, g->dg.n, list,
-                       ctl);
-    hipLaunchKernelGGL(k_gl_plan, dim3(1), dim3(1024), 0, s, g->dg.row_ptr, list, ctl, first, items);
-    g->gl_heavy_built = true;
-  }
-  hipLaunchKernelGGL(k_gl_rows, dim3(rows_grid(g->dg.n, R)), dim3(kGLBlock), 0, s, g->dg.row_ptr,
-                     g->dg.adj, g->dg.n, gin, R, A, out);
+  if (R % 4 == 0 && (uintptr_t)gin % 16 == 0 && (uintptr_t)out % 16 == 0)
+    hipLaunchKernelGGL(k_gl_rows4, dim3(rows_grid(g->dg.n, R / 4)), dim3(kGLBlock), 0, s,
+                       g->dg.row_ptr, g->dg.adj, g->dg.n, gin, R, A, out);
+  else
+    hipLaunchKernelGGL(k_gl_rows, dim3(rows_grid(g->dg.n, R)), dim3(kGLBlock), 0, s,
+                       g->dg.row_ptr, g->dg.adj, g->dg.n, gin, R, A, out);
+  if (g->gl_nheavy == 0) return hipGetLastError();
   const int cgrid = (int)std::min<int64_t>((int64_t)L.glicap, 8192);
   hipLaunchKernelGGL(k_gl_chunks, dim3(cgrid), dim3(kGLBlock), 0, s, g->dg.row_ptr, g->dg.adj, list,
                      items, ctl, gin, R, A, part);
@@ -387,6 +480,28 @@ hipError_t launch_rows(fi_graph* g, const float* gin, int R, const RowArgs& A, f
 }
 
 }  // namespace
+
+// At graph upload: the rows longer than kGLHeavy and their items (blocks).
+hipError_t graphl_setup(fi_graph* g, hipStream_t s) {
+  const Layout& L = g->L;
+  int32_t* list = (int32_t*)(g->ws + L.glheavy);
+  int32_t* first = (int32_t*)(g->ws + L.glfirst);
+  int2* items = (int2*)(g->ws + L.glitems);
+  uint32_t* ctl = gl_ctl(g);
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, ctl, (int64_t)2, 0u);
+  if (g->dg.n > 0) {
+    const int grid =
+        (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)g->dg.n + 255) / 256, 16384));
+    hipLaunchKernelGGL(k_gl_heavy_list, dim3(grid), dim3(256), 0, s, g->dg.row_ptr, g->dg.n, list,
+                       ctl);
+    hipLaunchKernelGGL(k_gl_plan, dim3(1), dim3(1024), 0, s, g->dg.row_ptr, list, ctl, first, items);
+  }
+  uint32_t cnt[2] = {0, 0};
+  hipError_t e = hipMemcpyAsync(cnt, ctl, sizeof(cnt), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  g->gl_nheavy = (int32_t)cnt[0];
+  return e == hipSuccess ? hipGetLastError() : e;
+}
 
 }  // namespace fi
 
