@@ -357,19 +357,28 @@ def bench_graphl_large(synth, torch, G, R=32, steps=500, alpha=0.001):
 
 
 def bench_graphl(fr, synth, torch):
-    """graphL on the 1,000-vertex graph: 32 restarts x 500 fused steps, against
-    32 separate single-restart runs (the plain per-restart path)."""
+    """graphL on the 1,000-vertex graph: 32 restarts x 500 steps in one
+    launch (fi_graphl_descend) then rounding and the exact count, against one
+    launch per step for all restarts and against 32 separate single-restart
+    runs (the plain per-restart path)."""
     g = synth.config_small(0)
     G = fr.Graph(g.row_ptr, g.col, g.sign, cloud_capacity=16)
     R, steps, alpha = 32, 500, 0.001
     gamma0 = torch.from_numpy(synth.graphl_init(g.n, R, 0)).cuda()
+    G.graphl_descend(gamma0, 20, alpha)
     fr.graphl_descent(G, gamma0, 20, alpha)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    out = fr.graphl_descent(G, gamma0, steps, alpha)
+    out, _ = G.graphl_descend(gamma0, steps, alpha)
     counts = G.round_count(out)
     torch.cuda.synchronize()
     batched = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    stepwise = fr.graphl_descent(G, gamma0, steps, alpha)
+    G.round_count(stepwise)
+    torch.cuda.synchronize()
+    per_step = time.perf_counter() - t0
+    assert torch.equal(stepwise, out)
     t0 = time.perf_counter()
     for r in range(R):
         o = fr.graphl_descent(G, gamma0[:, r:r + 1].contiguous(), steps, alpha)
@@ -392,6 +401,7 @@ def bench_graphl(fr, synth, torch):
         "workload": "n=1,000 m=5,000, 32 restarts, 500 steps, alpha=0.001",
         "steps_per_s": round(steps / batched, 1),
         "restart_steps_per_s": round(steps * R / batched, 1),
+        "launch_per_step_steps_per_s": round(steps / per_step, 1),
         "plain_per_restart_restart_steps_per_s": round(steps * R / plain, 1),
         "autograd_steps_per_s": round(1.0 / autograd, 1),
         "best_rounded_frustration": int(counts.min().item()),

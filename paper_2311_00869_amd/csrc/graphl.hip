@@ -9,6 +9,11 @@
 #include "fi_internal.h"
 #include "fi_prims.h"
 
+// No multiply-add contraction in this file: every kernel that computes an
+// update rounds the same operations the same way, so the fused small-graph
+// descent, the per-step kernels and their vector variants agree bit for bit.
+#pragma clang fp contract(off)
+
 namespace fi {
 
 namespace {
@@ -385,6 +390,85 @@ __global__ void __launch_bounds__(1024) k_gl_plan(const int32_t* rp, const int32
   }
 }
 
+// The whole descent on a small graph without long rows: one workgroup per
+// restart, Gamma's column in LDS (ping-pong), and the per-component maxima
+// and scales of the overflow policy in LDS too, so the steps run with no
+// launch between them.  Same rows, same order, same operations as the
+// per-step kernels.  LDS: 8n (Gamma) + 4n (component slots) + 16 C bytes,
+// plus the CSR itself (4(n+1) + 4 nnz) when it fits, so that a step touches
+// no global memory.
+constexpr int kSmallDescentN = 4096;
+constexpr size_t kSmallDescentLds = 128 * 1024;
+
+template <bool CSR_IN_LDS>
+__global__ void __launch_bounds__(1024) k_gl_descend_small(const int32_t* rp_g,
+                                                           const uint32_t* adj_g,
+                                                           const int32_t* comp,
+                                                           const int32_t* aslot, int32_t n,
+                                                           int32_t ncomp, int R, float alpha,
+                                                           int64_t steps, int shift, float* gamma,
+                                                           int32_t* exps) {
+  extern __shared__ uint32_t sm[];
+  float* G0 = (float*)sm;
+  float* G1 = G0 + n;
+  int32_t* cs = (int32_t*)(G1 + n);
+  uint32_t* mx = (uint32_t*)(cs + n);  // [3][ncomp]
+  int32_t* ex = (int32_t*)(mx + 3 * ncomp);
+  const int32_t* rp = rp_g;
+  const uint32_t* adj = adj_g;
+  if (CSR_IN_LDS) {
+    int32_t* rp_l = ex + ncomp;
+    uint32_t* adj_l = (uint32_t*)(rp_l + n + 1);
+    const int32_t nnz = rp_g[n];
+    for (int32_t i = threadIdx.x; i <= n; i += blockDim.x) rp_l[i] = rp_g[i];
+    for (int32_t e = threadIdx.x; e < nnz; e += blockDim.x) adj_l[e] = adj_g[e];
+    rp = rp_l;
+    adj = adj_l;
+    __syncthreads();
+  }
+  const int r = blockIdx.x;
+  const uint32_t thresh = (uint32_t)(127 + shift) << 23;
+  const float down = __uint_as_float((uint32_t)(127 - shift) << 23);
+  for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
+    G0[i] = gamma[(size_t)i * R + r];
+    cs[i] = rp[i + 1] > rp[i] ? aslot[comp[i]] : -1;
+  }
+  for (int32_t c = threadIdx.x; c < 3 * ncomp; c += blockDim.x) mx[c] = 0;
+  for (int32_t c = threadIdx.x; c < ncomp; c += blockDim.x) ex[c] = 0;
+  __syncthreads();
+  float* gin = G0;
+  float* gout = G1;
+  for (int64_t k = 0; k < steps; ++k) {
+    const uint32_t* min_ = mx + (k % 3) * ncomp;
+    uint32_t* mout = mx + ((k + 1) % 3) * ncomp;
+    uint32_t* mclr = mx + ((k + 2) % 3) * ncomp;
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
+      const int32_t c = cs[i];
+      const float sc = (c >= 0 && min_[c] >= thresh) ? down : 1.0f;
+      float acc = 0.0f;
+      for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+        const uint32_t a = adj[e];
+        const float gj = gin[a & kVertexMask] * sc;
+        acc += (a >> 31) ? -gj : gj;
+      }
+      const float g = -0.5f * acc * 1.0f;
+      const float v = gin[i] * sc - alpha * g;
+      gout[i] = v;
+      if (c >= 0) {
+        atomicMax(mout + c, __float_as_uint(fabsf(v)));
+        if (comp[i] == i && sc != 1.0f) ex[c] += shift;
+      }
+    }
+    for (int32_t c = threadIdx.x; c < ncomp; c += blockDim.x) mclr[c] = 0;
+    __syncthreads();
+    float* t = gin;
+    gin = gout;
+    gout = t;
+  }
+  for (int32_t i = threadIdx.x; i < n; i += blockDim.x) gamma[(size_t)i * R + r] = gin[i];
+  for (int32_t c = threadIdx.x; c < ncomp; c += blockDim.x) exps[(size_t)c * R + r] = ex[c];
+}
+
 // Per-vertex log2 scales of a descent: out[i][r] = the scale of (component
 // of i, r), 0 for vertices without edges.
 __global__ void k_gl_scales(const int32_t* rp, const int32_t* comp, const int32_t* aslot,
@@ -572,6 +656,26 @@ int fi_graphl_descend(fi_graph* g, float* d_gamma, float* d_work, int32_t R, flo
   hipLaunchKernelGGL(k_fill_u32, dim3(256), dim3(256), 0, s, (uint32_t*)aux,
                      (int64_t)(part), 0u);
   if (g->dg.n == 0 || steps == 0) return hipGetLastError() == hipSuccess ? FI_OK : FI_EDEVICE;
+  const int32_t ncomp = std::max<int32_t>(g->nanch, 1);
+  const size_t lds = 12 * (size_t)g->dg.n + 16 * (size_t)ncomp;
+  const size_t lds_csr = lds + 4 * ((size_t)g->dg.n + 1) + 4 * (size_t)g->dg.nnz;
+  if (g->dg.n <= kSmallDescentN && g->gl_nheavy == 0 && lds <= kSmallDescentLds) {
+    const int32_t* aslot = (const int32_t*)(g->ws + g->L.aslot);
+    if (lds_csr <= kSmallDescentLds) {
+      FI_HIP(hipFuncSetAttribute((const void*)k_gl_descend_small<true>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_csr));
+      hipLaunchKernelGGL(k_gl_descend_small<true>, dim3(R), dim3(1024), lds_csr, s, g->dg.row_ptr,
+                         g->dg.adj, g->dg.comp, aslot, g->dg.n, ncomp, (int)R, alpha, steps,
+                         (int)rescale_log2, d_gamma, (int32_t*)aux);
+    } else {
+      FI_HIP(hipFuncSetAttribute((const void*)k_gl_descend_small<false>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      hipLaunchKernelGGL(k_gl_descend_small<false>, dim3(R), dim3(1024), lds, s, g->dg.row_ptr,
+                         g->dg.adj, g->dg.comp, aslot, g->dg.n, ncomp, (int)R, alpha, steps,
+                         (int)rescale_log2, d_gamma, (int32_t*)aux);
+    }
+    return hipGetLastError() == hipSuccess ? FI_OK : FI_EDEVICE;
+  }
   float* buf[2] = {d_gamma, d_work};
   for (int64_t k = 0; k < steps; ++k) {
     RowArgs A{};

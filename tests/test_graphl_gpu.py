@@ -188,3 +188,31 @@ def test_descend_exact_across_rescale_thresholds(hub):
     ca, ba = G.round_count(a, return_bits=True)
     cb, bb = G.round_count(b, return_bits=True)
     assert torch.equal(ca, cb) and torch.equal(ba, bb)
+
+
+def test_fused_small_descent_policy():
+    # n = 3,000 and no row above 256 entries: the one-launch descent, with
+    # hubs of degree ~190 that overflow float32 within 100 steps at alpha = 0.3
+    g = synth.chung_lu(3000, 9000, 2.8, 3, p_pos=0.6)
+    assert int(np.diff(g.row_ptr).max()) <= 256
+    G = fr.Graph(g.row_ptr, g.col, g.sign, cloud_capacity=16)
+    R, steps, alpha = 5, 120, 0.3
+    gamma0 = torch.from_numpy(synth.graphl_init(g.n, R, 21)).cuda()
+    # no overflow yet: the same bits as the per-step kernels
+    plain = fr.graphl_descent(G, gamma0, 9, alpha)
+    early, _ = G.graphl_descend(gamma0, 9, alpha)
+    assert torch.equal(early, plain)
+    got, scales = G.graphl_descend(gamma0, steps, alpha)
+    assert torch.isfinite(got).all() and int(scales().max()) >= 64
+    ref = ogl.descent(g, gamma0.cpu().numpy(), steps, alpha)
+    true = _true(got, scales)
+    _, anchor = oracle.components(g)
+    deg = np.diff(g.row_ptr)
+    for a in np.unique(anchor[deg > 0]):
+        rows = anchor == a
+        for r in range(R):
+            top = np.abs(ref[rows, r]).max()
+            assert np.abs(true[rows, r] - ref[rows, r]).max() <= 1e-3 * top
+    b, sb = G.graphl_descend(gamma0, steps, alpha, rescale_log2=9)
+    assert np.array_equal(_true(b, sb), true)
+    G.close()
