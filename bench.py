@@ -174,7 +174,8 @@ def main():
     achieved = bpt * T / avg_launch_s / 1e9
     traffic = load_traffic(args.workload)
     roofline = {
-        "kernel": {3: "k_sweep_grid", 4: "k_sweep_multi"}.get(G.get_schedule()["path"], "k_sweep_wg"),
+        "kernel": {3: "k_sweep_grid", 4: "k_sweep_multi", 5: "k_sweep_multi"}.get(
+            G.get_schedule()["path"], "k_sweep_wg"),
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": None if traffic is None else traffic["bytes_per_launch"],

@@ -224,7 +224,7 @@ void prof_end(fi_graph* g, hipStream_t s, void* token, int kernel);
 // launchers implemented in the .hip files
 hipError_t launch_sweep(fi_graph* g, const SweepArgs& a, hipStream_t s);
 hipError_t launch_grid(fi_graph* g, const SweepArgs& a, hipStream_t s);
-hipError_t launch_multi(fi_graph* g, const SweepArgs& a, hipStream_t s);
+hipError_t launch_multi(fi_graph* g, const SweepArgs& a, int words, hipStream_t s);
 hipError_t launch_count(const DevGraph& dg, const uint64_t* bits, int32_t B, uint64_t* counts,
                         hipStream_t s);
 hipError_t graphl_setup(fi_graph* g, hipStream_t s);

@@ -249,5 +249,295 @@ __device__ __forceinline__ int select_lane(uint64_t mask, int k) {
   return lo;
 }
 
+// ------------------------------------------------------------ W words per vertex
+// The same helpers for passes of 64 W trees: every per-vertex array holds W
+// consecutive words per vertex (vertex v at v W .. v W + W - 1), word w, bit
+// t is tree 64 w + t, and lane t of a wavefront carries trees t, 64 + t, ...
+// A gather of a vertex's W words touches one cache line, so a pass of 64 W
+// trees moves about as many lines as a pass of 64.
+template <int W>
+struct TW {
+  uint64_t w[W];
+};
+
+template <int W>
+__device__ __forceinline__ TW<W> ldw(const uint64_t* a, int64_t v) {
+  TW<W> r;
+  if constexpr (W == 1) {
+    r.w[0] = a[v];
+  } else {
+    static_assert(W == 2, "one or two words per vertex");
+    const ulonglong2 x = *reinterpret_cast<const ulonglong2*>(a + 2 * v);
+    r.w[0] = x.x;
+    r.w[1] = x.y;
+  }
+  return r;
+}
+
+template <int W>
+__device__ __forceinline__ void stw_(uint64_t* a, int64_t v, const TW<W>& x) {
+  if constexpr (W == 1) {
+    a[v] = x.w[0];
+  } else {
+    *reinterpret_cast<ulonglong2*>(a + 2 * v) = make_ulonglong2(x.w[0], x.w[1]);
+  }
+}
+
+template <int W>
+__device__ __forceinline__ bool any_w(const TW<W>& x) {
+  uint64_t o = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) o |= x.w[w];
+  return o != 0;
+}
+
+template <int W>
+__device__ __forceinline__ bool eq_w(const TW<W>& a, const TW<W>& b) {
+  bool e = true;
+#pragma unroll
+  for (int w = 0; w < W; ++w) e = e && a.w[w] == b.w[w];
+  return e;
+}
+
+template <int W>
+__device__ __forceinline__ TW<W> and_not(const TW<W>& a, const TW<W>& b) {
+  TW<W> r;
+#pragma unroll
+  for (int w = 0; w < W; ++w) r.w[w] = a.w[w] & ~b.w[w];
+  return r;
+}
+
+template <int W>
+__device__ __forceinline__ TW<W> or_w(const TW<W>& a, const TW<W>& b) {
+  TW<W> r;
+#pragma unroll
+  for (int w = 0; w < W; ++w) r.w[w] = a.w[w] | b.w[w];
+  return r;
+}
+
+template <int W>
+__device__ __forceinline__ TW<W> shfl_w(const TW<W>& x, int src) {
+  TW<W> r;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)x.w[w], src);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(x.w[w] >> 32), src);
+    r.w[w] = ((uint64_t)hi << 32) | lo;
+  }
+  return r;
+}
+
+// Lane t, word w: minimum over the edges [e0, e1) of the candidate of every
+// neighbour discovered at the previous level of tree 64 w + t in a tree of
+// `want`, folded into best[w].
+template <int W>
+__device__ __forceinline__ void pull_edges_w(const uint32_t* adj, const uint64_t* nbw,
+                                             const uint64_t* stw, int64_t e0, int64_t e1,
+                                             const TW<W>& want, const KeyMix* km, uint64_t* best) {
+  const int lane = lane_id();
+  for (int64_t c = e0; c < e1; c += 64) {
+    const int64_t e = c + lane;
+    uint32_t H = 0;
+    TW<W> F{}, S{};
+    bool hit = false;
+    if (e < e1) {
+      const uint32_t a = adj[e];
+      const uint32_t u = a & kVertexMask;
+      const TW<W> nb = ldw<W>(nbw, u);
+#pragma unroll
+      for (int w = 0; w < W; ++w) F.w[w] = nb.w[w] & want.w[w];
+      hit = any_w(F);
+      if (hit) {
+        const TW<W> st = ldw<W>(stw, u);
+        const uint64_t neg = (a >> 31) ? ~0ull : 0ull;
+#pragma unroll
+        for (int w = 0; w < W; ++w) S.w[w] = st.w[w] ^ neg;
+      }
+      H = fmix32(u);
+    }
+    uint64_t hits = __ballot(hit);
+    while (hits) {
+      const int j = __builtin_ctzll(hits);
+      hits &= hits - 1;
+      const uint32_t Hj = __builtin_amdgcn_readlane(H, j);
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const uint64_t Fj = readlane64(F.w[w], j);
+        const uint64_t Sj = readlane64(S.w[w], j);
+        if ((Fj >> lane) & 1) {
+          const uint64_t c2 = ((uint64_t)vkey_of(km[w], Hj) << 1) | ((Sj >> lane) & 1);
+          best[w] = c2 < best[w] ? c2 : best[w];
+        }
+      }
+    }
+  }
+}
+
+// Lane t, word w: the minimum root candidate of tree 64 w + t over
+// cverts[b, e).
+template <int W>
+__device__ __forceinline__ void comp_min_w(const int32_t* cverts, int32_t b, int32_t e,
+                                           const KeyMix* km, uint64_t* best) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int w = 0; w < W; ++w) best[w] = kUnvisited;
+  for (int32_t c = b; c < e; c += 64) {
+    const int32_t i = c + lane;
+    const int32_t mine = i < e ? cverts[i] : 0;
+    const int cnt = min(64, e - c);
+    const uint32_t hm = fmix32((uint32_t)mine);
+    for (int j = 0; j < cnt; ++j) {
+      const uint32_t v = (uint32_t)__builtin_amdgcn_readlane(mine, j);
+      const uint32_t h = (uint32_t)__builtin_amdgcn_readlane((int)hm, j);
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const uint64_t k = root_candidate(vkey_of(km[w], h), v);
+        best[w] = k < best[w] ? k : best[w];
+      }
+    }
+  }
+}
+
+// The write-back of vertex v once its trees of this level are decided.
+template <int W>
+__device__ __forceinline__ bool settle_w(const MState& A, int32_t v, const TW<W>& vis,
+                                         const TW<W>& st, int dv, const uint64_t* best, int p,
+                                         const TW<W>& valid, uint64_t& cnt, uint64_t& deg,
+                                         uint64_t& fin) {
+  TW<W> newb, stb;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    newb.w[w] = __ballot(best[w] != kUnvisited);
+    stb.w[w] = __ballot(best[w] != kUnvisited && (best[w] & 1));
+  }
+  if (!any_w(newb)) return false;
+  const TW<W> nv = or_w(vis, newb);
+  const bool full = eq_w(nv, valid);
+  if (lane_id() == 0) {
+    stw_<W>(A.vis, v, nv);
+    stw_<W>(A.nbw[p], v, newb);
+    if (any_w(stb)) stw_<W>(A.stw, v, or_w(st, stb));
+    if (full) aand64(A.unf + (v >> 6), ~(1ull << (v & 63)));
+  }
+  if (full) fin += (uint64_t)dv;
+  cnt += 1;
+  deg += (uint64_t)dv;
+  return true;
+}
+
+// One wave pulls ne <= 64 vertices of rows up to 64 edges (as pull_small).
+template <int W>
+__device__ __forceinline__ uint64_t pull_small_w(const DevGraph& G, const MState& A, int32_t v,
+                                                 int ne, int pp, int p, const TW<W>& valid,
+                                                 const KeyMix* km, bool push, uint64_t& cnt,
+                                                 uint64_t& deg, uint64_t& fin) {
+  const int lane = lane_id();
+  const bool ok = lane < ne;
+  int s = 0, d = 0;
+  TW<W> vis{}, st{};
+  if (ok) {
+    s = G.row_ptr[v];
+    d = G.row_ptr[v + 1] - s;
+    vis = ldw<W>(A.vis, v);
+    st = ldw<W>(A.stw, v);
+  }
+  const TW<W> want = and_not(valid, vis);
+  int inc = d;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  const int excl = inc - d;
+  TW<W> mnew{}, mstb{};  // outcome of this lane's row
+  int k0 = 0;
+  while (k0 < ne) {
+    const int eb = uni(__shfl(excl, k0));
+    const bool inr = ok && lane >= k0 && inc - eb <= 64;
+    const uint64_t fit = __ballot(inr);
+    const int k1 = k0 + (int)__popcll(fit);
+    const int total = uni(__shfl(inc, k1 - 1)) - eb;
+    const int e = inc - eb;
+    const uint64_t starts = 1ull | wave_or64(inr && e < total ? (1ull << e) : 0ull);
+    const int r = (int)__popcll(starts & ((2ull << lane) - 1));
+    const int kj = k0 + r - 1;
+    const int sk = __shfl(s, kj);
+    const int ek = __shfl(excl, kj);
+    const TW<W> wk = shfl_w<W>(want, kj);
+    uint32_t H = 0;
+    TW<W> F{}, S{};
+    bool hit = false;
+    if (lane < total) {
+      const uint32_t a = G.adj[(int64_t)sk + (eb + lane - ek)];
+      const uint32_t u = a & kVertexMask;
+      const TW<W> nb = ldw<W>(A.nbw[pp], u);
+#pragma unroll
+      for (int w = 0; w < W; ++w) F.w[w] = nb.w[w] & wk.w[w];
+      hit = any_w(F);
+      if (hit) {
+        const TW<W> su = ldw<W>(A.stw, u);
+        const uint64_t neg = (a >> 31) ? ~0ull : 0ull;
+#pragma unroll
+        for (int w = 0; w < W; ++w) S.w[w] = su.w[w] ^ neg;
+      }
+      H = fmix32(u);
+    }
+    uint64_t hits = __ballot(hit);
+    uint64_t best[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) best[w] = kUnvisited;
+    int cur = -1;
+    auto keep = [&]() {
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const uint64_t nb = __ballot(best[w] != kUnvisited);
+        const uint64_t sb = __ballot(best[w] != kUnvisited && (best[w] & 1));
+        if (lane == cur) {
+          mnew.w[w] = nb;
+          mstb.w[w] = sb;
+        }
+      }
+    };
+    while (hits) {
+      const int jj = __builtin_ctzll(hits);
+      hits &= hits - 1;
+      const int kk = __builtin_amdgcn_readlane(kj, jj);
+      if (kk != cur) {
+        if (cur >= 0) keep();
+#pragma unroll
+        for (int w = 0; w < W; ++w) best[w] = kUnvisited;
+        cur = kk;
+      }
+      const uint32_t Hj = __builtin_amdgcn_readlane(H, jj);
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const uint64_t Fj = readlane64(F.w[w], jj);
+        const uint64_t Sj = readlane64(S.w[w], jj);
+        if ((Fj >> lane) & 1) {
+          const uint64_t c2 = ((uint64_t)vkey_of(km[w], Hj) << 1) | ((Sj >> lane) & 1);
+          best[w] = c2 < best[w] ? c2 : best[w];
+        }
+      }
+    }
+    if (cur >= 0) keep();
+    k0 = k1;
+  }
+  const bool got = ok && any_w(mnew);
+  const TW<W> nv = or_w(vis, mnew);
+  const bool full = got && eq_w(nv, valid);
+  if (got) {
+    stw_<W>(A.vis, v, nv);
+    stw_<W>(A.nbw[p], v, mnew);
+    if (any_w(mstb)) stw_<W>(A.stw, v, or_w(st, mstb));
+    if (full) aand64(A.unf + (v >> 6), ~(1ull << (v & 63)));
+  }
+  if (ok && push) aand64(A.cand + (v >> 6), ~(1ull << (v & 63)));
+  const uint64_t reached = __ballot(got);
+  cnt += (uint64_t)__popcll(reached);
+  deg += wave_sum_u64(got ? (uint64_t)d : 0ull);
+  fin += wave_sum_u64(full ? (uint64_t)d : 0ull);
+  return reached;
+}
+
 }  // namespace mt
 }  // namespace fi

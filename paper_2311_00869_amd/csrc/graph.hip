@@ -442,9 +442,9 @@ Layout make_layout(int32_t n, int64_t nnz, int64_t cloud_capacity, uint64_t tabl
   L.slots = take(L.slot_stride * L.nslots);
   // multi-tree path (the lists, bitmaps, control and barrier words are the
   // whole-grid path's, which never runs at the same time)
-  L.mrec = take(40 * nn);  // two 16-byte records and a visited word per vertex
+  L.mrec = take(64 * nn);  // four arrays of up to two 8-byte tree words per vertex
   L.mhcap = (size_t)nnz / kMSplit + 1;
-  L.mhslot = take(8 * 64 * L.mhcap);
+  L.mhslot = take(8 * 128 * L.mhcap);
   // reached bitmaps over the two levels' list entries: light, then split rows
   L.mreach = take(8 * (4 * ((nn + 64) / 64 + 2) + 2 * (L.mhcap / 64 + 2)));
   L.aslot = take(4 * nn);
@@ -454,7 +454,7 @@ Layout make_layout(int32_t n, int64_t nnz, int64_t cloud_capacity, uint64_t tabl
   L.mtcap = nn / 2 + nn / kRootChunk + 2;
   L.mtasks = take(16 * L.mtcap);
   L.nbigcap = nn / kBigComp + 1;
-  L.rootbig = take(8 * 64 * L.nbigcap);
+  L.rootbig = take(8 * 128 * L.nbigcap);
   L.swtile = take(16 * ((size_t)switch_tiles((int64_t)m) + 1));
   L.glheavy = take(4 * ((size_t)nnz / kGLHeavy + 2));
   L.glfirst = take(4 * ((size_t)nnz / kGLHeavy + 3));
@@ -829,7 +829,7 @@ int fi_count(fi_graph* g, const uint64_t* d_bits, int32_t B, uint64_t* d_counts,
 
 int fi_set_schedule(fi_graph* g, const fi_schedule* sc) {
   if (!g || !sc) return FI_EINVAL;
-  if (sc->path < 0 || sc->path > 4) return FI_EINVAL;
+  if (sc->path < 0 || sc->path > 5 || (g->is_batch && sc->path == 5)) return FI_EINVAL;
   if (sc->block != 256 && sc->block != 512 && sc->block != 1024) return FI_EINVAL;
   if (sc->grid < 0 || sc->heavy < 32 || sc->batch < 1 || sc->batch > kGridSlots) return FI_EINVAL;
   if (sc->grid > 16 * 4096) return FI_EINVAL;

@@ -104,14 +104,14 @@ hipError_t launch_sweep(fi_graph* g, const SweepArgs& a, hipStream_t s) {
   if (path == 0) return hipErrorInvalidValue;  // a sampler other than BFS above 1M vertices
   // the multi-tree path keeps no per-tree state words to hand out; it alone
   // gathers the cloud statistics
-  if (path == 4 && a.bits_out) path = 3;
-  if (a.vminus || a.eswitch) path = 4;  // (BFS only: checked by the caller)
+  if ((path == 4 || path == 5) && a.bits_out) path = 3;
+  if (a.vminus || a.eswitch) path = path == 5 ? 5 : 4;  // (BFS only: checked by the caller)
   const int nt = g->sched.block;
   void* tok = nullptr;
   if (prof_begin(g, s, &tok)) return hipErrorUnknown;
   hipError_t e;
-  if (path == 4) {
-    e = launch_multi(g, a, s);
+  if (path == 4 || path == 5) {
+    e = launch_multi(g, a, path == 5 ? 2 : 1, s);
   } else if (path == 3) {
     e = launch_grid(g, a, s);
   } else {

@@ -1,11 +1,13 @@
-// Multi-tree sweep for large graphs: the trees of Alg. alg-index taken 64 at
-// a time, one bit per tree in every per-vertex word (bit t is tree t0 + t and
-// lane t of every wavefront).
+// Multi-tree sweep for large graphs: the trees of Alg. alg-index taken 64 W
+// at a time (W = 1 or 2 words per vertex), one bit per tree in every
+// per-vertex word (word w, bit t is tree t0 + 64 w + t, carried by lane t of
+// every wavefront).  A vertex's W words are adjacent, so gathering them costs
+// one cache line whatever W is: the pass time grows far less than its tree
+// count, and W = 2 sweeps more trees per second.
 //
-// Each vertex has two 16-byte records, one per level parity, each holding
-// the trees in which it was discovered at the last level of that parity and
-// its state bits, plus a word of the trees that have visited it.  One BFS
-// level then serves all 64 trees with one pass over the rows involved:
+// Per vertex: the trees that discovered it at the last even and at the last
+// odd level, its state bits, and the trees that have visited it.  One BFS
+// level then serves all 64 W trees with one pass over the rows involved:
 //   push - while the frontier is small, its rows mark as candidates every
 //          neighbour still unvisited in a tree where the frontier vertex was
 //          just discovered;
@@ -25,7 +27,7 @@
 // clearing between levels.
 // After the BFS, bit-sliced counters over the edge list give every tree's
 // frustrated-edge count, 64x64 bit transposes of the state words give its
-// canonical key, and the 64 trees enter the cloud.
+// canonical key, and the pass's trees enter the cloud.
 //
 // Memory discipline across XCDs: within one phase a word is either written
 // with plain stores by its single owner or updated with atomics, never both.
@@ -49,11 +51,11 @@ constexpr int kSmall = 32;         // rows up to this many edges are pulled 64 v
 constexpr int kMedChunk = 64;      // medium frontier rows per push unit
 constexpr int kPlanes = 8;         // bit-sliced counter planes (flushed every 255 edges)
 
-// Per-vertex state in separate 8-byte words: the trees that discovered the
-// vertex at the last even / odd level, its state bits, the trees that have
-// visited it.  A pull gathers the previous parity's discovery word of every
-// neighbour (a 128 MB array at 16M vertices) and the state word only for
-// neighbours that hit some tree.
+// Per-vertex state in separate arrays of W 8-byte words per vertex: the
+// trees that discovered the vertex at the last even / odd level, its state
+// bits, the trees that have visited it.  A pull gathers the previous
+// parity's discovery words of every neighbour (128 MB per word at 16M
+// vertices) and the state words only for neighbours that hit some tree.
 
 // Control words; each group sits on its own 128-byte line.  r = level mod 4.
 //   F(r): the level's pull lists and frontier: small-row count, heavy
@@ -62,14 +64,14 @@ constexpr int kPlanes = 8;         // bit-sliced counter planes (flushed every 2
 //   TP(r), TQ(r), TM(r): work tickets of the push phase, of the split-row
 //         parts and of the medium rows
 //   UNF: degree sum of vertices not yet visited by every tree
-//   ACC + 4 t: tree t's switches, key_hi, key_lo
+//   ACC + 4 t: tree t's switches, key_hi, key_lo (t < 64 W)
 __host__ __device__ constexpr int cF(int r) { return 16 * r; }
 __host__ __device__ constexpr int cTP(int r) { return 128 + 16 * r; }
 __host__ __device__ constexpr int cTQ(int r) { return 192 + 16 * r; }
 __host__ __device__ constexpr int cTM(int r) { return 384 + 16 * r; }
 constexpr int cUNF = 256;
 constexpr int cACC = 512;
-constexpr int kMCtlWords = 768;
+constexpr int kMCtlWords = 1024;  // ACC holds 4 words for each of up to 128 trees
 static_assert(kMCtlWords <= kGridSlots * kGridCtlWords, "control block");
 
 struct MArgs {
@@ -87,19 +89,19 @@ struct MArgs {
   uint64_t* rm;         // [2][rlstride] entries of pm some tree reached
   uint64_t* rh;         // [2][rhstride] entries of ph some tree reached
   int64_t lstride, hstride, rlstride, rhstride;
-  uint64_t* hslot;      // [rows][64] partial minima of split rows
+  uint64_t* hslot;      // [rows][64 W] partial minima of split rows
   const int4* tasks;    // root tasks: (begin, end) in cverts, big slot or -1
   const int32_t* cverts;
-  uint64_t* rootbig;    // [big components][64]
+  uint64_t* rootbig;    // [big components][64 W]
   uint64_t* ctl;
   uint64_t* bar;
 };
 
-template <int NT>
+template <int NT, int W>
 struct MS {
   int off[NT];
   int start[NT];
-  uint64_t base[NT];
+  uint64_t base[NT * W];
   int scan[NT / 64 + 1];
   int32_t q[kStageM];   // staging: small rows
   int32_t q2[kStageM];  // staging: medium rows
@@ -112,13 +114,13 @@ struct MS {
   uint64_t cnt, deg, fin;
   int mode, active;
   uint32_t nl, nm, nh, hunits;
-  uint64_t hbest[64];
-  uint64_t tacc[3][64];
+  uint64_t hbest[64 * W];
+  uint64_t tacc[3][64 * W];
 };
 
 // Move the LDS staging list into a global list (one reservation per block).
-template <int NT>
-__device__ __forceinline__ void mflush1(MS<NT>& sh, int32_t* q, uint32_t* qn, int32_t* list,
+template <int NT, class SH>
+__device__ __forceinline__ void mflush1(SH& sh, int32_t* q, uint32_t* qn, int32_t* list,
                                         uint64_t* counter) {
   __syncthreads();
   const uint32_t k = *qn;
@@ -133,8 +135,8 @@ __device__ __forceinline__ void mflush1(MS<NT>& sh, int32_t* q, uint32_t* qn, in
   __syncthreads();
 }
 // both staging lists into the level's small and medium lists
-template <int NT>
-__device__ __forceinline__ void mflush(MS<NT>& sh, int32_t* ls, int32_t* lm, uint64_t* ring) {
+template <int NT, class SH>
+__device__ __forceinline__ void mflush(SH& sh, int32_t* ls, int32_t* lm, uint64_t* ring) {
   mflush1<NT>(sh, sh.q, &sh.qn, ls, ring);
   mflush1<NT>(sh, sh.q2, &sh.qn2, lm, ring + 4);
 }
@@ -152,8 +154,8 @@ __device__ __forceinline__ void stage(bool pred, int32_t v, int32_t* q, uint32_t
     if (pred) q[base + lanes_below(mask)] = v;
   }
 }
-template <int NT>
-__device__ __forceinline__ void mlist(bool in, int32_t v, int dv, MS<NT>& sh, int2* qh,
+template <class SH>
+__device__ __forceinline__ void mlist(bool in, int32_t v, int dv, SH& sh, int2* qh,
                                       uint64_t* ring) {
   const bool heavy = in && dv > kMSplit;
   stage(in && dv <= kSmall, v, sh.q, &sh.qn);
@@ -180,48 +182,59 @@ __device__ __forceinline__ void mlist_global(bool in, int32_t v, int dv, int32_t
   }
 }
 
-// Roots of one component (the wave owns it): lanes are grouped by root
-// vertex; each root's record gets the trees it roots, and it enters the
-// level-0 lists.  cnt / deg gather the wave's roots and their degrees, fin
-// (in the lanes that wrote a root) the degrees of vertices already visited
-// by every tree.
-__device__ __forceinline__ void set_roots(uint64_t best, bool vlane, uint64_t valid, const MArgs& A,
-                                          const int32_t* rp, uint64_t& cnt, uint64_t& deg,
-                                          uint64_t& fin) {
+// Roots of one component (the wave owns it): each distinct root vertex, over
+// all W words, gets the trees it roots in its records and enters the level-0
+// lists once.  cnt / deg gather the wave's roots and their degrees, fin (in
+// lane 0) the degrees of roots already visited by every tree.
+template <int W>
+__device__ __forceinline__ void set_roots(const uint64_t* best, const bool* vlane,
+                                          const TW<W>& valid, const MArgs& A, const int32_t* rp,
+                                          uint64_t& cnt, uint64_t& deg, uint64_t& fin) {
   const int lane = lane_id();
-  const bool ok = vlane && best != kUnvisited;
-  const uint32_t r = (uint32_t)word_vertex(best);
-  uint64_t rem = __ballot(ok);
-  bool leader = false;
-  uint64_t mine = 0;
-  while (rem) {
-    const int j = __builtin_ctzll(rem);
-    const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)r, j);
-    const uint64_t m = __ballot(ok && r == r0);
-    rem &= ~m;
-    if (lane == j) {
-      leader = true;
-      mine = m;
-    }
+  bool ok[W];
+  uint32_t r[W];
+  uint64_t rem[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    ok[w] = vlane[w] && best[w] != kUnvisited;
+    r[w] = (uint32_t)word_vertex(best[w]);
+    rem[w] = __ballot(ok[w]);
   }
-  int dv = 0;
-  if (leader) {
-    dv = rp[r + 1] - rp[r];
-    A.S.nbw[0][r] = mine;
-    A.S.vis[r] = mine;
-    if (mine == valid) {
-      aand64(A.S.unf + (r >> 6), ~(1ull << (r & 63)));
-      fin += (uint64_t)dv;
+  while (true) {
+    int ww = -1;
+#pragma unroll
+    for (int w = W - 1; w >= 0; --w)
+      if (rem[w]) ww = w;
+    if (ww < 0) break;
+    uint32_t r0 = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+      if (w == ww) r0 = (uint32_t)__builtin_amdgcn_readlane((int)r[w], __builtin_ctzll(rem[w]));
+    TW<W> mine;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      mine.w[w] = __ballot(ok[w] && r[w] == r0);
+      rem[w] &= ~mine.w[w];
     }
+    const int dv = rp[r0 + 1] - rp[r0];
+    const bool full = eq_w(mine, valid);
+    if (lane == 0) {
+      stw_<W>(A.S.nbw[0], r0, mine);
+      stw_<W>(A.S.vis, r0, mine);
+      if (full) {
+        aand64(A.S.unf + (r0 >> 6), ~(1ull << (r0 & 63)));
+        fin += (uint64_t)dv;
+      }
+    }
+    mlist_global(lane == 0, (int32_t)r0, dv, A.pl, A.pm, A.ph, A.ctl + cF(0));
+    cnt += 1;
+    deg += (uint64_t)dv;
   }
-  mlist_global(leader, (int32_t)r, dv, A.pl, A.pm, A.ph, A.ctl + cF(0));
-  cnt += (uint64_t)__popcll(__ballot(leader));
-  deg += wave_sum_u64(leader ? (uint64_t)dv : 0ull);
 }
 
-template <int NT, bool STATS>
+template <int NT, bool STATS, int W>
 __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
-  __shared__ MS<NT> sh;
+  __shared__ MS<NT, W> sh;
   constexpr int NW = NT / 64;
   const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
   const uint32_t rank = blockIdx.x, nb = gridDim.x;
@@ -231,14 +244,21 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
   const int32_t* rp = G.row_ptr;
   uint64_t* ctl = A.ctl;
 
-  for (uint64_t tb = A.t0; tb < A.t1; tb += 64) {
-    const int nvalid = (int)min<uint64_t>(64, A.t1 - tb);
-    const uint64_t valid = nvalid == 64 ? ~0ull : ((1ull << nvalid) - 1);
-    const bool vlane = lane < nvalid;
-    const KeyMix km = key_mix(tree_salt(A.seed, tb + lane));
+  for (uint64_t tb = A.t0; tb < A.t1; tb += 64 * W) {
+    const int nvalid = (int)min<uint64_t>(64 * W, A.t1 - tb);
+    TW<W> valid;
+    bool vlane[W];
+    KeyMix km[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const int nv = nvalid - 64 * w;
+      valid.w[w] = nv >= 64 ? ~0ull : nv > 0 ? ((1ull << nv) - 1) : 0ull;
+      vlane[w] = lane < nv;
+      km[w] = key_mix(tree_salt(A.seed, tb + 64 * w + lane));
+    }
 
     // ---- reset: records, bitmaps, control words
-    for (int64_t v = stid; v < n; v += sstride) {
+    for (int64_t v = stid; v < (int64_t)n * W; v += sstride) {
       A.S.nbw[0][v] = 0;
       A.S.nbw[1][v] = 0;
       A.S.stw[v] = 0;
@@ -262,18 +282,27 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
       uint64_t cnt = 0, deg = 0, fin = 0;
       for (int64_t k = gwave; k < A.ntasks; k += nwaves) {
         const int4 tk = A.tasks[k];
-        const uint64_t best = comp_min(A.cverts, tk.x, tk.y, km);
-        if (tk.z < 0)
-          set_roots(best, vlane, valid, A, rp, cnt, deg, fin);
-        else if (vlane && best != kUnvisited)
-          amin64(A.rootbig + (size_t)tk.z * 64 + lane, best);
+        uint64_t best[W];
+        comp_min_w<W>(A.cverts, tk.x, tk.y, km, best);
+        if (tk.z < 0) {
+          set_roots<W>(best, vlane, valid, A, rp, cnt, deg, fin);
+        } else {
+#pragma unroll
+          for (int w = 0; w < W; ++w)
+            if (vlane[w] && best[w] != kUnvisited)
+              amin64(A.rootbig + (size_t)tk.z * 64 * W + 64 * w + lane, best[w]);
+        }
       }
       group_sync(A.bar, rank, nb);
       for (int64_t b = gwave; b < A.nbig; b += nwaves) {
-        uint64_t* rb = A.rootbig + (size_t)b * 64;
-        const uint64_t best = vlane ? rb[lane] : kUnvisited;
-        if (vlane) rb[lane] = kUnvisited;
-        set_roots(best, vlane, valid, A, rp, cnt, deg, fin);
+        uint64_t* rb = A.rootbig + (size_t)b * 64 * W;
+        uint64_t best[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          best[w] = vlane[w] ? rb[64 * w + lane] : kUnvisited;
+          if (vlane[w]) rb[64 * w + lane] = kUnvisited;
+        }
+        set_roots<W>(best, vlane, valid, A, rp, cnt, deg, fin);
       }
       fin = wave_sum_u64(fin);
       if (lane == 0) {
@@ -357,10 +386,10 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
           if (k >= U) break;
           int total = 0;
           int64_t e0 = 0;
-          uint64_t hbits = 0;
+          TW<W> hbits{};
           if (k < nchunks) {
             int d = 0, st = 0;
-            uint64_t bits = 0;
+            TW<W> bits{};
             int32_t u = -1;
             if (k < nsc) {
               const uint32_t i = k * NT + tid;
@@ -372,12 +401,15 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
             if (u >= 0) {
               st = rp[u];
               d = rp[u + 1] - st;
-              bits = A.S.nbw[pp][u] & valid;
+              const TW<W> nbu = ldw<W>(A.S.nbw[pp], u);
+#pragma unroll
+              for (int w = 0; w < W; ++w) bits.w[w] = nbu.w[w] & valid.w[w];
             }
             const int off = block_exclusive_scan<NT>(d, total, sh.scan);
             sh.off[tid] = off;
             sh.start[tid] = st;
-            sh.base[tid] = bits;
+#pragma unroll
+            for (int w = 0; w < W; ++w) sh.base[tid * W + w] = bits.w[w];
             __syncthreads();
             total = uni(total);
           } else {
@@ -398,7 +430,9 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
               const uint32_t part = hk - (uint32_t)uni(sh.heavy.y);
               e0 = rp[u] + (int64_t)part * kMSplit;
               const int64_t e1 = min<int64_t>(rp[u + 1], e0 + kMSplit);
-              hbits = A.S.nbw[pp][u] & valid;
+              const TW<W> nbu = ldw<W>(A.S.nbw[pp], u);
+#pragma unroll
+              for (int w = 0; w < W; ++w) hbits.w[w] = nbu.w[w] & valid.w[w];
               total = (int)(e1 - e0);
             }
           }
@@ -409,17 +443,18 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
             int dv = 0;
             if (j < total) {
               uint32_t a;
-              uint64_t bits;
+              TW<W> bits;
               if (k < nchunks) {
                 const int kk = upper_index(sh.off, NT, j);
                 a = G.adj[sh.start[kk] + (j - sh.off[kk])];
-                bits = sh.base[kk];
+#pragma unroll
+                for (int w = 0; w < W; ++w) bits.w[w] = sh.base[kk * W + w];
               } else {
                 a = G.adj[e0 + j];
                 bits = hbits;
               }
               v = (int32_t)(a & kVertexMask);
-              if (bits & ~A.S.vis[v]) {
+              if (any_w(and_not(bits, ldw<W>(A.S.vis, v)))) {
                 const uint64_t bit = 1ull << (v & 63);
                 if (!(aor64(A.S.cand + (v >> 6), bit) & bit)) {
                   first = true;
@@ -427,7 +462,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
                 }
               }
             }
-            mlist<NT>(first, v, dv, sh, phn, rf);
+            mlist(first, v, dv, sh, phn, rf);
             __syncthreads();
             if (sh.qn > kStageM - NT || sh.qn2 > kStageM - NT) mflush<NT>(sh, pln, pmn, rf);
           }
@@ -441,7 +476,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
           const bool in = (bits >> lane) & 1;
           const int32_t v = (int32_t)(w * 64 + lane);
           const int dv = in ? rp[v + 1] - rp[v] : 0;
-          mlist<NT>(in, v, dv, sh, phn, rf);
+          mlist(in, v, dv, sh, phn, rf);
           __syncthreads();
           if (sh.qn > kStageM - NT || sh.qn2 > kStageM - NT) mflush<NT>(sh, pln, pmn, rf);
         }
@@ -474,8 +509,9 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
           const int64_t b = (int64_t)rank + (int64_t)uni((int)i) * nb;
           if (b * 64 >= nl) break;
           const int ne = (int)min<int64_t>(64, nl - b * 64);
-          const uint64_t r = pull_small(G, A.S, b * 64 + lane < nl ? pln[b * 64 + lane] : 0, ne, pp, p, valid,
-                                        km, push, cnt, deg, fin);
+          const uint64_t r =
+              pull_small_w<W>(G, A.S, b * 64 + lane < nl ? pln[b * 64 + lane] : 0, ne, pp, p, valid,
+                              km, push, cnt, deg, fin);
           if (lane == 0) rln[b] = r;
         }
         // medium rows: block b owns rows b, b + nb, ...; its waves draw them
@@ -489,19 +525,26 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
             if (i >= (int64_t)nm) break;
             const int32_t v = pmn[i];
             const int64_t e0 = rp[v], e1 = rp[v + 1];
-            const uint64_t visq = A.S.vis[v], stq = A.S.stw[v];
-            const uint64_t want = valid & ~visq;
-            uint64_t best = kUnvisited;
-            if (want) best = pull_edges(G.adj, A.S.nbw[pp], A.S.stw, e0, e1, pp, want, km, best);
-            const uint64_t mnew = __ballot(best != kUnvisited);
-            const uint64_t mstb = __ballot(best != kUnvisited && (best & 1));
+            const TW<W> visq = ldw<W>(A.S.vis, v), stq = ldw<W>(A.S.stw, v);
+            const TW<W> want = and_not(valid, visq);
+            uint64_t best[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) best[w] = kUnvisited;
+            if (any_w(want)) pull_edges_w<W>(G.adj, A.S.nbw[pp], A.S.stw, e0, e1, want, km, best);
+            TW<W> mnew, mstb;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+              mnew.w[w] = __ballot(best[w] != kUnvisited);
+              mstb.w[w] = __ballot(best[w] != kUnvisited && (best[w] & 1));
+            }
             const int dq = (int)(e1 - e0);
-            if (mnew) {
-              const bool full = (visq | mnew) == valid;
+            if (any_w(mnew)) {
+              const TW<W> nv = or_w(visq, mnew);
+              const bool full = eq_w(nv, valid);
               if (lane == 0) {
-                A.S.vis[v] = visq | mnew;
-                A.S.nbw[p][v] = mnew;
-                if (mstb) A.S.stw[v] = stq | mstb;
+                stw_<W>(A.S.vis, v, nv);
+                stw_<W>(A.S.nbw[p], v, mnew);
+                if (any_w(mstb)) stw_<W>(A.S.stw, v, or_w(stq, mstb));
                 if (full) aand64(A.S.unf + (v >> 6), ~(1ull << (v & 63)));
                 aor64(rmn + (i >> 6), 1ull << (i & 63));
               }
@@ -537,22 +580,28 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
             sh.hidx = lo;
             sh.heavy = phn[lo];
           }
-          if (tid < 64) sh.hbest[tid] = kUnvisited;
+          if (tid < 64 * W) sh.hbest[tid] = kUnvisited;
           __syncthreads();
           const int32_t v = uni(sh.heavy.x);
           const uint32_t part = hk - (uint32_t)uni(sh.heavy.y);
           const int64_t e0 = rp[v] + (int64_t)part * kMSplit;
           const int64_t e1 = min<int64_t>(rp[v + 1], e0 + kMSplit);
-          const uint64_t want = valid & ~A.S.vis[v];
+          const TW<W> want = and_not(valid, ldw<W>(A.S.vis, v));
           const int64_t seg = ((e1 - e0 + NW - 1) / NW + 63) / 64 * 64;
           const int64_t s0 = min<int64_t>(e1, e0 + (int64_t)wave * seg);
           const int64_t s1 = min<int64_t>(e1, s0 + seg);
-          uint64_t best = kUnvisited;
-          if (want && s0 < s1) best = pull_edges(G.adj, A.S.nbw[pp], A.S.stw, s0, s1, pp, want, km, best);
-          if (best != kUnvisited) atomicMin((unsigned long long*)&sh.hbest[lane], (unsigned long long)best);
+          uint64_t best[W];
+#pragma unroll
+          for (int w = 0; w < W; ++w) best[w] = kUnvisited;
+          if (any_w(want) && s0 < s1)
+            pull_edges_w<W>(G.adj, A.S.nbw[pp], A.S.stw, s0, s1, want, km, best);
+#pragma unroll
+          for (int w = 0; w < W; ++w)
+            if (best[w] != kUnvisited)
+              atomicMin((unsigned long long*)&sh.hbest[64 * w + lane], (unsigned long long)best[w]);
           __syncthreads();
-          if (tid < 64 && sh.hbest[tid] != kUnvisited)
-            amin64(A.hslot + (size_t)sh.hidx * 64 + tid, sh.hbest[tid]);
+          if (tid < 64 * W && sh.hbest[tid] != kUnvisited)
+            amin64(A.hslot + (size_t)sh.hidx * 64 * W + tid, sh.hbest[tid]);
         }
         __syncthreads();
         if (tid == 0) {
@@ -571,12 +620,16 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
         uint64_t cnt = 0, deg = 0, fin = 0;
         for (int64_t h = gwave; h < (int64_t)nheavy; h += nwaves) {
           const int32_t v = phn[h].x;
-          uint64_t* hs = A.hslot + (size_t)h * 64;
-          const uint64_t best = hs[lane];
-          if (best != kUnvisited) hs[lane] = kUnvisited;
-          const uint64_t vis = A.S.vis[v], st = A.S.stw[v];
+          uint64_t* hs = A.hslot + (size_t)h * 64 * W;
+          uint64_t best[W];
+#pragma unroll
+          for (int w = 0; w < W; ++w) {
+            best[w] = hs[64 * w + lane];
+            if (best[w] != kUnvisited) hs[64 * w + lane] = kUnvisited;
+          }
+          const TW<W> vis = ldw<W>(A.S.vis, v), st = ldw<W>(A.S.stw, v);
           const int dv = rp[v + 1] - rp[v];
-          if (settle(A.S, v, vis, st, dv, best, p, valid, cnt, deg, fin) && lane == 0)
+          if (settle_w<W>(A.S, v, vis, st, dv, best, p, valid, cnt, deg, fin) && lane == 0)
             aor64(rhn + (h >> 6), 1ull << (h & 63));
           if (push && lane == 0) aand64(A.S.cand + (v >> 6), ~(1ull << (v & 63)));
         }
@@ -591,78 +644,117 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
       }
     }
 
-    // ---- counts and canonical keys of the 64 trees
+    // ---- counts and canonical keys of the 64 W trees
     {
-      if (tid < 192) (&sh.tacc[0][0])[tid] = 0;
+      for (int i = tid; i < 3 * 64 * W; i += NT) (&sh.tacc[0][0])[i] = 0;
       __syncthreads();
-      uint64_t c[kPlanes];
+      uint64_t myS[W];
 #pragma unroll
-      for (int b = 0; b < kPlanes; ++b) c[b] = 0;
-      uint64_t myS = 0;
-      int it = 0;
-      auto flush = [&]() {
-        for (int t = 0; t < 64; ++t) {
-          uint32_t tot = 0;
+      for (int w = 0; w < W; ++w) myS[w] = 0;
+      {
+        uint64_t c[W][kPlanes];
 #pragma unroll
-          for (int b = 0; b < kPlanes; ++b)
-            tot += (uint32_t)__popcll(__ballot((c[b] >> t) & 1)) << b;
-          if (lane == t) myS += tot;
-        }
+        for (int w = 0; w < W; ++w)
 #pragma unroll
-        for (int b = 0; b < kPlanes; ++b) c[b] = 0;
-      };
-      // frustrated iff the edge is negative xor the endpoint states differ
-      for (int64_t e0 = (int64_t)rank * NT; e0 < G.m; e0 += sstride) {
-        const int64_t e = e0 + tid;
-        uint64_t x = 0;
-        if (e < G.m) {
-          const uint2 uv = G.edges[e];
-          x = A.S.stw[uv.x] ^ A.S.stw[uv.y & kVertexMask];
-          if (uv.y >> 31) x = ~x;
-          // one owner per edge word in every pass
-          if constexpr (STATS)
-            if (A.eswitch) A.eswitch[e] += (uint64_t)__popcll(x & valid);
-        }
+          for (int b = 0; b < kPlanes; ++b) c[w][b] = 0;
+        int it = 0;
+        auto flush = [&]() {
 #pragma unroll
-        for (int b = 0; b < kPlanes; ++b) {
-          const uint64_t carry = c[b] & x;
-          c[b] ^= x;
-          x = carry;
+          for (int w = 0; w < W; ++w) {
+            for (int t = 0; t < 64; ++t) {
+              uint32_t tot = 0;
+#pragma unroll
+              for (int b = 0; b < kPlanes; ++b)
+                tot += (uint32_t)__popcll(__ballot((c[w][b] >> t) & 1)) << b;
+              if (lane == t) myS[w] += tot;
+            }
+#pragma unroll
+            for (int b = 0; b < kPlanes; ++b) c[w][b] = 0;
+          }
+        };
+        // frustrated iff the edge is negative xor the endpoint states differ
+        for (int64_t e0 = (int64_t)rank * NT; e0 < G.m; e0 += sstride) {
+          const int64_t e = e0 + tid;
+          TW<W> x{};
+          if (e < G.m) {
+            const uint2 uv = G.edges[e];
+            const TW<W> su = ldw<W>(A.S.stw, uv.x), sv = ldw<W>(A.S.stw, uv.y & kVertexMask);
+            const uint64_t neg = (uv.y >> 31) ? ~0ull : 0ull;
+#pragma unroll
+            for (int w = 0; w < W; ++w) x.w[w] = su.w[w] ^ sv.w[w] ^ neg;
+            // one owner per edge word in every pass
+            if constexpr (STATS) {
+              if (A.eswitch) {
+                uint64_t k = 0;
+#pragma unroll
+                for (int w = 0; w < W; ++w) k += (uint64_t)__popcll(x.w[w] & valid.w[w]);
+                A.eswitch[e] += k;
+              }
+            }
+          }
+#pragma unroll
+          for (int w = 0; w < W; ++w) {
+            uint64_t xw = x.w[w];
+#pragma unroll
+            for (int b = 0; b < kPlanes; ++b) {
+              const uint64_t carry = c[w][b] & xw;
+              c[w][b] ^= xw;
+              xw = carry;
+            }
+          }
+          if (++it == 255) {
+            flush();
+            it = 0;
+          }
         }
-        if (++it == 255) {
-          flush();
-          it = 0;
-        }
+        flush();
       }
-      flush();
       // canonical words: state relative to the component's anchor
-      uint64_t khi = 0, klo = 0;
+      uint64_t khi[W], klo[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) khi[w] = klo[w] = 0;
       for (int64_t i = gwave; i < nw; i += nwaves) {
         const int64_t v = i * 64 + lane;
-        uint64_t cs = 0;
-        if (v < n) cs = A.S.stw[v] ^ A.S.stw[G.comp[v]];
-        if constexpr (STATS)
-          if (A.vminus && v < n) A.vminus[v] += (uint64_t)__popcll(cs & valid);
-        uint64_t W = 0;
-        for (int t = 0; t < 64; ++t) {
-          const uint64_t b = __ballot((cs >> t) & 1);
-          if (lane == t) W = b;
+        TW<W> cs{};
+        if (v < n) {
+          const TW<W> a = ldw<W>(A.S.stw, v), b = ldw<W>(A.S.stw, G.comp[v]);
+#pragma unroll
+          for (int w = 0; w < W; ++w) cs.w[w] = a.w[w] ^ b.w[w];
         }
-        key_terms((uint64_t)i, W, khi, klo);
+        if constexpr (STATS) {
+          if (A.vminus && v < n) {
+            uint64_t k = 0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) k += (uint64_t)__popcll(cs.w[w] & valid.w[w]);
+            A.vminus[v] += k;
+          }
+        }
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          uint64_t Wd = 0;
+          for (int t = 0; t < 64; ++t) {
+            const uint64_t b = __ballot((cs.w[w] >> t) & 1);
+            if (lane == t) Wd = b;
+          }
+          key_terms((uint64_t)i, Wd, khi[w], klo[w]);
+        }
       }
-      atomicAdd((unsigned long long*)&sh.tacc[0][lane], (unsigned long long)myS);
-      atomicAdd((unsigned long long*)&sh.tacc[1][lane], (unsigned long long)khi);
-      atomicAdd((unsigned long long*)&sh.tacc[2][lane], (unsigned long long)klo);
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        atomicAdd((unsigned long long*)&sh.tacc[0][64 * w + lane], (unsigned long long)myS[w]);
+        atomicAdd((unsigned long long*)&sh.tacc[1][64 * w + lane], (unsigned long long)khi[w]);
+        atomicAdd((unsigned long long*)&sh.tacc[2][64 * w + lane], (unsigned long long)klo[w]);
+      }
       __syncthreads();
-      if (tid < 64) {
-        aadd64(ctl + cACC + 4 * tid, sh.tacc[0][tid]);
-        aadd64(ctl + cACC + 4 * tid + 1, sh.tacc[1][tid]);
-        aadd64(ctl + cACC + 4 * tid + 2, sh.tacc[2][tid]);
+      for (int t = tid; t < 64 * W; t += NT) {
+        aadd64(ctl + cACC + 4 * t, sh.tacc[0][t]);
+        aadd64(ctl + cACC + 4 * t + 1, sh.tacc[1][t]);
+        aadd64(ctl + cACC + 4 * t + 2, sh.tacc[2][t]);
       }
     }
     group_sync(A.bar, rank, nb);
 
-    // ---- the 64 trees enter the cloud
+    // ---- the trees of the pass enter the cloud
     if (rank == 0 && tid < nvalid) {
       const uint64_t S = load_agent(ctl + cACC + 4 * tid);
       const uint64_t hi = load_agent(ctl + cACC + 4 * tid + 1);
@@ -675,11 +767,11 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
   }
 }
 
-template <int NT, bool STATS>
+template <int NT, bool STATS, int W>
 hipError_t launch_mt(fi_graph* g, const MArgs& a, hipStream_t s) {
   int per_cu = 0;
   hipError_t e =
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_multi<NT, STATS>, NT, 0);
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_multi<NT, STATS, W>, NT, 0);
   if (e != hipSuccess) return e;
   if (per_cu < 1) return hipErrorInvalidConfiguration;
   const int maxg = per_cu * g->cu_count;
@@ -688,17 +780,27 @@ hipError_t launch_mt(fi_graph* g, const MArgs& a, hipStream_t s) {
   DevGraph G = g->dg;
   MArgs A = a;
   void* args[] = {(void*)&G, (void*)&A};
-  e = hipLaunchCooperativeKernel((const void*)k_sweep_multi<NT, STATS>, dim3(grid), dim3(NT), args,
-                                 0, s);
+  e = hipLaunchCooperativeKernel((const void*)k_sweep_multi<NT, STATS, W>, dim3(grid), dim3(NT),
+                                 args, 0, s);
   if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
+template <bool STATS, int W>
+hipError_t launch_mt_block(fi_graph* g, const MArgs& a, hipStream_t s) {
+  const int nt = g->sched.block;
+  return nt == 1024 ? launch_mt<1024, STATS, W>(g, a, s)
+         : nt == 512 ? launch_mt<512, STATS, W>(g, a, s)
+                     : launch_mt<256, STATS, W>(g, a, s);
+}
+
 }  // namespace
 
-hipError_t launch_multi(fi_graph* g, const SweepArgs& sa, hipStream_t s) {
+// words: tree words per vertex (1: 64 trees per pass, 2: 128)
+hipError_t launch_multi(fi_graph* g, const SweepArgs& sa, int words, hipStream_t s) {
   const Layout& L = g->L;
   char* ws = g->ws;
+  const int64_t nwv = (int64_t)g->dg.n * words;
   MArgs a{};
   a.seed = sa.seed;
   a.t0 = sa.t0;
@@ -710,9 +812,9 @@ hipError_t launch_multi(fi_graph* g, const SweepArgs& sa, hipStream_t s) {
   a.ntasks = g->mtasks;
   a.nbig = g->mnbig;
   a.S.nbw[0] = (uint64_t*)(ws + L.mrec);
-  a.S.nbw[1] = a.S.nbw[0] + g->dg.n;
-  a.S.stw = a.S.nbw[1] + g->dg.n;
-  a.S.vis = a.S.stw + g->dg.n;
+  a.S.nbw[1] = a.S.nbw[0] + nwv;
+  a.S.stw = a.S.nbw[1] + nwv;
+  a.S.vis = a.S.stw + nwv;
   a.S.unf = (uint64_t*)(ws + L.gvis);
   a.S.cand = (uint64_t*)(ws + L.gsb);
   a.lstride = (int64_t)g->dg.n + 64;
@@ -731,12 +833,10 @@ hipError_t launch_multi(fi_graph* g, const SweepArgs& sa, hipStream_t s) {
   a.rootbig = (uint64_t*)(ws + L.rootbig);
   a.ctl = (uint64_t*)(ws + L.gctl);
   a.bar = (uint64_t*)(ws + L.gbar);
-  const int nt = g->sched.block;
-  if (a.vminus || a.eswitch)
-    return nt == 1024 ? launch_mt<1024, true>(g, a, s) : nt == 512 ? launch_mt<512, true>(g, a, s)
-                                                                   : launch_mt<256, true>(g, a, s);
-  return nt == 1024 ? launch_mt<1024, false>(g, a, s) : nt == 512 ? launch_mt<512, false>(g, a, s)
-                                                                  : launch_mt<256, false>(g, a, s);
+  const bool stats = a.vminus || a.eswitch;
+  if (words == 2)
+    return stats ? launch_mt_block<true, 2>(g, a, s) : launch_mt_block<false, 2>(g, a, s);
+  return stats ? launch_mt_block<true, 1>(g, a, s) : launch_mt_block<false, 1>(g, a, s);
 }
 
 }  // namespace fi

@@ -27,6 +27,7 @@ def candidates(n: int, nnz: int):
             out.append(dict(path=3, block=b, grid=0, heavy=512, batch=batch))
     for b in (512, 1024):
         out.append(dict(path=4, block=b, grid=0, heavy=512, batch=1))
+        out.append(dict(path=5, block=b, grid=0, heavy=512, batch=1))
     return out
 
 
@@ -42,7 +43,7 @@ def default_schedule(n: int, nnz: int):
         return dict(path=1, block=512, grid=0, heavy=512, batch=1)
     if n <= 200_000:
         return dict(path=2, block=1024, grid=0, heavy=512, batch=1)
-    return dict(path=4, block=1024, grid=0, heavy=512, batch=1)
+    return dict(path=5, block=1024, grid=0, heavy=512, batch=1)
 
 
 def _load():

@@ -41,7 +41,8 @@ def test_bounded_cloud_matches_oracle(name, g):
     r = oracle.sweep(g, seed, 0, K, checks=False)
     distinct = len(r.cloud)
     bounds = sorted({1, 7, 64, max(1, distinct - 1), distinct, 5000})
-    scheds = [dict(path=0), dict(path=4, block=1024), dict(path=3, block=512, batch=4)]
+    scheds = [dict(path=0), dict(path=4, block=1024), dict(path=3, block=512, batch=4),
+              dict(path=5, block=1024)]
     if G.n <= 12000:
         scheds.append(dict(path=1, block=256))
     for fmax in bounds:

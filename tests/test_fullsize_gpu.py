@@ -45,6 +45,7 @@ def test_large_graph_bench_configuration():
     _check(G, gold, tune.default_schedule(G.n, G.nnz))
     _check(G, gold, dict(path=3, block=512, heavy=256, batch=1))
     _check(G, gold, dict(path=4, block=1024))
+    _check(G, gold, dict(path=5, block=1024))
     # every tree's frustrated edges, recounted by the exact counter from its state
     words, s0 = G.tree_state(gold["seed"], gold["t0"])
     got = int(G.count(torch.from_numpy(words.view(np.int64))).item())
@@ -132,7 +133,8 @@ def test_planted_powerlaw_all_paths():
     G = fr.Graph(g.row_ptr, g.col, g.sign, cloud_capacity=256)
     for sched in [tune.default_schedule(G.n, G.nnz), dict(path=2, block=1024),
                   dict(path=3, block=1024, batch=8), dict(path=3, block=256, batch=3, heavy=64),
-                  dict(path=4, block=1024), dict(path=4, block=512)]:
+                  dict(path=4, block=1024), dict(path=4, block=512),
+                  dict(path=5, block=1024), dict(path=5, block=512)]:
         _check(G, gold, sched)
     # the planted split frustrates exactly the flipped edges
     side = g.meta["side"]

@@ -18,6 +18,7 @@ SCHEDULES = [
     dict(path=3, block=256, batch=1), dict(path=3, block=512, heavy=32, batch=3),
     dict(path=3, block=1024, heavy=64, batch=8), dict(path=3, block=256, batch=5, grid=40),
     dict(path=4, block=1024), dict(path=4, block=512), dict(path=4, block=256, grid=40),
+    dict(path=5, block=1024), dict(path=5, block=512), dict(path=5, block=256, grid=40),
 ]
 
 
@@ -203,7 +204,8 @@ def test_powerlaw_multi_tile_all_paths():
     for s in [dict(path=2, block=256), dict(path=2, block=1024),
               dict(path=3, block=256, heavy=64, batch=1), dict(path=3, block=512, heavy=512, batch=8),
               dict(path=3, block=1024, heavy=4096, batch=3), dict(path=3, block=512, batch=7, grid=17),
-              dict(path=4, block=1024), dict(path=4, block=256, grid=17)]:
+              dict(path=4, block=1024), dict(path=4, block=256, grid=17),
+              dict(path=5, block=1024), dict(path=5, block=256, grid=17)]:
         G.set_schedule(**s)
         G.cloud_reset()
         sw = G.sweep_range(0, K, seed, tree_switches=True).cpu().numpy().astype(np.uint64)

@@ -83,7 +83,8 @@ def test_sweep_stats_match_oracle(name, g):
     K, seed = 90, 23
     want_v, want_e = switches.sweep_stats(g, seed, 0, K)
     G = fr.Graph(g.row_ptr, g.col, g.sign, cloud_capacity=K)
-    for sched in (dict(path=0), dict(path=4, block=512), dict(path=1, block=256)):
+    for sched in (dict(path=0), dict(path=4, block=512), dict(path=1, block=256),
+                  dict(path=5, block=1024)):
         if sched["path"] == 1 and g.n > 12000:
             continue
         G.set_schedule(**sched)
