@@ -266,10 +266,13 @@ __device__ __forceinline__ TW<W> ldw(const uint64_t* a, int64_t v) {
   if constexpr (W == 1) {
     r.w[0] = a[v];
   } else {
-    static_assert(W == 2, "one or two words per vertex");
-    const ulonglong2 x = *reinterpret_cast<const ulonglong2*>(a + 2 * v);
-    r.w[0] = x.x;
-    r.w[1] = x.y;
+    static_assert(W % 2 == 0, "one word or an even number of words per vertex");
+#pragma unroll
+    for (int k = 0; k < W; k += 2) {
+      const ulonglong2 x = *reinterpret_cast<const ulonglong2*>(a + W * v + k);
+      r.w[k] = x.x;
+      r.w[k + 1] = x.y;
+    }
   }
   return r;
 }
@@ -279,7 +282,9 @@ __device__ __forceinline__ void stw_(uint64_t* a, int64_t v, const TW<W>& x) {
   if constexpr (W == 1) {
     a[v] = x.w[0];
   } else {
-    *reinterpret_cast<ulonglong2*>(a + 2 * v) = make_ulonglong2(x.w[0], x.w[1]);
+#pragma unroll
+    for (int k = 0; k < W; k += 2)
+      *reinterpret_cast<ulonglong2*>(a + W * v + k) = make_ulonglong2(x.w[k], x.w[k + 1]);
   }
 }
 
@@ -363,6 +368,7 @@ __device__ __forceinline__ void pull_edges_w(const uint32_t* adj, const uint64_t
 #pragma unroll
       for (int w = 0; w < W; ++w) {
         const uint64_t Fj = readlane64(F.w[w], j);
+        if (W > 1 && Fj == 0) continue;  // the edge hits only trees of other words
         const uint64_t Sj = readlane64(S.w[w], j);
         if ((Fj >> lane) & 1) {
           const uint64_t c2 = ((uint64_t)vkey_of(km[w], Hj) << 1) | ((Sj >> lane) & 1);
@@ -512,6 +518,7 @@ __device__ __forceinline__ uint64_t pull_small_w(const DevGraph& G, const MState
 #pragma unroll
       for (int w = 0; w < W; ++w) {
         const uint64_t Fj = readlane64(F.w[w], jj);
+        if (W > 1 && Fj == 0) continue;  // the edge hits only trees of other words
         const uint64_t Sj = readlane64(S.w[w], jj);
         if ((Fj >> lane) & 1) {
           const uint64_t c2 = ((uint64_t)vkey_of(km[w], Hj) << 1) | ((Sj >> lane) & 1);
