@@ -45,6 +45,17 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t x, int j) {
 
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// Lane t's bit of a wave-uniform mask, taken as the execution mask.
+__device__ __forceinline__ bool lane_bit(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+
+// A neighbour's candidate in the trees it reaches: its key in the high half and
+// the state it hands down in bit 0, so that the unsigned order is the key's
+// (the neighbours of one vertex have distinct keys).  Bit 0 is the state of
+// the minimum; no candidate equals kUnvisited.
+__device__ __forceinline__ uint64_t pull_cand(uint32_t key, bool st) {
+  return ((uint64_t)key << 32) | (uint64_t)st;
+}
+
 
 __device__ __forceinline__ uint64_t wave_or64(uint64_t x) {
 #pragma unroll
@@ -58,7 +69,7 @@ __device__ __forceinline__ uint64_t wave_or64(uint64_t x) {
 }
 
 
-// Lane t: minimum over the edges [e0, e1) of the candidate (key << 1 |
+// Lane t: minimum over the edges [e0, e1) of the candidate (key << 32 |
 // state bit) of every neighbour discovered at the previous level of tree t
 // (parity pp) in a tree of `want`.  The tree-independent part of each
 // neighbour's key and the edge sign are folded in once per edge lane; the
@@ -86,8 +97,8 @@ __device__ __forceinline__ uint64_t pull_edges(const uint32_t* adj, const uint64
       const uint32_t Hj = __builtin_amdgcn_readlane(H, j);
       const uint64_t Fj = readlane64(F, j);
       const uint64_t Sj = readlane64(S, j);
-      if ((Fj >> lane) & 1) {
-        const uint64_t c2 = ((uint64_t)vkey_of(km, Hj) << 1) | ((Sj >> lane) & 1);
+      if (lane_bit(Fj)) {
+        const uint64_t c2 = pull_cand(vkey_of(km, Hj), lane_bit(Sj));
         best = c2 < best ? c2 : best;
       }
     }
@@ -212,8 +223,8 @@ __device__ __forceinline__ uint64_t pull_small(const DevGraph& G, const MState& 
       const uint32_t Hj = __builtin_amdgcn_readlane(H, jj);
       const uint64_t Fj = readlane64(F, jj);
       const uint64_t Sj = readlane64(S, jj);
-      if ((Fj >> lane) & 1) {
-        const uint64_t c2 = ((uint64_t)vkey_of(km, Hj) << 1) | ((Sj >> lane) & 1);
+      if (lane_bit(Fj)) {
+        const uint64_t c2 = pull_cand(vkey_of(km, Hj), lane_bit(Sj));
         best = c2 < best ? c2 : best;
       }
     }
@@ -370,8 +381,8 @@ __device__ __forceinline__ void pull_edges_w(const uint32_t* adj, const uint64_t
         const uint64_t Fj = readlane64(F.w[w], j);
         if (W > 1 && Fj == 0) continue;  // the edge hits only trees of other words
         const uint64_t Sj = readlane64(S.w[w], j);
-        if ((Fj >> lane) & 1) {
-          const uint64_t c2 = ((uint64_t)vkey_of(km[w], Hj) << 1) | ((Sj >> lane) & 1);
+        if (lane_bit(Fj)) {
+          const uint64_t c2 = pull_cand(vkey_of(km[w], Hj), lane_bit(Sj));
           best[w] = c2 < best[w] ? c2 : best[w];
         }
       }
@@ -520,8 +531,8 @@ __device__ __forceinline__ uint64_t pull_small_w(const DevGraph& G, const MState
         const uint64_t Fj = readlane64(F.w[w], jj);
         if (W > 1 && Fj == 0) continue;  // the edge hits only trees of other words
         const uint64_t Sj = readlane64(S.w[w], jj);
-        if ((Fj >> lane) & 1) {
-          const uint64_t c2 = ((uint64_t)vkey_of(km[w], Hj) << 1) | ((Sj >> lane) & 1);
+        if (lane_bit(Fj)) {
+          const uint64_t c2 = pull_cand(vkey_of(km[w], Hj), lane_bit(Sj));
           best[w] = c2 < best[w] ? c2 : best[w];
         }
       }
