@@ -261,11 +261,15 @@ __device__ __forceinline__ int select_lane(uint64_t mask, int k) {
 }
 
 // ------------------------------------------------------------ W words per vertex
-// The same helpers for passes of 64 W trees: every per-vertex array holds W
-// consecutive words per vertex (vertex v at v W .. v W + W - 1), word w, bit
-// t is tree 64 w + t, and lane t of a wavefront carries trees t, 64 + t, ...
-// A gather of a vertex's W words touches one cache line, so a pass of 64 W
-// trees moves about as many lines as a pass of 64.
+// The same helpers for passes of 64 W trees.  Word w, bit t of a field is
+// tree 64 w + t, and lane t of a wavefront carries trees t, 64 + t, ...  The
+// four fields of a vertex (discoveries at even levels, states, discoveries at
+// odd levels, visits) form one record of 4 W words, field f of vertex v at
+// words 4 W v + f W .. + W - 1; MState's pointers point at field f of vertex 0.
+// A gather of a neighbour's discoveries and states then touches one record,
+// and a pass of 64 W trees moves about as many lines as a pass of 64.
+constexpr int kRecFields = 4;
+
 template <int W>
 struct TW {
   uint64_t w[W];
@@ -275,12 +279,12 @@ template <int W>
 __device__ __forceinline__ TW<W> ldw(const uint64_t* a, int64_t v) {
   TW<W> r;
   if constexpr (W == 1) {
-    r.w[0] = a[v];
+    r.w[0] = a[kRecFields * v];
   } else {
     static_assert(W % 2 == 0, "one word or an even number of words per vertex");
 #pragma unroll
     for (int k = 0; k < W; k += 2) {
-      const ulonglong2 x = *reinterpret_cast<const ulonglong2*>(a + W * v + k);
+      const ulonglong2 x = *reinterpret_cast<const ulonglong2*>(a + kRecFields * W * v + k);
       r.w[k] = x.x;
       r.w[k + 1] = x.y;
     }
@@ -291,11 +295,11 @@ __device__ __forceinline__ TW<W> ldw(const uint64_t* a, int64_t v) {
 template <int W>
 __device__ __forceinline__ void stw_(uint64_t* a, int64_t v, const TW<W>& x) {
   if constexpr (W == 1) {
-    a[v] = x.w[0];
+    a[kRecFields * v] = x.w[0];
   } else {
 #pragma unroll
     for (int k = 0; k < W; k += 2)
-      *reinterpret_cast<ulonglong2*>(a + W * v + k) = make_ulonglong2(x.w[k], x.w[k + 1]);
+      *reinterpret_cast<ulonglong2*>(a + kRecFields * W * v + k) = make_ulonglong2(x.w[k], x.w[k + 1]);
   }
 }
 
@@ -360,15 +364,13 @@ __device__ __forceinline__ void pull_edges_w(const uint32_t* adj, const uint64_t
       const uint32_t a = adj[e];
       const uint32_t u = a & kVertexMask;
       const TW<W> nb = ldw<W>(nbw, u);
+      const TW<W> st = ldw<W>(stw, u);  // the same record as nb
 #pragma unroll
       for (int w = 0; w < W; ++w) F.w[w] = nb.w[w] & want.w[w];
       hit = any_w(F);
-      if (hit) {
-        const TW<W> st = ldw<W>(stw, u);
-        const uint64_t neg = (a >> 31) ? ~0ull : 0ull;
+      const uint64_t neg = (a >> 31) ? ~0ull : 0ull;
 #pragma unroll
-        for (int w = 0; w < W; ++w) S.w[w] = st.w[w] ^ neg;
-      }
+      for (int w = 0; w < W; ++w) S.w[w] = st.w[w] ^ neg;
       H = fmix32(u);
     }
     uint64_t hits = __ballot(hit);
@@ -488,15 +490,13 @@ __device__ __forceinline__ uint64_t pull_small_w(const DevGraph& G, const MState
       const uint32_t a = G.adj[(int64_t)sk + (eb + lane - ek)];
       const uint32_t u = a & kVertexMask;
       const TW<W> nb = ldw<W>(A.nbw[pp], u);
+      const TW<W> su = ldw<W>(A.stw, u);  // the same record as nb
 #pragma unroll
       for (int w = 0; w < W; ++w) F.w[w] = nb.w[w] & wk.w[w];
       hit = any_w(F);
-      if (hit) {
-        const TW<W> su = ldw<W>(A.stw, u);
-        const uint64_t neg = (a >> 31) ? ~0ull : 0ull;
+      const uint64_t neg = (a >> 31) ? ~0ull : 0ull;
 #pragma unroll
-        for (int w = 0; w < W; ++w) S.w[w] = su.w[w] ^ neg;
-      }
+      for (int w = 0; w < W; ++w) S.w[w] = su.w[w] ^ neg;
       H = fmix32(u);
     }
     uint64_t hits = __ballot(hit);

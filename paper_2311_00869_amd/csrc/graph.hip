@@ -442,7 +442,7 @@ Layout make_layout(int32_t n, int64_t nnz, int64_t cloud_capacity, uint64_t tabl
   L.slots = take(L.slot_stride * L.nslots);
   // multi-tree path (the lists, bitmaps, control and barrier words are the
   // whole-grid path's, which never runs at the same time)
-  L.mrec = take(64 * nn);  // four arrays of up to two 8-byte tree words per vertex
+  L.mrec = take(64 * nn);  // a record per vertex: four fields of up to two 8-byte tree words
   L.mhcap = (size_t)nnz / kMSplit + 1;
   L.mhslot = take(8 * 128 * L.mhcap);
   // reached bitmaps over the two levels' list entries: light, then split rows

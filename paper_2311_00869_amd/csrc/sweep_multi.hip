@@ -258,12 +258,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
     }
 
     // ---- reset: records, bitmaps, control words
-    for (int64_t v = stid; v < (int64_t)n * W; v += sstride) {
-      A.S.nbw[0][v] = 0;
-      A.S.nbw[1][v] = 0;
-      A.S.stw[v] = 0;
-      A.S.vis[v] = 0;
-    }
+    for (int64_t v = stid; v < (int64_t)n * W * kRecFields; v += sstride) A.S.nbw[0][v] = 0;
     for (int64_t i = stid; i < nw; i += sstride) {
       A.S.unf[i] = G.word_mask[i];
       A.S.cand[i] = 0;
@@ -800,7 +795,6 @@ hipError_t launch_mt_block(fi_graph* g, const MArgs& a, hipStream_t s) {
 hipError_t launch_multi(fi_graph* g, const SweepArgs& sa, int words, hipStream_t s) {
   const Layout& L = g->L;
   char* ws = g->ws;
-  const int64_t nwv = (int64_t)g->dg.n * words;
   MArgs a{};
   a.seed = sa.seed;
   a.t0 = sa.t0;
@@ -811,10 +805,11 @@ hipError_t launch_multi(fi_graph* g, const SweepArgs& sa, int words, hipStream_t
   a.insert = sa.insert;
   a.ntasks = g->mtasks;
   a.nbig = g->mnbig;
+  // one record of kRecFields fields of `words` words per vertex
   a.S.nbw[0] = (uint64_t*)(ws + L.mrec);
-  a.S.nbw[1] = a.S.nbw[0] + nwv;
-  a.S.stw = a.S.nbw[1] + nwv;
-  a.S.vis = a.S.stw + nwv;
+  a.S.stw = a.S.nbw[0] + words;
+  a.S.nbw[1] = a.S.nbw[0] + 2 * words;
+  a.S.vis = a.S.nbw[0] + 3 * words;
   a.S.unf = (uint64_t*)(ws + L.gvis);
   a.S.cand = (uint64_t*)(ws + L.gsb);
   a.lstride = (int64_t)g->dg.n + 64;
