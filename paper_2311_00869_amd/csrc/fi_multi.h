@@ -303,6 +303,19 @@ __device__ __forceinline__ void stw_(uint64_t* a, int64_t v, const TW<W>& x) {
   }
 }
 
+// A value every lane holds alike, moved to scalar registers.
+template <int W>
+__device__ __forceinline__ TW<W> uni_w(const TW<W>& x) {
+  TW<W> r;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x.w[w]);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x.w[w] >> 32));
+    r.w[w] = ((uint64_t)hi << 32) | lo;
+  }
+  return r;
+}
+
 template <int W>
 __device__ __forceinline__ bool any_w(const TW<W>& x) {
   uint64_t o = 0;
@@ -349,30 +362,39 @@ __device__ __forceinline__ TW<W> shfl_w(const TW<W>& x, int src) {
 
 // Lane t, word w: minimum over the edges [e0, e1) of the candidate of every
 // neighbour discovered at the previous level of tree 64 w + t in a tree of
-// `want`, folded into best[w].
+// `want`, folded into best[w].  The edges go in chunks of 64 through a
+// two-stage pipeline, as in pull_small_w: a chunk's records and the next
+// chunk's adjacency are in flight while the chunk before is walked; lanes
+// past e1 read entry e0 and vertex 0.
 template <int W>
 __device__ __forceinline__ void pull_edges_w(const uint32_t* adj, const uint64_t* nbw,
                                              const uint64_t* stw, int64_t e0, int64_t e1,
                                              const TW<W>& want, const KeyMix* km, uint64_t* best) {
+  if (e0 >= e1) return;
   const int lane = lane_id();
+  uint32_t an = adj[e0 + lane < e1 ? e0 + lane : e0];
+  uint32_t un = e0 + lane < e1 ? (an & kVertexMask) : 0u;
+  uint64_t gn = (an >> 31) ? ~0ull : 0ull;
+  TW<W> nb = ldw<W>(nbw, un);
+  TW<W> st = ldw<W>(stw, un);  // the same record
+  an = adj[e0 + 64 + lane < e1 ? e0 + 64 + lane : e0];
   for (int64_t c = e0; c < e1; c += 64) {
-    const int64_t e = c + lane;
-    uint32_t H = 0;
+    const uint32_t H = fmix32(un);
     TW<W> F{}, S{};
     bool hit = false;
-    if (e < e1) {
-      const uint32_t a = adj[e];
-      const uint32_t u = a & kVertexMask;
-      const TW<W> nb = ldw<W>(nbw, u);
-      const TW<W> st = ldw<W>(stw, u);  // the same record as nb
+    if (c + lane < e1) {
 #pragma unroll
       for (int w = 0; w < W; ++w) F.w[w] = nb.w[w] & want.w[w];
       hit = any_w(F);
-      const uint64_t neg = (a >> 31) ? ~0ull : 0ull;
 #pragma unroll
-      for (int w = 0; w < W; ++w) S.w[w] = st.w[w] ^ neg;
-      H = fmix32(u);
+      for (int w = 0; w < W; ++w) S.w[w] = st.w[w] ^ gn;
     }
+    // the next chunk's records, then the adjacency of the chunk after it
+    un = c + 64 + lane < e1 ? (an & kVertexMask) : 0u;
+    gn = (an >> 31) ? ~0ull : 0ull;
+    nb = ldw<W>(nbw, un);
+    st = ldw<W>(stw, un);
+    an = adj[c + 128 + lane < e1 ? c + 128 + lane : e0];
     uint64_t hits = __ballot(hit);
     while (hits) {
       const int j = __builtin_ctzll(hits);
@@ -445,22 +467,29 @@ __device__ __forceinline__ bool settle_w(const MState& A, int32_t v, const TW<W>
 }
 
 // One wave pulls ne <= 64 vertices of rows up to 64 edges (as pull_small).
+// The rows are walked in chunks of as many whole rows as fit in 64 lanes, in
+// a two-stage pipeline: while the edges of one chunk are walked, the next
+// chunk's records are in flight (its adjacency was read while this chunk's
+// records arrived).  lw is the wave's LDS scratch of 3 x 64 entries: each
+// row's wanted trees, then its newly reached trees and their states.
 template <int W>
 __device__ __forceinline__ uint64_t pull_small_w(const DevGraph& G, const MState& A, int32_t v,
                                                  int ne, int pp, int p, const TW<W>& valid,
-                                                 const KeyMix* km, bool push, uint64_t& cnt,
-                                                 uint64_t& deg, uint64_t& fin) {
+                                                 const KeyMix* km, bool push, TW<W>* lw,
+                                                 uint64_t& cnt, uint64_t& deg, uint64_t& fin) {
   const int lane = lane_id();
   const bool ok = lane < ne;
   int s = 0, d = 0;
-  TW<W> vis{}, st{};
+  TW<W> want{};
   if (ok) {
     s = G.row_ptr[v];
     d = G.row_ptr[v + 1] - s;
-    vis = ldw<W>(A.vis, v);
-    st = ldw<W>(A.stw, v);
+    want = and_not(valid, ldw<W>(A.vis, v));
   }
-  const TW<W> want = and_not(valid, vis);
+  lw[lane] = want;
+  lw[64 + lane] = TW<W>{};
+  lw[128 + lane] = TW<W>{};
+  __builtin_amdgcn_wave_barrier();
   int inc = d;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
@@ -468,51 +497,81 @@ __device__ __forceinline__ uint64_t pull_small_w(const DevGraph& G, const MState
     if (lane >= o) inc += y;
   }
   const int excl = inc - d;
-  TW<W> mnew{}, mstb{};  // outcome of this lane's row
-  int k0 = 0;
-  while (k0 < ne) {
+  // the chunk that starts at row k0: lane i < total takes its edge i, of row kj
+  struct Chunk {
+    int k1, total, kj;
+    int64_t pos;
+  };
+  auto chunk_at = [&](int k0) {
+    Chunk c;
     const int eb = uni(__shfl(excl, k0));
     const bool inr = ok && lane >= k0 && inc - eb <= 64;
     const uint64_t fit = __ballot(inr);
-    const int k1 = k0 + (int)__popcll(fit);
-    const int total = uni(__shfl(inc, k1 - 1)) - eb;
+    c.k1 = k0 + (int)__popcll(fit);
+    c.total = uni(__shfl(inc, c.k1 - 1)) - eb;
     const int e = inc - eb;
-    const uint64_t starts = 1ull | wave_or64(inr && e < total ? (1ull << e) : 0ull);
+    const uint64_t starts = 1ull | wave_or64(inr && e < c.total ? (1ull << e) : 0ull);
     const int r = (int)__popcll(starts & ((2ull << lane) - 1));
-    const int kj = k0 + r - 1;
-    const int sk = __shfl(s, kj);
-    const int ek = __shfl(excl, kj);
-    const TW<W> wk = shfl_w<W>(want, kj);
-    uint32_t H = 0;
+    c.kj = k0 + r - 1;
+    c.pos = (int64_t)__shfl(s, c.kj) + (eb + lane - __shfl(excl, c.kj));
+    return c;
+  };
+  // c0: the chunk being walked; c1: its records are in flight; the adjacency
+  // of the chunk after c1 is in flight.  Every lane issues every load (lanes
+  // without an edge read entry 0 and vertex 0), so the wait counts are the
+  // same on every path through the loop.
+  Chunk c0 = chunk_at(0);
+  uint32_t an = G.adj[lane < c0.total ? c0.pos : 0];
+  uint32_t un = lane < c0.total ? (an & kVertexMask) : 0u;
+  uint64_t gn = (an >> 31) ? ~0ull : 0ull;
+  TW<W> nb = ldw<W>(A.nbw[pp], un);
+  TW<W> su = ldw<W>(A.stw, un);  // the same record
+  bool m1 = c0.k1 < ne;
+  Chunk c1 = m1 ? chunk_at(c0.k1) : c0;
+  an = G.adj[m1 && lane < c1.total ? c1.pos : 0];
+  int k0 = 0;
+  while (k0 < ne) {
+    // c0's edges
+    const uint32_t H = fmix32(un);
     TW<W> F{}, S{};
     bool hit = false;
-    if (lane < total) {
-      const uint32_t a = G.adj[(int64_t)sk + (eb + lane - ek)];
-      const uint32_t u = a & kVertexMask;
-      const TW<W> nb = ldw<W>(A.nbw[pp], u);
-      const TW<W> su = ldw<W>(A.stw, u);  // the same record as nb
+    if (lane < c0.total) {
+      const TW<W> wk = lw[c0.kj];
 #pragma unroll
       for (int w = 0; w < W; ++w) F.w[w] = nb.w[w] & wk.w[w];
       hit = any_w(F);
-      const uint64_t neg = (a >> 31) ? ~0ull : 0ull;
 #pragma unroll
-      for (int w = 0; w < W; ++w) S.w[w] = su.w[w] ^ neg;
-      H = fmix32(u);
+      for (int w = 0; w < W; ++w) S.w[w] = su.w[w] ^ gn;
     }
+    const int kj = c0.kj;
+    const int k1 = c0.k1;
+    // c1's records
+    un = m1 && lane < c1.total ? (an & kVertexMask) : 0u;
+    gn = (an >> 31) ? ~0ull : 0ull;
+    nb = ldw<W>(A.nbw[pp], un);
+    su = ldw<W>(A.stw, un);
+    // the adjacency of the chunk after c1
+    const bool m2 = m1 && c1.k1 < ne;
+    const Chunk c2 = m2 ? chunk_at(c1.k1) : c1;
+    an = G.adj[m2 && lane < c2.total ? c2.pos : 0];
+    c0 = c1;
+    c1 = c2;
+    m1 = m2;
     uint64_t hits = __ballot(hit);
     uint64_t best[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) best[w] = kUnvisited;
     int cur = -1;
     auto keep = [&]() {
+      TW<W> nbits, sbits;
 #pragma unroll
       for (int w = 0; w < W; ++w) {
-        const uint64_t nb = __ballot(best[w] != kUnvisited);
-        const uint64_t sb = __ballot(best[w] != kUnvisited && (best[w] & 1));
-        if (lane == cur) {
-          mnew.w[w] = nb;
-          mstb.w[w] = sb;
-        }
+        nbits.w[w] = __ballot(best[w] != kUnvisited);
+        sbits.w[w] = __ballot(best[w] != kUnvisited && (best[w] & 1));
+      }
+      if (lane == 0) {
+        lw[64 + cur] = nbits;
+        lw[128 + cur] = sbits;
       }
     };
     while (hits) {
@@ -540,7 +599,17 @@ __device__ __forceinline__ uint64_t pull_small_w(const DevGraph& G, const MState
     if (cur >= 0) keep();
     k0 = k1;
   }
+  __builtin_amdgcn_wave_barrier();
+  TW<W> mnew{}, mstb{}, vis{}, st{};
+  if (ok) {
+    mnew = lw[64 + lane];
+    mstb = lw[128 + lane];
+  }
   const bool got = ok && any_w(mnew);
+  if (got) {
+    vis = ldw<W>(A.vis, v);
+    st = ldw<W>(A.stw, v);
+  }
   const TW<W> nv = or_w(vis, mnew);
   const bool full = got && eq_w(nv, valid);
   if (got) {

@@ -116,6 +116,7 @@ struct MS {
   uint32_t nl, nm, nh, hunits;
   uint64_t hbest[64 * W];
   uint64_t tacc[3][64 * W];
+  TW<W> pw[NT / 64][3 * 64];  // per wave: wanted trees, outcomes of small rows
 };
 
 // Move the LDS staging list into a global list (one reservation per block).
@@ -506,7 +507,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
           const int ne = (int)min<int64_t>(64, nl - b * 64);
           const uint64_t r =
               pull_small_w<W>(G, A.S, b * 64 + lane < nl ? pln[b * 64 + lane] : 0, ne, pp, p, valid,
-                              km, push, cnt, deg, fin);
+                              km, push, sh.pw[wave], cnt, deg, fin);
           if (lane == 0) rln[b] = r;
         }
         // medium rows: block b owns rows b, b + nb, ...; its waves draw them
@@ -520,8 +521,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
             if (i >= (int64_t)nm) break;
             const int32_t v = pmn[i];
             const int64_t e0 = rp[v], e1 = rp[v + 1];
-            const TW<W> visq = ldw<W>(A.S.vis, v), stq = ldw<W>(A.S.stw, v);
-            const TW<W> want = and_not(valid, visq);
+            const TW<W> want = uni_w(and_not(valid, ldw<W>(A.S.vis, v)));  // v is the wave's
             uint64_t best[W];
 #pragma unroll
             for (int w = 0; w < W; ++w) best[w] = kUnvisited;
@@ -534,6 +534,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
             }
             const int dq = (int)(e1 - e0);
             if (any_w(mnew)) {
+              const TW<W> visq = ldw<W>(A.S.vis, v), stq = ldw<W>(A.S.stw, v);
               const TW<W> nv = or_w(visq, mnew);
               const bool full = eq_w(nv, valid);
               if (lane == 0) {
@@ -581,7 +582,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
           const uint32_t part = hk - (uint32_t)uni(sh.heavy.y);
           const int64_t e0 = rp[v] + (int64_t)part * kMSplit;
           const int64_t e1 = min<int64_t>(rp[v + 1], e0 + kMSplit);
-          const TW<W> want = and_not(valid, ldw<W>(A.S.vis, v));
+          const TW<W> want = uni_w(and_not(valid, ldw<W>(A.S.vis, v)));  // v is the block's
           const int64_t seg = ((e1 - e0 + NW - 1) / NW + 63) / 64 * 64;
           const int64_t s0 = min<int64_t>(e1, e0 + (int64_t)wave * seg);
           const int64_t s1 = min<int64_t>(e1, s0 + seg);
