@@ -492,14 +492,16 @@ __global__ void __launch_bounds__(NT) k_batch_multi(BatchMArgs B) {
   __shared__ int64_t s_item;
   __shared__ int s_any[2];  // some vertex reached, by level parity
   __shared__ uint64_t s_acc[3][64];
+  __shared__ mt::TW<1> s_pw[NW][3 * 64];  // per wave: wanted trees, outcomes of short rows
   char* slot = B.slots + (size_t)blockIdx.x * B.slot_stride;
   const size_t nm = (size_t)B.n_max;
+  // vertex records of one word per field, then the unfinished-vertex bitmap
   mt::MState S;
   S.nbw[0] = (uint64_t*)slot;
-  S.nbw[1] = S.nbw[0] + nm;
-  S.stw = S.nbw[1] + nm;
-  S.vis = S.stw + nm;
-  S.unf = S.vis + nm;
+  S.stw = S.nbw[0] + 1;
+  S.nbw[1] = S.nbw[0] + 2;
+  S.vis = S.nbw[0] + 3;
+  S.unf = S.nbw[0] + mt::kRecFields * nm;
   S.cand = nullptr;
   uint64_t* table = S.unf + (nm / 64 + 2);
   const int64_t nitems = (int64_t)B.G * B.groups;
@@ -535,12 +537,7 @@ __global__ void __launch_bounds__(NT) k_batch_multi(BatchMArgs B) {
     const KeyMix km = key_mix(tree_salt(B.seed, (uint64_t)(tb + lane)));
 
     // ---- reset
-    for (int32_t v = tid; v < n; v += NT) {
-      S.nbw[0][v] = 0;
-      S.nbw[1][v] = 0;
-      S.stw[v] = 0;
-      S.vis[v] = 0;
-    }
+    for (int32_t v = tid; v < mt::kRecFields * n; v += NT) S.nbw[0][v] = 0;
     for (int32_t w = wave; w < nw; w += NW) {
       const int32_t v = w * 64 + lane;
       const uint64_t m = __ballot(v < n && rp[v + 1] > rp[v]);
@@ -592,8 +589,8 @@ __global__ void __launch_bounds__(NT) k_batch_multi(BatchMArgs B) {
           const uint64_t msk = __ballot(ok && r == r1);
           rem &= ~msk;
           if (lane == 0) {
-            S.nbw[0][r1] = msk;
-            S.vis[r1] = msk;
+            mt::stw_<1>(S.nbw[0], r1, mt::TW<1>{{msk}});
+            mt::stw_<1>(S.vis, r1, mt::TW<1>{{msk}});
             if (msk == valid) mt::aand64(S.unf + (r1 >> 6), ~(1ull << (r1 & 63)));
           }
         }
@@ -626,18 +623,19 @@ __global__ void __launch_bounds__(NT) k_batch_multi(BatchMArgs B) {
         if (ne) {
           const int src = mt::select_lane(small, lane < ne ? lane : 0);
           const int32_t vk = __shfl(v, src);
-          mt::pull_small(G, S, vk, ne, pp, p, valid, km, false, cnt, deg, fin);
+          mt::pull_small_w<1>(G, S, vk, ne, pp, p, mt::TW<1>{{valid}}, &km, false, s_pw[wave], cnt,
+                              deg, fin);
         }
         uint64_t big = bits & ~small;
         while (big) {
           const int j = __builtin_ctzll(big);
           big &= big - 1;
           const int32_t vj = w * 64 + j;
-          const uint64_t vis = S.vis[vj], st = S.stw[vj];
-          const uint64_t want = valid & ~vis;
+          const mt::TW<1> want = mt::uni_w(mt::and_not(mt::TW<1>{{valid}}, mt::ldw<1>(S.vis, vj)));
           uint64_t best = kUnvisited;
-          if (want) best = mt::pull_edges(G.adj, S.nbw[pp], S.stw, rp[vj], rp[vj + 1], pp, want, km, best);
-          mt::settle(S, vj, vis, st, rp[vj + 1] - rp[vj], best, p, valid, cnt, deg, fin);
+          if (want.w[0]) mt::pull_edges_w<1>(G.adj, S.nbw[pp], S.stw, rp[vj], rp[vj + 1], want, &km, &best);
+          mt::settle_w<1>(S, vj, mt::ldw<1>(S.vis, vj), mt::ldw<1>(S.stw, vj), rp[vj + 1] - rp[vj], &best,
+                          p, mt::TW<1>{{valid}}, cnt, deg, fin);
         }
       }
       if (lane == 0 && cnt) s_any[p] = 1;
@@ -669,7 +667,7 @@ __global__ void __launch_bounds__(NT) k_batch_multi(BatchMArgs B) {
         uint64_t x = 0;
         if (e < G.m) {
           const uint2 uv = G.edges[e];
-          x = S.stw[uv.x] ^ S.stw[uv.y & kVertexMask];
+          x = mt::ldw<1>(S.stw, uv.x).w[0] ^ mt::ldw<1>(S.stw, uv.y & kVertexMask).w[0];
           if (uv.y >> 31) x = ~x;
         }
 #pragma unroll
@@ -688,7 +686,7 @@ __global__ void __launch_bounds__(NT) k_batch_multi(BatchMArgs B) {
       for (int32_t i = wave; i < nw; i += NW) {
         const int32_t v = i * 64 + lane;
         uint64_t cs = 0;
-        if (v < n) cs = S.stw[v] ^ S.stw[G.comp[v]];
+        if (v < n) cs = mt::ldw<1>(S.stw, v).w[0] ^ mt::ldw<1>(S.stw, G.comp[v]).w[0];
         uint64_t W = 0;
         for (int t = 0; t < 64; ++t) {
           const uint64_t bb = __ballot((cs >> t) & 1);

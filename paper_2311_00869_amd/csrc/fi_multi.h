@@ -1,7 +1,8 @@
-// Device helpers of the multi-tree sweep (64 trees per pass, one bit per
-// tree in every per-vertex word; lane t of a wavefront is tree t), shared by
-// the whole-grid sweep of one large graph (sweep_multi.hip) and the
-// workgroup-per-graph sweep of batches (batch.hip).
+// Device helpers of the multi-tree sweep: 64 W trees per pass, one bit per
+// tree in the W-word fields of each vertex's record, lane t of a wavefront
+// carrying trees t, 64 + t, ...  Shared by the whole-grid sweep of one large
+// graph (sweep_multi.hip, W = 1 or 2) and the workgroup-per-graph sweep of
+// batches (batch.hip, W = 1).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -13,10 +14,11 @@
 namespace fi {
 namespace mt {
 
-// Per-vertex state of one pass, each an array of n 8-byte words: the trees
-// that discovered the vertex at the last even / odd level, its state bits,
-// the trees that have visited it; the vertices with an edge not yet visited
-// by every tree, and the push candidates of the level (n/64 words each).
+// Per-vertex state of one pass: the trees that discovered the vertex at the
+// last even / odd level, its state bits and the trees that have visited it
+// (the fields of the vertex records, below); the vertices with an edge not yet
+// visited by every tree, and the push candidates of the level (n/64 words
+// each).
 struct MState {
   uint64_t* nbw[2];
   uint64_t* stw;
@@ -68,185 +70,6 @@ __device__ __forceinline__ uint64_t wave_or64(uint64_t x) {
          (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
 }
 
-
-// Lane t: minimum over the edges [e0, e1) of the candidate (key << 32 |
-// state bit) of every neighbour discovered at the previous level of tree t
-// (parity pp) in a tree of `want`.  The tree-independent part of each
-// neighbour's key and the edge sign are folded in once per edge lane; the
-// edges that hit some tree are then walked one by one with all lanes.
-__device__ __forceinline__ uint64_t pull_edges(const uint32_t* adj, const uint64_t* nbw,
-                                               const uint64_t* stw, int64_t e0,
-                                               int64_t e1, int pp, uint64_t want, KeyMix km,
-                                               uint64_t best) {
-  const int lane = lane_id();
-  for (int64_t c = e0; c < e1; c += 64) {
-    const int64_t e = c + lane;
-    uint32_t H = 0;
-    uint64_t F = 0, S = 0;
-    if (e < e1) {
-      const uint32_t a = adj[e];
-      const uint32_t u = a & kVertexMask;
-      F = nbw[u] & want;
-      if (F) S = stw[u] ^ ((a >> 31) ? ~0ull : 0ull);
-      H = fmix32(a & kVertexMask);
-    }
-    uint64_t hits = __ballot(F != 0);
-    while (hits) {
-      const int j = __builtin_ctzll(hits);
-      hits &= hits - 1;
-      const uint32_t Hj = __builtin_amdgcn_readlane(H, j);
-      const uint64_t Fj = readlane64(F, j);
-      const uint64_t Sj = readlane64(S, j);
-      if (lane_bit(Fj)) {
-        const uint64_t c2 = pull_cand(vkey_of(km, Hj), lane_bit(Sj));
-        best = c2 < best ? c2 : best;
-      }
-    }
-  }
-  return best;
-}
-
-// Lane t: the minimum root candidate of tree t over cverts[b, e).
-__device__ __forceinline__ uint64_t comp_min(const int32_t* cverts, int32_t b, int32_t e, KeyMix km) {
-  const int lane = lane_id();
-  uint64_t best = kUnvisited;
-  for (int32_t c = b; c < e; c += 64) {
-    const int32_t i = c + lane;
-    const int32_t mine = i < e ? cverts[i] : 0;
-    const int cnt = min(64, e - c);
-    const uint32_t hm = fmix32((uint32_t)mine);
-    for (int j = 0; j < cnt; ++j) {
-      const uint32_t v = (uint32_t)__builtin_amdgcn_readlane(mine, j);
-      const uint32_t h = (uint32_t)__builtin_amdgcn_readlane((int)hm, j);
-      const uint64_t k = root_candidate(vkey_of(km, h), v);
-      best = k < best ? k : best;
-    }
-  }
-  return best;
-}
-
-// Lane t: the write-back of vertex v once its trees of this level are
-// decided (best: lane t's minimum candidate, kUnvisited if none).  One lane
-// stores; every lane gets the reached / finished bookkeeping.
-__device__ __forceinline__ bool settle(const MState& A, int32_t v, uint64_t vis, uint64_t st, int dv,
-                                       uint64_t best, int p, uint64_t valid, uint64_t& cnt,
-                                       uint64_t& deg, uint64_t& fin) {
-  const uint64_t newb = __ballot(best != kUnvisited);
-  if (!newb) return false;
-  const uint64_t stb = __ballot(best != kUnvisited && (best & 1));
-  const bool full = (vis | newb) == valid;
-  if (lane_id() == 0) {
-    A.vis[v] = vis | newb;
-    A.nbw[p][v] = newb;
-    if (stb) A.stw[v] = st | stb;
-    if (full) aand64(A.unf + (v >> 6), ~(1ull << (v & 63)));
-  }
-  if (full) fin += (uint64_t)dv;
-  cnt += 1;
-  deg += (uint64_t)dv;
-  return true;
-}
-
-// One wave pulls ne <= 64 vertices (lane k < ne holds vertex v; every row
-// has at most 64 edges and at least one).  Rows are walked in rounds of at most 64 edges, as many whole rows as
-// fit, all loads of a round in flight together.  Each row's outcome (trees
-// that reached the vertex, their state bits) stays in its lane until the
-// batch is walked, then every vertex is written back at once, so no store
-// is waited for inside the walk.  Returns the entries some tree reached.
-__device__ __forceinline__ uint64_t pull_small(const DevGraph& G, const MState& A, int32_t v, int ne,
-                                               int pp, int p, uint64_t valid, KeyMix km, bool push,
-                                               uint64_t& cnt, uint64_t& deg, uint64_t& fin) {
-  const int lane = lane_id();
-  const bool ok = lane < ne;
-  int s = 0, d = 0;
-  uint64_t vis = 0, st = 0;
-  if (ok) {
-    s = G.row_ptr[v];
-    d = G.row_ptr[v + 1] - s;
-    vis = A.vis[v];
-    st = A.stw[v];
-  }
-  const uint64_t want = valid & ~vis;
-  int inc = d;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(inc, o);
-    if (lane >= o) inc += y;
-  }
-  const int excl = inc - d;
-  uint64_t mnew = 0, mstb = 0;  // outcome of this lane's row
-  auto keep = [&](int k, uint64_t newb, uint64_t stb) {
-    if (lane == k) {
-      mnew = newb;
-      mstb = stb;
-    }
-  };
-  int k0 = 0;
-  while (k0 < ne) {
-    const int eb = uni(__shfl(excl, k0));
-    const bool inr = ok && lane >= k0 && inc - eb <= 64;
-    const uint64_t fit = __ballot(inr);
-    const int k1 = k0 + (int)__popcll(fit);  // >= k0 + 1: every row fits a round
-    const int total = uni(__shfl(inc, k1 - 1)) - eb;
-    // the rows' starts: 0 and every row end but the last
-    const int e = inc - eb;
-    const uint64_t starts = 1ull | wave_or64(inr && e < total ? (1ull << e) : 0ull);
-    const int r = (int)__popcll(starts & ((2ull << lane) - 1));
-    const int kj = k0 + r - 1;
-    const int sk = __shfl(s, kj);
-    const int ek = __shfl(excl, kj);
-    const uint32_t wlo = (uint32_t)__shfl((int)(uint32_t)want, kj);
-    const uint32_t whi = (uint32_t)__shfl((int)(uint32_t)(want >> 32), kj);
-    const uint64_t wk = ((uint64_t)whi << 32) | wlo;
-    uint32_t H = 0;
-    uint64_t F = 0, S = 0;
-    if (lane < total) {
-      const uint32_t a = G.adj[(int64_t)sk + (eb + lane - ek)];
-      const uint32_t u = a & kVertexMask;
-      F = A.nbw[pp][u] & wk;
-      if (F) S = A.stw[u] ^ ((a >> 31) ? ~0ull : 0ull);
-      H = fmix32(a & kVertexMask);
-    }
-    uint64_t hits = __ballot(F != 0);
-    uint64_t best = kUnvisited;
-    int cur = -1;
-    while (hits) {
-      const int jj = __builtin_ctzll(hits);
-      hits &= hits - 1;
-      const int kk = __builtin_amdgcn_readlane(kj, jj);
-      if (kk != cur) {
-        if (cur >= 0)
-          keep(cur, __ballot(best != kUnvisited), __ballot(best != kUnvisited && (best & 1)));
-        best = kUnvisited;
-        cur = kk;
-      }
-      const uint32_t Hj = __builtin_amdgcn_readlane(H, jj);
-      const uint64_t Fj = readlane64(F, jj);
-      const uint64_t Sj = readlane64(S, jj);
-      if (lane_bit(Fj)) {
-        const uint64_t c2 = pull_cand(vkey_of(km, Hj), lane_bit(Sj));
-        best = c2 < best ? c2 : best;
-      }
-    }
-    if (cur >= 0) keep(cur, __ballot(best != kUnvisited), __ballot(best != kUnvisited && (best & 1)));
-    k0 = k1;
-  }
-  // write back every reached vertex of the batch
-  const bool got = ok && mnew != 0;
-  const bool full = got && (vis | mnew) == valid;
-  if (got) {
-    A.vis[v] = vis | mnew;
-    A.nbw[p][v] = mnew;
-    if (mstb) A.stw[v] = st | mstb;
-    if (full) aand64(A.unf + (v >> 6), ~(1ull << (v & 63)));
-  }
-  if (ok && push) aand64(A.cand + (v >> 6), ~(1ull << (v & 63)));
-  const uint64_t reached = __ballot(got);
-  cnt += (uint64_t)__popcll(reached);
-  deg += wave_sum_u64(got ? (uint64_t)d : 0ull);
-  fin += wave_sum_u64(full ? (uint64_t)d : 0ull);
-  return reached;
-}
 
 // Lane k < ne (ne = popcount of mask) gets the lane index of the k-th set
 // bit of mask.
@@ -345,18 +168,6 @@ __device__ __forceinline__ TW<W> or_w(const TW<W>& a, const TW<W>& b) {
   TW<W> r;
 #pragma unroll
   for (int w = 0; w < W; ++w) r.w[w] = a.w[w] | b.w[w];
-  return r;
-}
-
-template <int W>
-__device__ __forceinline__ TW<W> shfl_w(const TW<W>& x, int src) {
-  TW<W> r;
-#pragma unroll
-  for (int w = 0; w < W; ++w) {
-    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)x.w[w], src);
-    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(x.w[w] >> 32), src);
-    r.w[w] = ((uint64_t)hi << 32) | lo;
-  }
   return r;
 }
 
