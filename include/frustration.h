@@ -415,10 +415,11 @@ int fi_bcloud_stats(fi_bcloud* c, int64_t* out_trees, int64_t* out_dropped, void
  * 2 = one workgroup per tree with the tree state in workspace memory
  * (n <= 1,000,000), 3 = the whole grid on a few trees at a time
  * (persistent cooperative kernel, any n), 4 = the whole grid on 64 trees
- * at once with one bit per tree in every per-vertex word (cooperative, any
- * n; fi_tree_state falls back to path 3), 5 = the same with 128 trees at once
- * (two words per vertex; a vertex's words share one cache line, so a pass
- * moves about as many lines as a pass of 64; not for batch handles).  block: threads per workgroup
+ * at once with one bit per tree in each field of a per-vertex record
+ * (cooperative, any n; fi_tree_state falls back to path 3), 5 = the same
+ * with 128 trees at once (two-word fields; a vertex's record is one 64-byte
+ * line, so a pass moves about as many lines as a pass of 64; not for batch
+ * handles; the default above 200,000 vertices).  block: threads per workgroup
  * (256, 512 or 1024); grid: workgroups (0 = default); heavy: degree above
  * which a top-down frontier vertex is expanded by several workgroups
  * (path 3, >= 32); batch: trees in flight on path 3 (1 .. 8). */

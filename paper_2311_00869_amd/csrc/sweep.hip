@@ -93,7 +93,7 @@ int pick_path(fi_graph* g) {
   if (g->sched.path != 0) return g->sched.path;
   if (fits) return 1;
   if (n <= 200000 && g->L.nslots > 0) return 2;
-  return 3;
+  return 5;
 }
 
 }  // namespace

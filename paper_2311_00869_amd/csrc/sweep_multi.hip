@@ -784,7 +784,8 @@ hipError_t launch_mt(fi_graph* g, const MArgs& a, hipStream_t s) {
 
 template <bool STATS, int W>
 hipError_t launch_mt_block(fi_graph* g, const MArgs& a, hipStream_t s) {
-  const int nt = g->sched.block;
+  // the automatic schedule runs full 1,024-thread workgroups
+  const int nt = g->sched.path == 0 ? 1024 : g->sched.block;
   return nt == 1024 ? launch_mt<1024, STATS, W>(g, a, s)
          : nt == 512 ? launch_mt<512, STATS, W>(g, a, s)
                      : launch_mt<256, STATS, W>(g, a, s);

@@ -212,3 +212,17 @@ def test_powerlaw_multi_tile_all_paths():
         assert np.array_equal(sw, ref.trees[:, 0]), s
         assert np.array_equal(G.cloud(), ref.cloud), s
     G.close()
+
+
+def test_automatic_schedule_above_200k_vertices():
+    # path 0 takes the 128-tree multi-tree kernel (1,024-thread workgroups)
+    # above 200,000 vertices; 8 trees leave most of the pass's lanes idle
+    g = synth.chung_lu(250000, 1000000, 2.3, 21, p_pos=0.85)
+    K, seed = 8, 5
+    ref = oracle.sweep(g, seed, 0, K, checks=False)
+    G = _graph(g, cap=64)
+    G.set_schedule(path=0, block=256)
+    sw = G.sweep_range(0, K, seed, tree_switches=True).cpu().numpy().astype(np.uint64)
+    assert np.array_equal(sw, ref.trees[:, 0])
+    assert np.array_equal(G.cloud(), ref.cloud)
+    G.close()
