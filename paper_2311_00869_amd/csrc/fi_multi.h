@@ -277,7 +277,8 @@ __device__ __forceinline__ bool settle_w(const MState& A, int32_t v, const TW<W>
   return true;
 }
 
-// One wave pulls ne <= 64 vertices of rows up to 64 edges (as pull_small).
+// One wave pulls ne <= 64 vertices (lane k < ne holds vertex v; every row has
+// between 1 and 64 edges) and returns the entries some tree reached.
 // The rows are walked in chunks of as many whole rows as fit in 64 lanes, in
 // a two-stage pipeline: while the edges of one chunk are walked, the next
 // chunk's records are in flight (its adjacency was read while this chunk's
