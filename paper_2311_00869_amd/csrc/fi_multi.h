@@ -50,12 +50,24 @@ __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlan
 // Lane t's bit of a wave-uniform mask, taken as the execution mask.
 __device__ __forceinline__ bool lane_bit(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
 
-// A neighbour's candidate in the trees it reaches: its key in the high half and
-// the state it hands down in bit 0, so that the unsigned order is the key's
-// (the neighbours of one vertex have distinct keys).  Bit 0 is the state of
-// the minimum; no candidate equals kUnvisited.
-__device__ __forceinline__ uint64_t pull_cand(uint32_t key, bool st) {
-  return ((uint64_t)key << 32) | (uint64_t)st;
+// A neighbour's candidate in the trees it reaches: its key in the high half,
+// so that the unsigned order is the key's (the neighbours of one vertex have
+// distinct keys).  While a chunk of 64 edges is walked, the low half holds
+// kPending | the neighbour's lane in the chunk; once the chunk is walked, the
+// minimum's low half becomes the state it hands down (0 or 1).  No candidate
+// equals kUnvisited.
+constexpr uint32_t kPending = 0x40;
+
+__device__ __forceinline__ uint64_t walk_cand(uint32_t key, int j) {
+  return ((uint64_t)key << 32) | (kPending | (uint32_t)j);
+}
+
+// Lane t's state along edge j of the chunk: bit t of S_j (a lane-varying j).
+__device__ __forceinline__ bool edge_state(uint64_t S, int j) {
+  const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)S, j);
+  const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(S >> 32), j);
+  const int t = lane_id();
+  return ((t < 32 ? lo >> t : hi >> (t - 32)) & 1u) != 0;
 }
 
 
@@ -207,6 +219,7 @@ __device__ __forceinline__ void pull_edges_w(const uint32_t* adj, const uint64_t
     st = ldw<W>(stw, un);
     an = adj[c + 128 + lane < e1 ? c + 128 + lane : e0];
     uint64_t hits = __ballot(hit);
+    if (!hits) continue;
     while (hits) {
       const int j = __builtin_ctzll(hits);
       hits &= hits - 1;
@@ -215,11 +228,19 @@ __device__ __forceinline__ void pull_edges_w(const uint32_t* adj, const uint64_t
       for (int w = 0; w < W; ++w) {
         const uint64_t Fj = readlane64(F.w[w], j);
         if (W > 1 && Fj == 0) continue;  // the edge hits only trees of other words
-        const uint64_t Sj = readlane64(S.w[w], j);
         if (lane_bit(Fj)) {
-          const uint64_t c2 = pull_cand(vkey_of(km[w], Hj), lane_bit(Sj));
+          const uint64_t c2 = walk_cand(vkey_of(km[w], Hj), j);
           best[w] = c2 < best[w] ? c2 : best[w];
         }
+      }
+    }
+    // minima found in this chunk take their state
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const bool pend = best[w] != kUnvisited && (best[w] & kPending);
+      if (__ballot(pend)) {
+        const bool st = edge_state(S.w[w], (int)(best[w] & 63));
+        if (pend) best[w] = (best[w] & ~0xFFFFFFFFull) | (uint64_t)st;
       }
     }
   }
@@ -378,8 +399,11 @@ __device__ __forceinline__ uint64_t pull_small_w(const DevGraph& G, const MState
       TW<W> nbits, sbits;
 #pragma unroll
       for (int w = 0; w < W; ++w) {
-        nbits.w[w] = __ballot(best[w] != kUnvisited);
-        sbits.w[w] = __ballot(best[w] != kUnvisited && (best[w] & 1));
+        const bool has = best[w] != kUnvisited;
+        nbits.w[w] = __ballot(has);
+        // the minimum's edge lies in this chunk (rows are never split)
+        const bool st = edge_state(S.w[w], (int)(best[w] & 63));
+        sbits.w[w] = __ballot(has && st);
       }
       if (lane == 0) {
         lw[64 + cur] = nbits;
@@ -401,9 +425,8 @@ __device__ __forceinline__ uint64_t pull_small_w(const DevGraph& G, const MState
       for (int w = 0; w < W; ++w) {
         const uint64_t Fj = readlane64(F.w[w], jj);
         if (W > 1 && Fj == 0) continue;  // the edge hits only trees of other words
-        const uint64_t Sj = readlane64(S.w[w], jj);
         if (lane_bit(Fj)) {
-          const uint64_t c2 = pull_cand(vkey_of(km[w], Hj), lane_bit(Sj));
+          const uint64_t c2 = walk_cand(vkey_of(km[w], Hj), jj);
           best[w] = c2 < best[w] ? c2 : best[w];
         }
       }
