@@ -58,8 +58,11 @@ __device__ __forceinline__ bool lane_bit(uint64_t m) { return __builtin_amdgcn_i
 // equals kUnvisited.
 constexpr uint32_t kPending = 0x40;
 
-__device__ __forceinline__ uint64_t walk_cand(uint32_t key, int j) {
-  return ((uint64_t)key << 32) | (kPending | (uint32_t)j);
+// best = min(best, key << 32 | lo) for a key that no other candidate of best's
+// vertex and tree shares: comparing the high halves alone suffices, and a key
+// equal to kUnvisited's high half replaces it.
+__device__ __forceinline__ void take_min(uint64_t& best, uint32_t key, uint32_t lo) {
+  if (key <= (uint32_t)(best >> 32)) best = ((uint64_t)key << 32) | lo;
 }
 
 // Lane t's state along edge j of the chunk: bit t of S_j (a lane-varying j).
@@ -228,10 +231,7 @@ __device__ __forceinline__ void pull_edges_w(const uint32_t* adj, const uint64_t
       for (int w = 0; w < W; ++w) {
         const uint64_t Fj = readlane64(F.w[w], j);
         if (W > 1 && Fj == 0) continue;  // the edge hits only trees of other words
-        if (lane_bit(Fj)) {
-          const uint64_t c2 = walk_cand(vkey_of(km[w], Hj), j);
-          best[w] = c2 < best[w] ? c2 : best[w];
-        }
+        if (lane_bit(Fj)) take_min(best[w], vkey_of(km[w], Hj), kPending | j);
       }
     }
     // minima found in this chunk take their state
@@ -425,10 +425,7 @@ __device__ __forceinline__ uint64_t pull_small_w(const DevGraph& G, const MState
       for (int w = 0; w < W; ++w) {
         const uint64_t Fj = readlane64(F.w[w], jj);
         if (W > 1 && Fj == 0) continue;  // the edge hits only trees of other words
-        if (lane_bit(Fj)) {
-          const uint64_t c2 = walk_cand(vkey_of(km[w], Hj), jj);
-          best[w] = c2 < best[w] ? c2 : best[w];
-        }
+        if (lane_bit(Fj)) take_min(best[w], vkey_of(km[w], Hj), kPending | jj);
       }
     }
     if (cur >= 0) keep();
