@@ -31,6 +31,8 @@ def _mixed():
         synth.erdos_renyi_connected(6145, 15000, 0.8, 12),
         synth.erdos_renyi_connected(20000, 60000, 0.85, 13),
         synth.isolated_vertices(1),
+        synth.complete_graph(65, -1),  # rows of exactly 64 edges: one per chunk
+        synth.complete_graph(66, 1),   # rows of 65: one wave per row
     ]
 
 

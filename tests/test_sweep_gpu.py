@@ -226,3 +226,48 @@ def test_automatic_schedule_above_200k_vertices():
     assert np.array_equal(sw, ref.trees[:, 0])
     assert np.array_equal(G.cloud(), ref.cloud)
     G.close()
+
+
+def _row_boundaries():
+    """One graph whose rows sit on every class and chunk boundary of the
+    multi-tree pull: cliques with rows of 31, 32, 33, 63, 64 and 65 edges, and
+    stars with hubs of 2,048 and 2,049 edges (their leaves are rows of one
+    edge), joined into one component by a path, with mixed signs."""
+    rng = np.random.default_rng(7)
+    us, vs = [], []
+    off = 0
+    anchors = []
+    for k in (32, 33, 34, 64, 65, 66):
+        for a in range(k):
+            for b in range(a + 1, k):
+                us.append(off + a)
+                vs.append(off + b)
+        anchors.append(off)
+        off += k
+    for leaves in (2048, 2049):
+        for i in range(1, leaves + 1):
+            us.append(off)
+            vs.append(off + i)
+        anchors.append(off)
+        off += leaves + 1
+    for a, b in zip(anchors[:-1], anchors[1:]):
+        us.append(a + 1)
+        vs.append(b + 1)
+    sign = np.where(rng.random(len(us)) < 0.6, 1, -1)
+    return synth.csr_from_edges(off, us, vs, sign)
+
+
+def test_row_class_and_chunk_boundaries_all_paths():
+    g = _row_boundaries()
+    K, seed = 70, 31
+    ref = oracle.sweep(g, seed, 0, K, checks=False)
+    G = _graph(g, cap=128)
+    for s in [dict(path=1, block=256), dict(path=2, block=512), dict(path=3, block=256, heavy=64, batch=2),
+              dict(path=4, block=1024), dict(path=4, block=256, grid=9), dict(path=5, block=512),
+              dict(path=5, block=1024, grid=13)]:
+        G.set_schedule(**s)
+        G.cloud_reset()
+        sw = G.sweep_range(0, K, seed, tree_switches=True).cpu().numpy().astype(np.uint64)
+        assert np.array_equal(sw, ref.trees[:, 0]), s
+        assert np.array_equal(G.cloud(), ref.cloud), s
+    G.close()
