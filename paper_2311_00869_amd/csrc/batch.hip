@@ -482,8 +482,9 @@ struct BatchMArgs {
 // Multi-tree sweep of a batch: one workgroup per (graph, group of up to 64
 // trees), largest graph first, drawn by persistent workgroups.  Within a
 // workgroup the levels are pulls over every vertex not yet visited by all
-// trees (rows up to 64 edges 64 vertices per wave, longer rows one per
-// wave), separated by workgroup barriers.
+// trees (rows of up to 64 edges: the wave pulls the unfinished vertices of
+// one 64-vertex word; longer rows: one per wave), separated by workgroup
+// barriers.
 template <int NT>
 __global__ void __launch_bounds__(NT) k_batch_multi(BatchMArgs B) {
   constexpr int NW = NT / 64;

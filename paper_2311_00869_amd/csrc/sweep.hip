@@ -2,7 +2,7 @@
 // the min-key parent rule and fused state propagation, the exact frustration
 // count, the canonical-state key, and the cloud insert.
 //
-// Two kernel families compute identical results:
+// Three kernel families compute identical results:
 //   k_sweep_wg   - here: one workgroup per tree; the tree words and the BFS
 //                  queue live in LDS (small graphs) or in a per-workgroup
 //                  slice of the workspace.  Trees are spread over workgroups,
@@ -10,8 +10,9 @@
 //   k_sweep_grid - sweep_grid.hip: the whole grid works on a few trees at a
 //                  time (persistent cooperative kernel), for graphs far
 //                  beyond one workgroup.
-//   k_sweep_multi - sweep_multi.hip: the whole grid sweeps 64 trees at once
-//                  with one bit per tree in every per-vertex word.
+//   k_sweep_multi - sweep_multi.hip: the whole grid sweeps 64 or 128 trees
+//                  at once with one bit per tree in the fields of each
+//                  vertex's record.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
