@@ -252,23 +252,37 @@ template <int W>
 __device__ __forceinline__ void comp_min_w(const int32_t* cverts, int32_t b, int32_t e,
                                            const KeyMix* km, uint64_t* best) {
   const int lane = lane_id();
+  // two running minima (even and odd vertices of each 64) keep two compare
+  // chains in flight; the keys of distinct vertices never tie
+  uint64_t alt[W];
 #pragma unroll
-  for (int w = 0; w < W; ++w) best[w] = kUnvisited;
+  for (int w = 0; w < W; ++w) best[w] = alt[w] = kUnvisited;
   for (int32_t c = b; c < e; c += 64) {
     const int32_t i = c + lane;
     const int32_t mine = i < e ? cverts[i] : 0;
     const int cnt = min(64, e - c);
     const uint32_t hm = fmix32((uint32_t)mine);
-    for (int j = 0; j < cnt; ++j) {
-      const uint32_t v = (uint32_t)__builtin_amdgcn_readlane(mine, j);
-      const uint32_t h = (uint32_t)__builtin_amdgcn_readlane((int)hm, j);
+    int j = 0;
+    for (; j + 1 < cnt; j += 2) {
+      const uint32_t v0 = (uint32_t)__builtin_amdgcn_readlane(mine, j);
+      const uint32_t h0 = (uint32_t)__builtin_amdgcn_readlane((int)hm, j);
+      const uint32_t v1 = (uint32_t)__builtin_amdgcn_readlane(mine, j + 1);
+      const uint32_t h1 = (uint32_t)__builtin_amdgcn_readlane((int)hm, j + 1);
 #pragma unroll
       for (int w = 0; w < W; ++w) {
-        const uint64_t k = root_candidate(vkey_of(km[w], h), v);
-        best[w] = k < best[w] ? k : best[w];
+        take_min(best[w], vkey_of(km[w], h0), (uint32_t)root_candidate(0, v0));
+        take_min(alt[w], vkey_of(km[w], h1), (uint32_t)root_candidate(0, v1));
       }
     }
+    if (j < cnt) {
+      const uint32_t v0 = (uint32_t)__builtin_amdgcn_readlane(mine, j);
+      const uint32_t h0 = (uint32_t)__builtin_amdgcn_readlane((int)hm, j);
+#pragma unroll
+      for (int w = 0; w < W; ++w) take_min(best[w], vkey_of(km[w], h0), (uint32_t)root_candidate(0, v0));
+    }
   }
+#pragma unroll
+  for (int w = 0; w < W; ++w) best[w] = alt[w] < best[w] ? alt[w] : best[w];
 }
 
 // The write-back of vertex v once its trees of this level are decided.

@@ -183,15 +183,36 @@ __device__ __forceinline__ void mlist_global(bool in, int32_t v, int dv, int32_t
   }
 }
 
+// Root vertex r0 of the trees in `mine`: its records, the level-0 lists
+// (once), and the wave's counters (fin in lane 0: the degree of a root
+// already visited by every tree).
+template <int W>
+__device__ __forceinline__ void put_root(uint32_t r0, const TW<W>& mine, const TW<W>& valid,
+                                         const MArgs& A, const int32_t* rp, uint64_t& cnt,
+                                         uint64_t& deg, uint64_t& fin) {
+  const int lane = lane_id();
+  const int dv = rp[r0 + 1] - rp[r0];
+  const bool full = eq_w(mine, valid);
+  if (lane == 0) {
+    stw_<W>(A.S.nbw[0], r0, mine);
+    stw_<W>(A.S.vis, r0, mine);
+    if (full) {
+      aand64(A.S.unf + (r0 >> 6), ~(1ull << (r0 & 63)));
+      fin += (uint64_t)dv;
+    }
+  }
+  mlist_global(lane == 0, (int32_t)r0, dv, A.pl, A.pm, A.ph, A.ctl + cF(0));
+  cnt += 1;
+  deg += (uint64_t)dv;
+}
+
 // Roots of one component (the wave owns it): each distinct root vertex, over
 // all W words, gets the trees it roots in its records and enters the level-0
-// lists once.  cnt / deg gather the wave's roots and their degrees, fin (in
-// lane 0) the degrees of roots already visited by every tree.
+// lists once.
 template <int W>
 __device__ __forceinline__ void set_roots(const uint64_t* best, const bool* vlane,
                                           const TW<W>& valid, const MArgs& A, const int32_t* rp,
                                           uint64_t& cnt, uint64_t& deg, uint64_t& fin) {
-  const int lane = lane_id();
   bool ok[W];
   uint32_t r[W];
   uint64_t rem[W];
@@ -217,20 +238,35 @@ __device__ __forceinline__ void set_roots(const uint64_t* best, const bool* vlan
       mine.w[w] = __ballot(ok[w] && r[w] == r0);
       rem[w] &= ~mine.w[w];
     }
-    const int dv = rp[r0 + 1] - rp[r0];
-    const bool full = eq_w(mine, valid);
-    if (lane == 0) {
-      stw_<W>(A.S.nbw[0], r0, mine);
-      stw_<W>(A.S.vis, r0, mine);
-      if (full) {
-        aand64(A.S.unf + (r0 >> 6), ~(1ull << (r0 & 63)));
-        fin += (uint64_t)dv;
-      }
-    }
-    mlist_global(lane == 0, (int32_t)r0, dv, A.pl, A.pm, A.ph, A.ctl + cF(0));
-    cnt += 1;
-    deg += (uint64_t)dv;
+    put_root<W>(r0, mine, valid, A, rp, cnt, deg, fin);
   }
+}
+
+// Roots of big components, one wave per (component, tree): the wave of tree t
+// takes t's root vertex if no tree before t has the same root.
+template <int W>
+__device__ __forceinline__ void big_root(const uint64_t* rb, int t, const bool* vlane,
+                                         const TW<W>& valid, const MArgs& A, const int32_t* rp,
+                                         uint64_t& cnt, uint64_t& deg, uint64_t& fin) {
+  uint64_t best[W];
+  uint32_t r[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    best[w] = vlane[w] ? rb[64 * w + lane_id()] : kUnvisited;
+    r[w] = (uint32_t)word_vertex(best[w]);
+  }
+  uint32_t rt = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w)
+    if (w == t / 64) rt = (uint32_t)__builtin_amdgcn_readlane((int)r[w], t % 64);
+  TW<W> mine;
+  int first = -1;
+#pragma unroll
+  for (int w = W - 1; w >= 0; --w) {
+    mine.w[w] = __ballot(vlane[w] && best[w] != kUnvisited && r[w] == rt);
+    if (mine.w[w]) first = 64 * w + __builtin_ctzll(mine.w[w]);
+  }
+  if (first == t) put_root<W>(rt, mine, valid, A, rp, cnt, deg, fin);
 }
 
 template <int NT, bool STATS, int W>
@@ -264,6 +300,8 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
       A.S.unf[i] = G.word_mask[i];
       A.S.cand[i] = 0;
     }
+    // big components' root minima (read by several waves each, so cleared here)
+    for (int64_t i = stid; i < (int64_t)A.nbig * 64 * W; i += sstride) A.rootbig[i] = kUnvisited;
     if (rank == 0)
       for (int i = tid; i < kMCtlWords; i += NT) ctl[i] = i == cUNF ? (uint64_t)G.nnz : 0ull;
     if (tid == 0) {
@@ -290,15 +328,11 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
         }
       }
       group_sync(A.bar, rank, nb);
-      for (int64_t b = gwave; b < A.nbig; b += nwaves) {
-        uint64_t* rb = A.rootbig + (size_t)b * 64 * W;
-        uint64_t best[W];
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-          best[w] = vlane[w] ? rb[64 * w + lane] : kUnvisited;
-          if (vlane[w]) rb[64 * w + lane] = kUnvisited;
-        }
-        set_roots<W>(best, vlane, valid, A, rp, cnt, deg, fin);
+      for (int64_t it = gwave; it < (int64_t)A.nbig * 64 * W; it += nwaves) {
+        const int t = (int)(it % (64 * W));
+        if (t < nvalid)
+          big_root<W>(A.rootbig + (size_t)(it / (64 * W)) * 64 * W, t, vlane, valid, A, rp, cnt, deg,
+                      fin);
       }
       fin = wave_sum_u64(fin);
       if (lane == 0) {
