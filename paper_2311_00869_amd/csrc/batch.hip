@@ -504,6 +504,7 @@ __global__ void __launch_bounds__(NT) k_batch_multi(BatchMArgs B) {
   S.vis = S.nbw[0] + 3;
   S.unf = S.nbw[0] + mt::kRecFields * nm;
   S.cand = nullptr;
+  S.stc = nullptr;
   uint64_t* table = S.unf + (nm / 64 + 2);
   const int64_t nitems = (int64_t)B.G * B.groups;
 

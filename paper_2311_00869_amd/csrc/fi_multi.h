@@ -25,6 +25,9 @@ struct MState {
   uint64_t* vis;
   uint64_t* unf;
   uint64_t* cand;
+  // final states, W words per vertex side by side, written when the vertex
+  // is visited by every tree (null: not kept)
+  uint64_t* stc;
 };
 
 __device__ __forceinline__ uint64_t amin64(uint64_t* p, uint64_t v) {
@@ -139,6 +142,35 @@ __device__ __forceinline__ void stw_(uint64_t* a, int64_t v, const TW<W>& x) {
     for (int k = 0; k < W; k += 2)
       *reinterpret_cast<ulonglong2*>(a + kRecFields * W * v + k) = make_ulonglong2(x.w[k], x.w[k + 1]);
   }
+}
+
+// The final-state copy of vertex v (W words at W v).
+template <int W>
+__device__ __forceinline__ void put_final(const MState& A, int64_t v, const TW<W>& st) {
+  if (!A.stc) return;
+  if constexpr (W == 1) {
+    A.stc[v] = st.w[0];
+  } else {
+#pragma unroll
+    for (int k = 0; k < W; k += 2)
+      *reinterpret_cast<ulonglong2*>(A.stc + W * v + k) = make_ulonglong2(st.w[k], st.w[k + 1]);
+  }
+}
+
+template <int W>
+__device__ __forceinline__ TW<W> get_final(const uint64_t* stc, int64_t v) {
+  TW<W> r;
+  if constexpr (W == 1) {
+    r.w[0] = stc[v];
+  } else {
+#pragma unroll
+    for (int k = 0; k < W; k += 2) {
+      const ulonglong2 x = *reinterpret_cast<const ulonglong2*>(stc + W * v + k);
+      r.w[k] = x.x;
+      r.w[k + 1] = x.y;
+    }
+  }
+  return r;
 }
 
 // A value every lane holds alike, moved to scalar registers.
@@ -304,7 +336,10 @@ __device__ __forceinline__ bool settle_w(const MState& A, int32_t v, const TW<W>
     stw_<W>(A.vis, v, nv);
     stw_<W>(A.nbw[p], v, newb);
     if (any_w(stb)) stw_<W>(A.stw, v, or_w(st, stb));
-    if (full) aand64(A.unf + (v >> 6), ~(1ull << (v & 63)));
+    if (full) {
+      aand64(A.unf + (v >> 6), ~(1ull << (v & 63)));
+      put_final<W>(A, v, or_w(st, stb));
+    }
   }
   if (full) fin += (uint64_t)dv;
   cnt += 1;
@@ -462,7 +497,10 @@ __device__ __forceinline__ uint64_t pull_small_w(const DevGraph& G, const MState
     stw_<W>(A.vis, v, nv);
     stw_<W>(A.nbw[p], v, mnew);
     if (any_w(mstb)) stw_<W>(A.stw, v, or_w(st, mstb));
-    if (full) aand64(A.unf + (v >> 6), ~(1ull << (v & 63)));
+    if (full) {
+      aand64(A.unf + (v >> 6), ~(1ull << (v & 63)));
+      put_final<W>(A, v, or_w(st, mstb));
+    }
   }
   if (ok && push) aand64(A.cand + (v >> 6), ~(1ull << (v & 63)));
   const uint64_t reached = __ballot(got);

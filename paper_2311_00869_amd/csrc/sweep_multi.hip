@@ -198,6 +198,7 @@ __device__ __forceinline__ void put_root(uint32_t r0, const TW<W>& mine, const T
     stw_<W>(A.S.vis, r0, mine);
     if (full) {
       aand64(A.S.unf + (r0 >> 6), ~(1ull << (r0 & 63)));
+      put_final<W>(A.S, r0, TW<W>{});  // a root's state is +1 in its trees
       fin += (uint64_t)dv;
     }
   }
@@ -575,7 +576,10 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
                 stw_<W>(A.S.vis, v, nv);
                 stw_<W>(A.S.nbw[p], v, mnew);
                 if (any_w(mstb)) stw_<W>(A.S.stw, v, or_w(stq, mstb));
-                if (full) aand64(A.S.unf + (v >> 6), ~(1ull << (v & 63)));
+                if (full) {
+                  aand64(A.S.unf + (v >> 6), ~(1ull << (v & 63)));
+                  put_final<W>(A.S, v, or_w(stq, mstb));
+                }
                 aor64(rmn + (i >> 6), 1ull << (i & 63));
               }
               cnt += 1;
@@ -708,7 +712,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
           TW<W> x{};
           if (e < G.m) {
             const uint2 uv = G.edges[e];
-            const TW<W> su = ldw<W>(A.S.stw, uv.x), sv = ldw<W>(A.S.stw, uv.y & kVertexMask);
+            const TW<W> su = get_final<W>(A.S.stc, uv.x), sv = get_final<W>(A.S.stc, uv.y & kVertexMask);
             const uint64_t neg = (uv.y >> 31) ? ~0ull : 0ull;
 #pragma unroll
             for (int w = 0; w < W; ++w) x.w[w] = su.w[w] ^ sv.w[w] ^ neg;
@@ -747,7 +751,8 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
         const int64_t v = i * 64 + lane;
         TW<W> cs{};
         if (v < n) {
-          const TW<W> a = ldw<W>(A.S.stw, v), b = ldw<W>(A.S.stw, G.comp[v]);
+          // an isolated vertex is its own anchor (its copy is never written)
+          const TW<W> a = get_final<W>(A.S.stc, v), b = get_final<W>(A.S.stc, G.comp[v]);
 #pragma unroll
           for (int w = 0; w < W; ++w) cs.w[w] = a.w[w] ^ b.w[w];
         }
@@ -848,6 +853,9 @@ hipError_t launch_multi(fi_graph* g, const SweepArgs& sa, int words, hipStream_t
   a.S.vis = a.S.nbw[0] + 3 * words;
   a.S.unf = (uint64_t*)(ws + L.gvis);
   a.S.cand = (uint64_t*)(ws + L.gsb);
+  // the final-state copy sits in the whole-grid path's tree words (8 words a
+  // vertex per slot, never in use at the same time)
+  a.S.stc = (uint64_t*)(ws + L.gpw);
   a.lstride = (int64_t)g->dg.n + 64;
   a.hstride = (int64_t)L.hcap + 64;
   a.rlstride = a.lstride / 64 + 2;
