@@ -442,21 +442,43 @@ __global__ void __launch_bounds__(1024) k_gl_descend_small(const int32_t* rp_g,
     const uint32_t* min_ = mx + (k % 3) * ncomp;
     uint32_t* mout = mx + ((k + 1) % 3) * ncomp;
     uint32_t* mclr = mx + ((k + 2) % 3) * ncomp;
-    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
-      const int32_t c = cs[i];
-      const float sc = (c >= 0 && min_[c] >= thresh) ? down : 1.0f;
-      float acc = 0.0f;
-      for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
-        const uint32_t a = adj[e];
-        const float gj = gin[a & kVertexMask] * sc;
-        acc += (a >> 31) ? -gj : gj;
+    for (int32_t i0 = 0; i0 < n; i0 += blockDim.x) {
+      const int32_t i = i0 + threadIdx.x;
+      const int32_t c = i < n ? cs[i] : -1;
+      float v = 0.0f;
+      if (i < n) {
+        const float sc = (c >= 0 && min_[c] >= thresh) ? down : 1.0f;
+        float acc = 0.0f;
+        // two entries' loads in flight; the sum keeps the row's order
+        int64_t e = rp[i];
+        const int64_t e1 = rp[i + 1];
+        for (; e + 1 < e1; e += 2) {
+          const uint32_t a0 = adj[e], a1 = adj[e + 1];
+          const float x0 = gin[a0 & kVertexMask], x1 = gin[a1 & kVertexMask];
+          const float g0 = x0 * sc, g1 = x1 * sc;
+          acc += (a0 >> 31) ? -g0 : g0;
+          acc += (a1 >> 31) ? -g1 : g1;
+        }
+        if (e < e1) {
+          const uint32_t a = adj[e];
+          const float gj = gin[a & kVertexMask] * sc;
+          acc += (a >> 31) ? -gj : gj;
+        }
+        const float g = -0.5f * acc * 1.0f;
+        v = gin[i] * sc - alpha * g;
+        gout[i] = v;
+        if (c >= 0 && comp[i] == i && sc != 1.0f) ex[c] += shift;
       }
-      const float g = -0.5f * acc * 1.0f;
-      const float v = gin[i] * sc - alpha * g;
-      gout[i] = v;
-      if (c >= 0) {
-        atomicMax(mout + c, __float_as_uint(fabsf(v)));
-        if (comp[i] == i && sc != 1.0f) ex[c] += shift;
+      // the component maxima: one atomic per wave when its lanes share one
+      // component (the maximum does not depend on the order)
+      uint32_t m = c >= 0 ? __float_as_uint(fabsf(v)) : 0u;
+      const int32_t c0 = __builtin_amdgcn_readfirstlane(c);
+      if (__ballot(c != c0) == 0) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o));
+        if (c0 >= 0 && (threadIdx.x & 63) == 0) atomicMax(mout + c0, m);
+      } else if (c >= 0) {
+        atomicMax(mout + c, m);
       }
     }
     for (int32_t c = threadIdx.x; c < ncomp; c += blockDim.x) mclr[c] = 0;
