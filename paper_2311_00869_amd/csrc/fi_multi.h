@@ -78,14 +78,7 @@ __device__ __forceinline__ bool edge_state(uint64_t S, int j) {
 
 
 __device__ __forceinline__ uint64_t wave_or64(uint64_t x) {
-#pragma unroll
-  for (int dd = 32; dd > 0; dd >>= 1) {
-    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, dd);
-    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), dd);
-    x |= ((uint64_t)hi << 32) | lo;
-  }
-  return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32)) << 32) |
-         (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+  return ((uint64_t)wave_or_u32((uint32_t)(x >> 32)) << 32) | wave_or_u32((uint32_t)x);
 }
 
 
@@ -386,11 +379,11 @@ __device__ __forceinline__ uint64_t pull_small_w(const DevGraph& G, const MState
   };
   auto chunk_at = [&](int k0) {
     Chunk c;
-    const int eb = uni(__shfl(excl, k0));
+    const int eb = __builtin_amdgcn_readlane(excl, k0);
     const bool inr = ok && lane >= k0 && inc - eb <= 64;
     const uint64_t fit = __ballot(inr);
     c.k1 = k0 + (int)__popcll(fit);
-    c.total = uni(__shfl(inc, c.k1 - 1)) - eb;
+    c.total = __builtin_amdgcn_readlane(inc, c.k1 - 1) - eb;
     const int e = inc - eb;
     const uint64_t starts = 1ull | wave_or64(inr && e < c.total ? (1ull << e) : 0ull);
     const int r = (int)__popcll(starts & ((2ull << lane) - 1));

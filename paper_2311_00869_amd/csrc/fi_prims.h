@@ -16,6 +16,32 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Wave-wide OR / maximum of a 32-bit value with DPP lane moves (no LDS round
+// trips): pairs and quads, half rows and rows, then rows 1 and 3 take the row
+// before and rows 2 and 3 take row 1, so lane 63 ends with the whole wave's.
+// Both operations are idempotent, so lanes a move leaves alone keep theirs.
+#define FI_DPP(x, ctrl, rows) \
+  ((uint32_t)__builtin_amdgcn_update_dpp((int)(x), (int)(x), (ctrl), (rows), 0xF, false))
+__device__ __forceinline__ uint32_t wave_or_u32(uint32_t x) {
+  x |= FI_DPP(x, 0xB1, 0xF);   // quad_perm [1,0,3,2]
+  x |= FI_DPP(x, 0x4E, 0xF);   // quad_perm [2,3,0,1]
+  x |= FI_DPP(x, 0x141, 0xF);  // row_half_mirror
+  x |= FI_DPP(x, 0x140, 0xF);  // row_mirror
+  x |= FI_DPP(x, 0x142, 0xA);  // row_bcast:15
+  x |= FI_DPP(x, 0x143, 0xC);  // row_bcast:31
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
+  x = max(x, FI_DPP(x, 0xB1, 0xF));
+  x = max(x, FI_DPP(x, 0x4E, 0xF));
+  x = max(x, FI_DPP(x, 0x141, 0xF));
+  x = max(x, FI_DPP(x, 0x140, 0xF));
+  x = max(x, FI_DPP(x, 0x142, 0xA));
+  x = max(x, FI_DPP(x, 0x143, 0xC));
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+#undef FI_DPP
+
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
 #pragma unroll
   for (int d = 32; d > 0; d >>= 1) x += __shfl_xor(x, d);

@@ -474,8 +474,7 @@ __global__ void __launch_bounds__(1024) k_gl_descend_small(const int32_t* rp_g,
       uint32_t m = c >= 0 ? __float_as_uint(fabsf(v)) : 0u;
       const int32_t c0 = __builtin_amdgcn_readfirstlane(c);
       if (__ballot(c != c0) == 0) {
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o));
+        m = wave_max_u32(m);
         if (c0 >= 0 && (threadIdx.x & 63) == 0) atomicMax(mout + c0, m);
       } else if (c >= 0) {
         atomicMax(mout + c, m);
