@@ -449,17 +449,20 @@ __global__ void __launch_bounds__(1024) k_gl_descend_small(const int32_t* rp_g,
       if (i < n) {
         const float sc = (c >= 0 && min_[c] >= thresh) ? down : 1.0f;
         float acc = 0.0f;
-        // two entries' loads in flight; the sum keeps the row's order
+        // four entries' loads in flight; the sum keeps the row's order
         int64_t e = rp[i];
         const int64_t e1 = rp[i + 1];
-        for (; e + 1 < e1; e += 2) {
-          const uint32_t a0 = adj[e], a1 = adj[e + 1];
+        for (; e + 3 < e1; e += 4) {
+          const uint32_t a0 = adj[e], a1 = adj[e + 1], a2 = adj[e + 2], a3 = adj[e + 3];
           const float x0 = gin[a0 & kVertexMask], x1 = gin[a1 & kVertexMask];
-          const float g0 = x0 * sc, g1 = x1 * sc;
+          const float x2 = gin[a2 & kVertexMask], x3 = gin[a3 & kVertexMask];
+          const float g0 = x0 * sc, g1 = x1 * sc, g2 = x2 * sc, g3 = x3 * sc;
           acc += (a0 >> 31) ? -g0 : g0;
           acc += (a1 >> 31) ? -g1 : g1;
+          acc += (a2 >> 31) ? -g2 : g2;
+          acc += (a3 >> 31) ? -g3 : g3;
         }
-        if (e < e1) {
+        for (; e < e1; ++e) {
           const uint32_t a = adj[e];
           const float gj = gin[a & kVertexMask] * sc;
           acc += (a >> 31) ? -gj : gj;
@@ -467,7 +470,7 @@ __global__ void __launch_bounds__(1024) k_gl_descend_small(const int32_t* rp_g,
         const float g = -0.5f * acc * 1.0f;
         v = gin[i] * sc - alpha * g;
         gout[i] = v;
-        if (c >= 0 && comp[i] == i && sc != 1.0f) ex[c] += shift;
+        if (sc != 1.0f && c >= 0 && comp[i] == i) ex[c] += shift;  // comp is read only then
       }
       // the component maxima: one atomic per wave when its lanes share one
       // component (the maximum does not depend on the order)
