@@ -16,57 +16,70 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// Wave-wide OR / maximum of a 32-bit value with DPP lane moves (no LDS round
-// trips): pairs and quads, half rows and rows, then rows 1 and 3 take the row
-// before and rows 2 and 3 take row 1, so lane 63 ends with the whole wave's.
-// Both operations are idempotent, so lanes a move leaves alone keep theirs.
-#define FI_DPP(x, ctrl, rows) \
-  ((uint32_t)__builtin_amdgcn_update_dpp((int)(x), (int)(x), (ctrl), (rows), 0xF, false))
+// Wave-wide reductions with DPP lane moves (no LDS round trips): pairs and
+// quads, half rows and rows, then rows 1 and 3 take the row before and rows 2
+// and 3 take row 1, so lane 63 ends with the whole wave's result, which is
+// returned to every lane.  Lanes a move leaves alone get `old` (the identity
+// of a sum, or the lane's own value for idempotent operations).  Every lane of
+// the wave must be active.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp32(uint32_t x, uint32_t old) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)x, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp64(uint64_t x, uint64_t old) {
+  return ((uint64_t)dpp32<CTRL, ROWS>((uint32_t)(x >> 32), (uint32_t)(old >> 32)) << 32) |
+         dpp32<CTRL, ROWS>((uint32_t)x, (uint32_t)old);
+}
+template <int CTRL, int ROWS, class T>
+__device__ __forceinline__ T dpp_t(T x, T old) {
+  if constexpr (sizeof(T) == 8) return (T)dpp64<CTRL, ROWS>((uint64_t)x, (uint64_t)old);
+  else return (T)dpp32<CTRL, ROWS>((uint32_t)x, (uint32_t)old);
+}
+// quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror,
+// row_bcast:15 (rows 1, 3), row_bcast:31 (rows 2, 3); lane 63's result
+template <bool kZeroOld, class T, class Op>
+__device__ __forceinline__ T wave_reduce(T x, Op op) {
+  x = op(x, dpp_t<0xB1, 0xF>(x, kZeroOld ? T(0) : x));
+  x = op(x, dpp_t<0x4E, 0xF>(x, kZeroOld ? T(0) : x));
+  x = op(x, dpp_t<0x141, 0xF>(x, kZeroOld ? T(0) : x));
+  x = op(x, dpp_t<0x140, 0xF>(x, kZeroOld ? T(0) : x));
+  x = op(x, dpp_t<0x142, 0xA>(x, kZeroOld ? T(0) : x));
+  x = op(x, dpp_t<0x143, 0xC>(x, kZeroOld ? T(0) : x));
+  if constexpr (sizeof(T) == 8) {
+    return (T)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)x >> 32), 63)
+                << 32) |
+               (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)x, 63));
+  } else {
+    return (T)__builtin_amdgcn_readlane((int)x, 63);
+  }
+}
+
 __device__ __forceinline__ uint32_t wave_or_u32(uint32_t x) {
-  x |= FI_DPP(x, 0xB1, 0xF);   // quad_perm [1,0,3,2]
-  x |= FI_DPP(x, 0x4E, 0xF);   // quad_perm [2,3,0,1]
-  x |= FI_DPP(x, 0x141, 0xF);  // row_half_mirror
-  x |= FI_DPP(x, 0x140, 0xF);  // row_mirror
-  x |= FI_DPP(x, 0x142, 0xA);  // row_bcast:15
-  x |= FI_DPP(x, 0x143, 0xC);  // row_bcast:31
-  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+  return wave_reduce<false>(x, [](uint32_t a, uint32_t b) { return a | b; });
 }
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
-  x = max(x, FI_DPP(x, 0xB1, 0xF));
-  x = max(x, FI_DPP(x, 0x4E, 0xF));
-  x = max(x, FI_DPP(x, 0x141, 0xF));
-  x = max(x, FI_DPP(x, 0x140, 0xF));
-  x = max(x, FI_DPP(x, 0x142, 0xA));
-  x = max(x, FI_DPP(x, 0x143, 0xC));
-  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+  return wave_reduce<false>(x, [](uint32_t a, uint32_t b) { return a > b ? a : b; });
 }
-#undef FI_DPP
-
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
-#pragma unroll
-  for (int d = 32; d > 0; d >>= 1) x += __shfl_xor(x, d);
-  return x;
+  return wave_reduce<true>(x, [](uint64_t a, uint64_t b) { return a + b; });
 }
-
+// (LDS permutes here: the one hot caller, the randomized DFS step, shares its
+// kernel with the one-tree-per-workgroup BFS, which ran a quarter slower when
+// this minimum used DPP moves.)
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
 #pragma unroll
   for (int d = 32; d > 0; d >>= 1) {
-    uint64_t y = __shfl_xor(x, d);
+    const uint64_t y = __shfl_xor(x, d);
     x = y < x ? y : x;
   }
   return x;
 }
-
 __device__ __forceinline__ int wave_min_i32(int x) {
-#pragma unroll
-  for (int d = 32; d > 0; d >>= 1) x = min(x, __shfl_xor(x, d));
-  return x;
+  return wave_reduce<false>(x, [](int a, int b) { return a < b ? a : b; });
 }
-
 __device__ __forceinline__ int wave_max_i32(int x) {
-#pragma unroll
-  for (int d = 32; d > 0; d >>= 1) x = max(x, __shfl_xor(x, d));
-  return x;
+  return wave_reduce<false>(x, [](int a, int b) { return a > b ? a : b; });
 }
 
 // Wave-aggregated append: lanes with `pred` write `val` to consecutive slots
