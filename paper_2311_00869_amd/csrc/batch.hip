@@ -493,7 +493,7 @@ __global__ void __launch_bounds__(NT) k_batch_multi(BatchMArgs B) {
   __shared__ int64_t s_item;
   __shared__ int s_any[2];  // some vertex reached, by level parity
   __shared__ uint64_t s_acc[3][64];
-  __shared__ mt::TW<1> s_pw[NW][3 * 64];  // per wave: wanted trees, outcomes of short rows
+  __shared__ mt::TW<1> s_pw[NW][4 * 64];  // per wave: short rows' wanted trees and outcomes, edge states
   char* slot = B.slots + (size_t)blockIdx.x * B.slot_stride;
   const size_t nm = (size_t)B.n_max;
   // vertex records of one word per field, then the unfinished-vertex bitmap

@@ -345,8 +345,9 @@ __device__ __forceinline__ bool settle_w(const MState& A, int32_t v, const TW<W>
 // The rows are walked in chunks of as many whole rows as fit in 64 lanes, in
 // a two-stage pipeline: while the edges of one chunk are walked, the next
 // chunk's records are in flight (its adjacency was read while this chunk's
-// records arrived).  lw is the wave's LDS scratch of 3 x 64 entries: each
-// row's wanted trees, then its newly reached trees and their states.
+// records arrived).  lw is the wave's LDS scratch of 4 x 64 entries: each
+// row's wanted trees, its newly reached trees and their states, and the
+// states each edge of the current chunk hands down.
 template <int W>
 __device__ __forceinline__ uint64_t pull_small_w(const DevGraph& G, const MState& A, int32_t v,
                                                  int ne, int pp, int p, const TW<W>& valid,
@@ -418,6 +419,7 @@ __device__ __forceinline__ uint64_t pull_small_w(const DevGraph& G, const MState
 #pragma unroll
       for (int w = 0; w < W; ++w) S.w[w] = su.w[w] ^ gn;
     }
+    lw[192 + lane] = S;  // the states each edge hands down, read back per row
     const int kj = c0.kj;
     const int k1 = c0.k1;
     // c1's records
@@ -444,7 +446,7 @@ __device__ __forceinline__ uint64_t pull_small_w(const DevGraph& G, const MState
         const bool has = best[w] != kUnvisited;
         nbits.w[w] = __ballot(has);
         // the minimum's edge lies in this chunk (rows are never split)
-        const bool st = edge_state(S.w[w], (int)(best[w] & 63));
+        const bool st = (lw[192 + (int)(best[w] & 63)].w[w] >> lane) & 1;
         sbits.w[w] = __ballot(has && st);
       }
       if (lane == 0) {

@@ -116,7 +116,7 @@ struct MS {
   uint32_t nl, nm, nh, hunits;
   uint64_t hbest[64 * W];
   uint64_t tacc[3][64 * W];
-  TW<W> pw[NT / 64][3 * 64];  // per wave: wanted trees, outcomes of small rows
+  TW<W> pw[NT / 64][4 * 64];  // per wave: small rows' wanted trees and outcomes, edge states
 };
 
 // Move the LDS staging list into a global list (one reservation per block).
