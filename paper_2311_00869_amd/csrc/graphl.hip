@@ -398,6 +398,7 @@ __global__ void __launch_bounds__(1024) k_gl_plan(const int32_t* rp, const int32
 // plus the CSR itself (4(n+1) + 4 nnz) when it fits, so that a step touches
 // no global memory.
 constexpr int kSmallDescentN = 4096;
+constexpr int kSmallRows = kSmallDescentN / 1024;  // rows per thread of the fused descent
 constexpr size_t kSmallDescentLds = 128 * 1024;
 
 template <bool CSR_IN_LDS>
@@ -438,20 +439,36 @@ __global__ void __launch_bounds__(1024) k_gl_descend_small(const int32_t* rp_g,
   __syncthreads();
   float* gin = G0;
   float* gout = G1;
+  // each thread's rows (at most kSmallRows of them, n <= kSmallRows * 1024)
+  // keep their bounds, component slot and anchor flag in registers
+  int32_t rb[kSmallRows], re[kSmallRows], rc[kSmallRows];
+  bool ra[kSmallRows];
+#pragma unroll
+  for (int q = 0; q < kSmallRows; ++q) {
+    const int32_t i = q * (int32_t)blockDim.x + (int32_t)threadIdx.x;
+    const bool in = i < n;
+    rb[q] = in ? rp[i] : 0;
+    re[q] = in ? rp[i + 1] : 0;
+    rc[q] = in ? cs[i] : -1;
+    ra[q] = in && comp[i] == i;
+  }
+  int k3 = 0;  // step mod 3: which maxima buffer is read, written, cleared
   for (int64_t k = 0; k < steps; ++k) {
-    const uint32_t* min_ = mx + (k % 3) * ncomp;
-    uint32_t* mout = mx + ((k + 1) % 3) * ncomp;
-    uint32_t* mclr = mx + ((k + 2) % 3) * ncomp;
-    for (int32_t i0 = 0; i0 < n; i0 += blockDim.x) {
-      const int32_t i = i0 + threadIdx.x;
-      const int32_t c = i < n ? cs[i] : -1;
+    const uint32_t* min_ = mx + k3 * ncomp;
+    uint32_t* mout = mx + (k3 == 2 ? 0 : k3 + 1) * ncomp;
+    uint32_t* mclr = mx + (k3 == 0 ? 2 : k3 - 1) * ncomp;
+#pragma unroll
+    for (int q = 0; q < kSmallRows; ++q) {
+      if (q * (int32_t)blockDim.x >= n) break;
+      const int32_t i = q * (int32_t)blockDim.x + (int32_t)threadIdx.x;
+      const int32_t c = rc[q];
       float v = 0.0f;
       if (i < n) {
         const float sc = (c >= 0 && min_[c] >= thresh) ? down : 1.0f;
         float acc = 0.0f;
         // four entries' loads in flight; the sum keeps the row's order
-        int64_t e = rp[i];
-        const int64_t e1 = rp[i + 1];
+        int32_t e = rb[q];
+        const int32_t e1 = re[q];
         for (; e + 3 < e1; e += 4) {
           const uint32_t a0 = adj[e], a1 = adj[e + 1], a2 = adj[e + 2], a3 = adj[e + 3];
           const float x0 = gin[a0 & kVertexMask], x1 = gin[a1 & kVertexMask];
@@ -470,7 +487,7 @@ __global__ void __launch_bounds__(1024) k_gl_descend_small(const int32_t* rp_g,
         const float g = -0.5f * acc * 1.0f;
         v = gin[i] * sc - alpha * g;
         gout[i] = v;
-        if (sc != 1.0f && c >= 0 && comp[i] == i) ex[c] += shift;  // comp is read only then
+        if (sc != 1.0f && ra[q]) ex[c] += shift;
       }
       // the component maxima: one atomic per wave when its lanes share one
       // component (the maximum does not depend on the order)
@@ -483,6 +500,7 @@ __global__ void __launch_bounds__(1024) k_gl_descend_small(const int32_t* rp_g,
         atomicMax(mout + c, m);
       }
     }
+    k3 = k3 == 2 ? 0 : k3 + 1;
     for (int32_t c = threadIdx.x; c < ncomp; c += blockDim.x) mclr[c] = 0;
     __syncthreads();
     float* t = gin;
