@@ -399,6 +399,7 @@ __global__ void __launch_bounds__(1024) k_gl_plan(const int32_t* rp, const int32
 // no global memory.
 constexpr int kSmallDescentN = 4096;
 constexpr int kSmallRows = kSmallDescentN / 1024;  // rows per thread of the fused descent
+constexpr int kHeldEntries = 8;  // leading entries of each row kept in registers
 constexpr size_t kSmallDescentLds = 128 * 1024;
 
 template <bool CSR_IN_LDS>
@@ -441,8 +442,10 @@ __global__ void __launch_bounds__(1024) k_gl_descend_small(const int32_t* rp_g,
   float* gout = G1;
   // each thread's rows (at most kSmallRows of them, n <= kSmallRows * 1024)
   // keep their bounds, component slot and anchor flag in registers
+  // and the first kHeldEntries entries of each row
   int32_t rb[kSmallRows], re[kSmallRows], rc[kSmallRows];
   bool ra[kSmallRows];
+  uint32_t held[kSmallRows][kHeldEntries];
 #pragma unroll
   for (int q = 0; q < kSmallRows; ++q) {
     const int32_t i = q * (int32_t)blockDim.x + (int32_t)threadIdx.x;
@@ -451,6 +454,8 @@ __global__ void __launch_bounds__(1024) k_gl_descend_small(const int32_t* rp_g,
     re[q] = in ? rp[i + 1] : 0;
     rc[q] = in ? cs[i] : -1;
     ra[q] = in && comp[i] == i;
+#pragma unroll
+    for (int t = 0; t < kHeldEntries; ++t) held[q][t] = rb[q] + t < re[q] ? adj[rb[q] + t] : 0u;
   }
   int k3 = 0;  // step mod 3: which maxima buffer is read, written, cleared
   for (int64_t k = 0; k < steps; ++k) {
@@ -466,9 +471,20 @@ __global__ void __launch_bounds__(1024) k_gl_descend_small(const int32_t* rp_g,
       if (i < n) {
         const float sc = (c >= 0 && min_[c] >= thresh) ? down : 1.0f;
         float acc = 0.0f;
-        // four entries' loads in flight; the sum keeps the row's order
-        int32_t e = rb[q];
+        // the held entries' loads all in flight, then four at a time; the
+        // sum keeps the row's order
         const int32_t e1 = re[q];
+        float xh[kHeldEntries];
+#pragma unroll
+        for (int t = 0; t < kHeldEntries; ++t) xh[t] = gin[held[q][t] & kVertexMask];
+#pragma unroll
+        for (int t = 0; t < kHeldEntries; ++t) {
+          if (rb[q] + t < e1) {
+            const float gt = xh[t] * sc;
+            acc += (held[q][t] >> 31) ? -gt : gt;
+          }
+        }
+        int32_t e = rb[q] + kHeldEntries;
         for (; e + 3 < e1; e += 4) {
           const uint32_t a0 = adj[e], a1 = adj[e + 1], a2 = adj[e + 2], a3 = adj[e + 3];
           const float x0 = gin[a0 & kVertexMask], x1 = gin[a1 & kVertexMask];
