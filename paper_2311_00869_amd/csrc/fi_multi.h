@@ -76,11 +76,10 @@ __device__ __forceinline__ bool edge_state(uint64_t S, int j) {
   return ((t < 32 ? lo >> t : hi >> (t - 32)) & 1u) != 0;
 }
 
-
+// Wave-wide OR of a 64-bit value, returned to every lane.
 __device__ __forceinline__ uint64_t wave_or64(uint64_t x) {
   return ((uint64_t)wave_or_u32((uint32_t)(x >> 32)) << 32) | wave_or_u32((uint32_t)x);
 }
-
 
 // Lane k < ne (ne = popcount of mask) gets the lane index of the k-th set
 // bit of mask.
@@ -95,7 +94,7 @@ __device__ __forceinline__ int select_lane(uint64_t mask, int k) {
 }
 
 // ------------------------------------------------------------ W words per vertex
-// The same helpers for passes of 64 W trees.  Word w, bit t of a field is
+// Passes of 64 W trees.  Word w, bit t of a field is
 // tree 64 w + t, and lane t of a wavefront carries trees t, 64 + t, ...  The
 // four fields of a vertex (discoveries at even levels, states, discoveries at
 // odd levels, visits) form one record of 4 W words, field f of vertex v at
