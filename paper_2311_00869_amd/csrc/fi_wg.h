@@ -200,15 +200,22 @@ __device__ __forceinline__ void wg_tree_rdfs(const DevGraph& G, const SweepArgs&
           best = c < best ? c : best;
         }
       }
-      best = wave_min_u64(best);
-      if (best == ~0ull) {  // every neighbour visited: back up
+      // the smallest key wins (the keys of one row's neighbours are
+      // distinct): a 32-bit wave minimum, then the lane that holds it
+      const bool has = best != ~0ull;
+      if (!__ballot(has)) {  // every neighbour visited: back up
         if (top == 0) break;
         --top;
         u = stk[top];
         bu = (uint32_t)(pw[u] & 1);
         continue;
       }
-      const uint32_t a = G.adj[e0 + (int64_t)(best & 0xFFFFFFFFu)];
+      const uint32_t bk = (uint32_t)(best >> 32);
+      const uint32_t kmin = wave_reduce<false>(has ? bk : 0xFFFFFFFFu,
+                                               [](uint32_t x, uint32_t y) { return x < y ? x : y; });
+      const int wl = __builtin_ctzll(__ballot(has && bk == kmin));
+      const uint32_t off = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)best, wl);
+      const uint32_t a = G.adj[e0 + (int64_t)off];
       const int32_t v = (int32_t)(a & kVertexMask);
       bu ^= a >> 31;
       ++top;
@@ -308,20 +315,26 @@ __device__ __forceinline__ void wg_tree_kruskal(const DevGraph& G, const SweepAr
   __syncthreads();
 }
 
-// Tree t with the chosen sampler (paths 1 and 2 of the single-graph sweep).
-template <int NT>
+// Tree t with the chosen sampler (paths 1 and 2 of the single-graph sweep);
+// SMP is the family the kernel is built for (kSamplerRdfs also runs the
+// hybrid, which takes BFS or randomized DFS per tree).
+template <int NT, int SMP>
 __device__ __forceinline__ void wg_tree_sampled(const DevGraph& G, const SweepArgs& A, uint64_t t,
                                                 uint64_t* pw, int32_t* q, int32_t* d,
                                                 WgShared<NT>& sh) {
-  int smp = A.sampler;
-  if (smp == kSamplerHybrid) smp = hybrid_coin(tree_salt(A.seed, t)) ? kSamplerRdfs : kSamplerBfs;
-  if (smp == kSamplerBfs) {
+  if constexpr (SMP == kSamplerBfs) {
     wg_tree<NT>(G, A, t, pw, q, sh);
-    return;
+  } else if constexpr (SMP == kSamplerKruskal) {
+    wg_tree_kruskal<NT>(G, A, t, pw, q, d, sh);
+    wg_finish<NT>(G, A, t, pw, sh);
+  } else {
+    if (A.sampler == kSamplerHybrid && !hybrid_coin(tree_salt(A.seed, t))) {
+      wg_tree<NT>(G, A, t, pw, q, sh);
+      return;
+    }
+    wg_tree_rdfs<NT>(G, A, t, pw, q, sh);
+    wg_finish<NT>(G, A, t, pw, sh);
   }
-  if (smp == kSamplerRdfs) wg_tree_rdfs<NT>(G, A, t, pw, q, sh);
-  else wg_tree_kruskal<NT>(G, A, t, pw, q, d, sh);
-  wg_finish<NT>(G, A, t, pw, sh);
 }
 
 }  // namespace wg

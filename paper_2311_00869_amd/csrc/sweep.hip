@@ -29,7 +29,10 @@ namespace {
 using wg::WgShared;
 using wg::wg_tree_sampled;
 
-template <int NT, bool IN_LDS>
+// SMP: the sampler family the kernel is built for (BFS, Kruskal, or the
+// randomized DFS with the hybrid), so that each sampler's code is compiled
+// and register-allocated on its own.
+template <int NT, bool IN_LDS, int SMP>
 __global__ void __launch_bounds__(NT) k_sweep_wg(DevGraph G, SweepArgs A) {
   __shared__ WgShared<NT> sh;
   extern __shared__ uint64_t dyn[];
@@ -45,7 +48,7 @@ __global__ void __launch_bounds__(NT) k_sweep_wg(DevGraph G, SweepArgs A) {
   }
   int32_t* d = q + G.n;  // Kruskal's hooks (its LDS and slots have room)
   for (uint64_t t = A.t0 + blockIdx.x; t < A.t1; t += gridDim.x)
-    wg_tree_sampled<NT>(G, A, t, pw, q, d, sh);
+    wg_tree_sampled<NT, SMP>(G, A, t, pw, q, d, sh);
 }
 
 // tree words and queue; Kruskal also keeps a hook per vertex
@@ -53,32 +56,43 @@ size_t wg_lds_bytes(int32_t n, int sampler = kSamplerBfs) {
   return (sampler == kSamplerKruskal ? 16 : 12) * (size_t)n;
 }
 
-template <int NT>
-hipError_t launch_wg(fi_graph* g, const SweepArgs& a, int path, hipStream_t s) {
+template <int NT, int SMP>
+hipError_t launch_wg_smp(fi_graph* g, const SweepArgs& a, int path, hipStream_t s) {
   const uint64_t ntrees = a.t1 - a.t0;
   const DevGraph& G = g->dg;
   int grid = g->sched.grid;
   if (path == 1) {
     const size_t lds = wg_lds_bytes(G.n, a.sampler);
-    hipError_t ea = hipFuncSetAttribute((const void*)k_sweep_wg<NT, true>,
+    hipError_t ea = hipFuncSetAttribute((const void*)k_sweep_wg<NT, true, SMP>,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (ea != hipSuccess) return ea;
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_wg<NT, true>, NT, lds);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_wg<NT, true, SMP>, NT, lds);
     if (e != hipSuccess) return e;
     if (per_cu < 1) per_cu = 1;
+    // at most six resident workgroups per CU: on a 1,000-vertex graph every
+    // sampler ran a quarter slower at eight (the limit its registers allow)
+    if (per_cu > 6) per_cu = 6;
     if (grid <= 0) grid = per_cu * g->cu_count;
     grid = (int)std::min<uint64_t>((uint64_t)grid, ntrees);
-    hipLaunchKernelGGL((k_sweep_wg<NT, true>), dim3(grid), dim3(NT), lds, s, G, a);
+    hipLaunchKernelGGL((k_sweep_wg<NT, true, SMP>), dim3(grid), dim3(NT), lds, s, G, a);
   } else {
     SweepArgs b = a;
     b.pw = (uint64_t*)(g->ws + g->L.slots);
     b.slot_stride = g->L.slot_stride;
     if (grid <= 0) grid = 8 * g->cu_count;
     grid = (int)std::min<uint64_t>(std::min<uint64_t>((uint64_t)grid, ntrees), g->L.nslots);
-    hipLaunchKernelGGL((k_sweep_wg<NT, false>), dim3(grid), dim3(NT), 0, s, G, b);
+    hipLaunchKernelGGL((k_sweep_wg<NT, false, SMP>), dim3(grid), dim3(NT), 0, s, G, b);
   }
   return hipGetLastError();
+}
+
+template <int NT>
+hipError_t launch_wg(fi_graph* g, const SweepArgs& a, int path, hipStream_t s) {
+  if (a.sampler == kSamplerKruskal) return launch_wg_smp<NT, kSamplerKruskal>(g, a, path, s);
+  if (a.sampler == kSamplerRdfs || a.sampler == kSamplerHybrid)
+    return launch_wg_smp<NT, kSamplerRdfs>(g, a, path, s);
+  return launch_wg_smp<NT, kSamplerBfs>(g, a, path, s);
 }
 
 int pick_path(fi_graph* g) {
