@@ -530,9 +530,10 @@ def bench_planted(fr, synth, tune, torch, trees=10_000):
 
 
 def bench_samplers(fr, synth, torch):
-    """Trees per second of every sampler (one tree per workgroup) on the
-    1,000-vertex graph and on a 100,000-vertex graph, with the best switch
-    count each reached."""
+    """Trees per second of every sampler on the 1,000-vertex graph and on a
+    100,000-vertex graph, with the best switch count each reached.  Each runs
+    on the library's own choice of path: one tree per workgroup, except BFS
+    on the larger graph, which takes 128 trees per pass."""
     out = {}
     # the small graph's sweep takes well under a millisecond: time ten of them
     for name, g, K, reps in (("n=1,000 m=5,000", synth.config_small(0), 8192, 10),

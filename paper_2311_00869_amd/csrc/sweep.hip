@@ -107,7 +107,10 @@ int pick_path(fi_graph* g) {
   }
   if (g->sched.path != 0) return g->sched.path;
   if (fits) return 1;
-  if (n <= 200000 && g->L.nslots > 0) return 2;
+  // one tree per workgroup costs about m per tree, while 128 trees per pass
+  // cost about their BFS depth: past n + m/2 of about 250,000 the pass wins
+  // (measured at average degrees 4, 10 and 16)
+  if ((int64_t)n + g->dg.m / 2 <= 250000 && g->L.nslots > 0) return 2;
   return 5;
 }
 

@@ -79,3 +79,15 @@ def test_product_path_has_no_oracle_import():
                 text = open(os.path.join(root, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "liboracle" not in text, f
+
+
+def test_default_schedule_crossover(monkeypatch, tmp_path):
+    # one tree per workgroup in LDS, then in workspace slots while n + m/2 stays
+    # at or below 250,000, then 128 trees per pass
+    from paper_2311_00869_amd import tune
+    monkeypatch.setattr(tune, "CACHE", str(tmp_path / "none.json"))
+    assert tune.default_schedule(10000, 100000)["path"] == 1
+    assert tune.default_schedule(100000, 2 * 300000)["path"] == 2   # 100,000 + 150,000
+    assert tune.default_schedule(100000, 2 * 300002)["path"] == 5
+    assert tune.default_schedule(60000, 2 * 480000)["path"] == 5
+    assert tune.default_schedule(16000000, 2 * 64000000)["path"] == 5
