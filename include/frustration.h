@@ -419,7 +419,7 @@ int fi_bcloud_stats(fi_bcloud* c, int64_t* out_trees, int64_t* out_dropped, void
  * (cooperative, any n; fi_tree_state falls back to path 3), 5 = the same
  * with 128 trees at once (two-word fields; a vertex's record is one 64-byte
  * line, so a pass moves about as many lines as a pass of 64; not for batch
- * handles; the default once n + m/2 exceeds 250,000, m undirected edges).  block: threads per workgroup
+ * handles; the default once n + m/2 exceeds 135,000, m undirected edges).  block: threads per workgroup
  * (256, 512 or 1024); grid: workgroups (0 = default); heavy: degree above
  * which a top-down frontier vertex is expanded by several workgroups
  * (path 3, >= 32); batch: trees in flight on path 3 (1 .. 8). */

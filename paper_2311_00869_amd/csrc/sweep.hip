@@ -108,9 +108,9 @@ int pick_path(fi_graph* g) {
   if (g->sched.path != 0) return g->sched.path;
   if (fits) return 1;
   // one tree per workgroup costs about m per tree, while 128 trees per pass
-  // cost about their BFS depth: past n + m/2 of about 250,000 the pass wins
-  // (measured at average degrees 4, 10 and 16)
-  if ((int64_t)n + g->dg.m / 2 <= 250000 && g->L.nslots > 0) return 2;
+  // (on a grid sized to the graph) cost about their BFS depth: past n + m/2 of
+  // about 135,000 the pass wins (measured at average degrees 4, 10 and 16)
+  if ((int64_t)n + g->dg.m / 2 <= 135000 && g->L.nslots > 0) return 2;
   return 5;
 }
 
@@ -124,7 +124,11 @@ hipError_t launch_sweep(fi_graph* g, const SweepArgs& a, hipStream_t s) {
   // gathers the cloud statistics
   if ((path == 4 || path == 5) && a.bits_out) path = 3;
   if (a.vminus || a.eswitch) path = path == 5 ? 5 : 4;  // (BFS only: checked by the caller)
-  const int nt = g->sched.block;
+  // the automatic schedule gives one-tree-per-workgroup sweeps of sparse
+  // graphs (average degree up to 10) 256 threads, denser ones 1,024: measured
+  // up to 1.4 times apart either way
+  const int nt = g->sched.path == 0 && path == 2 ? (g->dg.m <= 5 * (int64_t)g->dg.n ? 256 : 1024)
+                                                 : g->sched.block;
   void* tok = nullptr;
   if (prof_begin(g, s, &tok)) return hipErrorUnknown;
   hipError_t e;

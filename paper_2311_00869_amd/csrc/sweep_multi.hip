@@ -810,7 +810,12 @@ hipError_t launch_mt(fi_graph* g, const MArgs& a, hipStream_t s) {
   if (e != hipSuccess) return e;
   if (per_cu < 1) return hipErrorInvalidConfiguration;
   const int maxg = per_cu * g->cu_count;
-  int grid = g->sched.grid > 0 ? std::min(g->sched.grid, maxg) : maxg;
+  // by default one workgroup per 16,384 of n + m/2, a multiple of 8 (the
+  // XCDs), at least 64: on graphs of 10^5 vertices most of a level is its grid
+  // barriers, and 64 workgroups ran 1.5 to 1.7 times faster than 256
+  const int64_t work = (int64_t)g->dg.n + g->dg.m / 2;
+  const int auto_grid = (int)std::max<int64_t>(64, std::min<int64_t>(maxg, work / 16384) & ~7);
+  int grid = std::min(g->sched.grid > 0 ? g->sched.grid : auto_grid, maxg);
   if (grid > kBarGroup * 512) grid = kBarGroup * 512;
   DevGraph G = g->dg;
   MArgs A = a;

@@ -83,11 +83,13 @@ def test_product_path_has_no_oracle_import():
 
 def test_default_schedule_crossover(monkeypatch, tmp_path):
     # one tree per workgroup in LDS, then in workspace slots while n + m/2 stays
-    # at or below 250,000, then 128 trees per pass
+    # at or below 135,000 (256 threads up to average degree 10), then 128 trees
+    # per pass
     from paper_2311_00869_amd import tune
     monkeypatch.setattr(tune, "CACHE", str(tmp_path / "none.json"))
     assert tune.default_schedule(10000, 100000)["path"] == 1
-    assert tune.default_schedule(100000, 2 * 300000)["path"] == 2   # 100,000 + 150,000
-    assert tune.default_schedule(100000, 2 * 300002)["path"] == 5
+    assert tune.default_schedule(60000, 2 * 150000) == dict(path=2, block=256, grid=0, heavy=512, batch=1)
+    assert tune.default_schedule(30000, 2 * 210000)["block"] == 1024   # 30,000 + 105,000
+    assert tune.default_schedule(30000, 2 * 210002)["path"] == 5
     assert tune.default_schedule(60000, 2 * 480000)["path"] == 5
     assert tune.default_schedule(16000000, 2 * 64000000)["path"] == 5
