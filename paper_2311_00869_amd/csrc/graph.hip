@@ -395,6 +395,11 @@ uint64_t table_size_for(int64_t cloud_capacity) {
   return s;
 }
 
+// root-finding chunks of components up to kRootWide vertices (see
+// build_components)
+constexpr int32_t kRootChunkSmall = 256;
+constexpr int32_t kRootWide = 2097152;
+
 Layout make_layout(int32_t n, int64_t nnz, int64_t cloud_capacity, uint64_t table_size) {
   Layout L{};
   size_t off = 0;
@@ -451,7 +456,7 @@ Layout make_layout(int32_t n, int64_t nnz, int64_t cloud_capacity, uint64_t tabl
   L.cverts = take(4 * nn);
   L.ccount = take(4 * (nn / 2 + 1));
   L.cptr = take(4 * (nn / 2 + 2));
-  L.mtcap = nn / 2 + nn / kRootChunk + 2;
+  L.mtcap = nn / 2 + nn / kRootChunkSmall + 2;
   L.mtasks = take(16 * L.mtcap);
   L.nbigcap = nn / kBigComp + 1;
   L.rootbig = take(8 * 128 * L.nbigcap);
@@ -468,8 +473,12 @@ Layout make_layout(int32_t n, int64_t nnz, int64_t cloud_capacity, uint64_t tabl
 
 // The multi-tree path's component lists and root-finding tasks: every
 // component with an edge gets one task if it has at most kBigComp vertices,
-// else one task per kRootChunk of its vertices and a row of big-component
-// minima.  Also resets the split-row and big-component minima.
+// else one task per chunk of its vertices and a row of big-component minima.
+// A task is one wave's serial scan, and every task of a component ends in
+// the same 64 W minima: components up to kRootWide vertices take chunks of
+// kRootChunkSmall (more waves on the scan), larger ones kRootChunk (fewer
+// atomic minima on those words).  Also resets the split-row and big-component
+// minima.
 int build_components(fi_graph* g, hipStream_t s) {
   const Layout& L = g->L;
   char* ws = g->ws;
@@ -502,8 +511,9 @@ int build_components(fi_graph* g, hipStream_t s) {
       if (cnt[i] <= kBigComp) {
         tasks.push_back(make_int4(ptr[i], ptr[i + 1], -1, 0));
       } else {
-        for (int32_t b = ptr[i]; b < ptr[i + 1]; b += kRootChunk)
-          tasks.push_back(make_int4(b, std::min(ptr[i + 1], b + kRootChunk), nbig, 0));
+        const int32_t chunk = cnt[i] <= kRootWide ? kRootChunkSmall : kRootChunk;
+        for (int32_t b = ptr[i]; b < ptr[i + 1]; b += chunk)
+          tasks.push_back(make_int4(b, std::min(ptr[i + 1], b + chunk), nbig, 0));
         ++nbig;
       }
     }
