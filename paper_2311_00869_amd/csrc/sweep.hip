@@ -114,6 +114,18 @@ int pick_path(fi_graph* g) {
   return 5;
 }
 
+// threads per workgroup of the automatic schedule's one-tree-per-workgroup
+// paths (measured up to 3 times apart).  Path 2: 256 for sparse graphs
+// (average degree up to 10), else 1,024.  Path 1: the tree's LDS bounds the
+// workgroups a CU holds, so the fewer fit, the wider each one (BFS and
+// Kruskal; the randomized DFS keeps most waves idle and takes 256).
+int auto_block(fi_graph* g, int path) {
+  if (path == 2) return g->dg.m <= 5 * (int64_t)g->dg.n ? 256 : 1024;
+  if (path != 1 || g->sampler == kSamplerRdfs || g->sampler == kSamplerHybrid) return 256;
+  const size_t lds = wg_lds_bytes(g->dg.n, g->sampler);
+  return lds <= 24576 ? 256 : lds <= 65536 ? 512 : 1024;
+}
+
 }  // namespace
 
 hipError_t launch_sweep(fi_graph* g, const SweepArgs& a, hipStream_t s) {
@@ -124,11 +136,7 @@ hipError_t launch_sweep(fi_graph* g, const SweepArgs& a, hipStream_t s) {
   // gathers the cloud statistics
   if ((path == 4 || path == 5) && a.bits_out) path = 3;
   if (a.vminus || a.eswitch) path = path == 5 ? 5 : 4;  // (BFS only: checked by the caller)
-  // the automatic schedule gives one-tree-per-workgroup sweeps of sparse
-  // graphs (average degree up to 10) 256 threads, denser ones 1,024: measured
-  // up to 1.4 times apart either way
-  const int nt = g->sched.path == 0 && path == 2 ? (g->dg.m <= 5 * (int64_t)g->dg.n ? 256 : 1024)
-                                                 : g->sched.block;
+  const int nt = g->sched.path == 0 ? auto_block(g, path) : g->sched.block;
   void* tok = nullptr;
   if (prof_begin(g, s, &tok)) return hipErrorUnknown;
   hipError_t e;

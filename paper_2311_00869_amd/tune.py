@@ -40,7 +40,9 @@ def default_schedule(n: int, nnz: int):
     if _key(n, nnz) in cache:
         return dict(cache[_key(n, nnz)])
     if 12 * n + 32768 <= LDS_BYTES:
-        return dict(path=1, block=512, grid=0, heavy=512, batch=1)
+        # the fewer trees' LDS a CU holds, the wider each workgroup
+        block = 256 if 12 * n <= 24576 else 512 if 12 * n <= 65536 else 1024
+        return dict(path=1, block=block, grid=0, heavy=512, batch=1)
     if n + nnz // 4 <= 135_000:  # nnz // 4 = m / 2 (m undirected edges)
         return dict(path=2, block=256 if nnz <= 10 * n else 1024, grid=0, heavy=512, batch=1)
     return dict(path=5, block=1024, grid=0, heavy=512, batch=1)

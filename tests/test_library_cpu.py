@@ -87,7 +87,9 @@ def test_default_schedule_crossover(monkeypatch, tmp_path):
     # per pass
     from paper_2311_00869_amd import tune
     monkeypatch.setattr(tune, "CACHE", str(tmp_path / "none.json"))
-    assert tune.default_schedule(10000, 100000)["path"] == 1
+    assert tune.default_schedule(1000, 10000)["block"] == 256
+    assert tune.default_schedule(3000, 30000)["block"] == 512
+    assert tune.default_schedule(10000, 100000) == dict(path=1, block=1024, grid=0, heavy=512, batch=1)
     assert tune.default_schedule(60000, 2 * 150000) == dict(path=2, block=256, grid=0, heavy=512, batch=1)
     assert tune.default_schedule(30000, 2 * 210000)["block"] == 1024   # 30,000 + 105,000
     assert tune.default_schedule(30000, 2 * 210002)["path"] == 5

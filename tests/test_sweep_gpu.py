@@ -214,11 +214,13 @@ def test_powerlaw_multi_tile_all_paths():
     G.close()
 
 
-@pytest.mark.parametrize("n,m", [(250000, 1000000), (60000, 480000), (40000, 200000), (30000, 100000)])
+@pytest.mark.parametrize("n,m", [(250000, 1000000), (60000, 480000), (40000, 200000), (30000, 100000),
+                                 (8000, 32000), (3000, 15000)])
 def test_automatic_schedule_past_the_crossover(n, m):
     # path 0 takes the 128-tree multi-tree kernel (1,024-thread workgroups, the
     # grid sized to the graph) once n + m/2 exceeds 135,000, else one tree per
-    # workgroup (256 threads on the last, sparse graph); 8 trees leave most of
+    # workgroup (256 threads on the sparse 30,000-vertex graph; the last two
+    # keep the tree in LDS, with 1,024 and 512 threads); 8 trees leave most of
     # the pass's lanes idle
     g = synth.chung_lu(n, m, 2.3, 21, p_pos=0.85)
     K, seed = 8, 5
