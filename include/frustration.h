@@ -410,17 +410,21 @@ int fi_bcloud_stats(fi_bcloud* c, int64_t* out_trees, int64_t* out_dropped, void
 /* ---------------------------------------------------------------- schedule */
 
 /* How a sweep is laid on the GPU.  Every schedule gives bit-identical
- * results; fi_set_schedule only changes speed.  path: 0 = automatic,
- * 1 = one workgroup per tree with the tree state in LDS (n <= 12,000),
- * 2 = one workgroup per tree with the tree state in workspace memory
+ * results; fi_set_schedule only changes speed.  path: 0 = automatic (path 1
+ * when the tree fits LDS, 2 while n + m/2 <= 135,000 with m undirected
+ * edges, else 5; the block is then chosen from the graph's size and the
+ * sampler, the block field is ignored, and a grid of 0 is sized to the
+ * graph), 1 = one workgroup per tree with the tree state in LDS
+ * (n <= 12,000), 2 = one workgroup per tree with the tree state in workspace memory
  * (n <= 1,000,000), 3 = the whole grid on a few trees at a time
  * (persistent cooperative kernel, any n), 4 = the whole grid on 64 trees
  * at once with one bit per tree in each field of a per-vertex record
  * (cooperative, any n; fi_tree_state falls back to path 3), 5 = the same
  * with 128 trees at once (two-word fields; a vertex's record is one 64-byte
  * line, so a pass moves about as many lines as a pass of 64; not for batch
- * handles; the default once n + m/2 exceeds 135,000, m undirected edges).  block: threads per workgroup
- * (256, 512 or 1024); grid: workgroups (0 = default); heavy: degree above
+ * handles).  block: threads per workgroup (256, 512 or 1024); grid:
+ * workgroups (0 = default; on paths 4 and 5 one per 16,384 of n + m/2, a
+ * multiple of 8, at least 64, at most what can be resident); heavy: degree above
  * which a top-down frontier vertex is expanded by several workgroups
  * (path 3, >= 32); batch: trees in flight on path 3 (1 .. 8). */
 typedef struct {
