@@ -63,7 +63,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--trees", type=int, default=1000)
-    ap.add_argument("--workload", choices=["large", "small", "planted"], default="large")
+    ap.add_argument("--workload", choices=["large", "mid", "small", "planted"], default="large")
     ap.add_argument("--path", type=int, default=0, help="schedule path (0 = tuned default)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
@@ -120,6 +120,9 @@ def main():
     if args.workload == "large":
         g = synth.config_large(0)
         wname = "chung-lu n=16,000,000 m=64,000,000 gamma=2.3 p+=0.85"
+    elif args.workload == "mid":
+        g = synth.chung_lu(100000, 500000, 2.3, 0, p_pos=0.85)
+        wname = "chung-lu n=100,000 m=500,000 gamma=2.3 p+=0.85"
     elif args.workload == "planted":
         g = synth.config_planted_powerlaw(0)
         wname = "planted chung-lu n=1,000,000 m=10,000,000 gamma=2.1 flip=0.05"
