@@ -276,3 +276,17 @@ def test_row_class_and_chunk_boundaries_all_paths():
         assert np.array_equal(sw, ref.trees[:, 0]), s
         assert np.array_equal(G.cloud(), ref.cloud), s
     G.close()
+
+
+def test_automatic_grid_several_passes_and_a_ragged_one():
+    # a 100,000-vertex graph takes 128 trees per pass on a grid of 64
+    # workgroups: 200 trees are one full pass and one of 72
+    g = synth.chung_lu(100000, 500000, 2.3, 0, p_pos=0.85)
+    K, seed = 200, 17
+    ref = oracle.sweep(g, seed, 0, K, checks=False)
+    G = _graph(g, cap=256)
+    sw = G.sweep_range(0, K, seed, tree_switches=True).cpu().numpy().astype(np.uint64)
+    assert np.array_equal(sw, ref.trees[:, 0])
+    assert np.array_equal(G.cloud(), ref.cloud)
+    assert G.min_frustration() == ref.best
+    G.close()
