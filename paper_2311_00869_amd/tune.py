@@ -25,9 +25,11 @@ def candidates(n: int, nnz: int):
     for b in (256, 512, 1024):
         for batch in (1, 4, 8):
             out.append(dict(path=3, block=b, grid=0, heavy=512, batch=batch))
+    # the multi-tree paths also at fixed small grids (0 = sized to the graph)
     for b in (512, 1024):
-        out.append(dict(path=4, block=b, grid=0, heavy=512, batch=1))
-        out.append(dict(path=5, block=b, grid=0, heavy=512, batch=1))
+        for grid in (0, 64, 128):
+            out.append(dict(path=4, block=b, grid=grid, heavy=512, batch=1))
+            out.append(dict(path=5, block=b, grid=grid, heavy=512, batch=1))
     return out
 
 

@@ -95,3 +95,12 @@ def test_default_schedule_crossover(monkeypatch, tmp_path):
     assert tune.default_schedule(30000, 2 * 210002)["path"] == 5
     assert tune.default_schedule(60000, 2 * 480000)["path"] == 5
     assert tune.default_schedule(16000000, 2 * 64000000)["path"] == 5
+
+
+def test_autotune_candidates_cover_every_path_and_multi_grids():
+    from paper_2311_00869_amd import tune
+    small = tune.candidates(5000, 50000)
+    assert {c["path"] for c in small} == {1, 2, 3, 4, 5}
+    assert {c["grid"] for c in small if c["path"] == 5} == {0, 64, 128}
+    large = tune.candidates(16000000, 128000000)
+    assert {c["path"] for c in large} == {3, 4, 5}

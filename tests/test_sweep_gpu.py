@@ -290,3 +290,20 @@ def test_automatic_grid_several_passes_and_a_ragged_one():
     assert np.array_equal(G.cloud(), ref.cloud)
     assert G.min_frustration() == ref.best
     G.close()
+
+
+def test_autotune_keeps_a_schedule_with_oracle_results():
+    # every candidate runs (each gives the same trees); the kept one still does
+    from paper_2311_00869_amd import tune
+    g = synth.chung_lu(20000, 100000, 2.3, 4, p_pos=0.85)
+    K, seed = 40, 23
+    ref = oracle.sweep(g, seed, 0, K, checks=False)
+    G = _graph(g, cap=64)
+    best, results = tune.autotune(G, trees=8, save=False)
+    assert len(results) == len(tune.candidates(G.n, G.nnz))
+    assert G.get_schedule()["path"] == best["path"]
+    G.cloud_reset()
+    sw = G.sweep_range(0, K, seed, tree_switches=True).cpu().numpy().astype(np.uint64)
+    assert np.array_equal(sw, ref.trees[:, 0]), best
+    assert np.array_equal(G.cloud(), ref.cloud), best
+    G.close()
