@@ -60,6 +60,9 @@ def lib():
             L.orc_tree_salt.restype = c.c_uint64
             L.orc_vertex_key.argtypes = [c.c_uint64, c.c_int32]
             L.orc_vertex_key.restype = c.c_uint64
+            L.orc_vertex_keys.argtypes = [c.c_uint64, c.c_int64, c.c_int64, c.c_int32,
+                                          np.ctypeslib.ndpointer(np.uint32, flags="C")]
+            L.orc_vertex_keys.restype = None
             L.orc_tree.argtypes = [c.c_int32, i32p, i32p, i8p, c.c_uint64, c.c_int64, c.c_int,
                                    i32p, i32p, i8p]
             L.orc_tree.restype = c.c_int
@@ -111,6 +114,13 @@ def tree_salt(seed: int, t: int) -> int:
 
 def vertex_key(salt: int, u: int) -> int:
     return int(lib().orc_vertex_key(salt, u))
+
+
+def vertex_keys(seed: int, t0: int, t1: int, n: int):
+    """Keys of vertices 0..n-1 in trees t0..t1-1: uint32 [t1 - t0, n]."""
+    out = np.empty((t1 - t0, n), np.uint32)
+    lib().orc_vertex_keys(seed & (2**64 - 1), t0, t1, n, out)
+    return out
 
 
 def splitmix(x: int) -> int:
@@ -209,3 +219,28 @@ def sweep(g, seed: int, t0: int, t1: int, checks: bool = True, paper_strings: bo
     if rc != 0:
         raise RuntimeError(f"oracle sweep failed: {ERRORS.get(rc, rc)}")
     return SweepResult(trees, cloud[: size.value].copy(), (int(best[0]), int(best[1])))
+
+
+def cloud_from_trees(trees, t0: int = 0):
+    """Alg. alg-index's cloud rebuilt from per-tree rows (switches, key_hi,
+    key_lo) of consecutive trees t0, t0+1, ...: a new key enters with C = 1,
+    S = s and its tree as first tree; a key seen before gets C + 1 and must
+    carry the same S (Eq. eq-cloud).  Returns (cloud rows key_hi, key_lo,
+    freq, switches, first_tree sorted by key, (min S, first tree reaching
+    it)).  Used to join sweeps of disjoint tree ranges run in separate
+    processes."""
+    cloud = {}
+    best = None
+    for i, (s, hi, lo) in enumerate(np.asarray(trees, np.uint64).tolist()):
+        t = t0 + i
+        e = cloud.get((hi, lo))
+        if e is None:
+            cloud[(hi, lo)] = [1, s, t]
+        else:
+            if e[1] != s:
+                raise RuntimeError(f"tree {t}: key seen before with {e[1]} switches, now {s}")
+            e[0] += 1
+        if best is None or s < best[0]:
+            best = (s, t)
+    rows = [[hi, lo, f, s, ft] for (hi, lo), (f, s, ft) in sorted(cloud.items())]
+    return np.array(rows, np.uint64).reshape(-1, 5), best

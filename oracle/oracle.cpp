@@ -518,6 +518,15 @@ int32_t orc_components(int32_t n, const int32_t* row_ptr, const int32_t* col, in
 uint64_t orc_tree_salt(uint64_t seed, int64_t t) { return tree_salt(seed, t); }
 uint64_t orc_vertex_key(uint64_t salt, int32_t u) { return vertex_key(salt, u); }
 
+// Keys of vertices 0 .. n-1 in trees t0 .. t1-1 of the sweep with this
+// seed, tree by tree: out[(t - t0) * n + u].
+void orc_vertex_keys(uint64_t seed, int64_t t0, int64_t t1, int32_t n, uint32_t* out) {
+    for (int64_t t = t0; t < t1; ++t) {
+        const uint64_t salt = tree_salt(seed, t);
+        for (int32_t u = 0; u < n; ++u) out[(t - t0) * n + u] = (uint32_t)vertex_key(salt, u);
+    }
+}
+
 // Tree t of the sweep with this seed: level, parent (-1 at roots), parent
 // edge sign, and the propagated +1/-1 state.
 int orc_tree(int32_t n, const int32_t* row_ptr, const int32_t* col, const int8_t* sign,

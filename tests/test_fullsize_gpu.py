@@ -38,14 +38,28 @@ def _check(G, gold, schedule):
 
 
 def test_large_graph_bench_configuration():
+    # trees 0..129: one full 128-tree pass of the benchmark's kernel (both
+    # tree words of every lane, the 256-workgroup grid and the 1,024-vertex
+    # root chunks of this size) plus two trees of the next pass.  All 130
+    # states are distinct, so the cloud's entries (keyed, with their first
+    # tree) give every tree's key
     gold = _golden("large")
+    assert gold["t1"] - gold["t0"] >= 130
     g = synth.config_large(0)
     assert (g.n, g.nnz) == (gold["n"], gold["nnz"])
     G = fr.Graph(g.row_ptr, g.col, g.sign, cloud_capacity=256)
-    _check(G, gold, tune.default_schedule(G.n, G.nnz))
-    _check(G, gold, dict(path=3, block=512, heavy=256, batch=1))
+    sched = tune.default_schedule(G.n, G.nnz)
+    assert sched["path"] == 5
+    _check(G, gold, sched)
+    assert G.get_schedule()["path"] == 5
+    _check(G, gold, dict(path=5, block=1024, grid=128))
     _check(G, gold, dict(path=4, block=1024))
-    _check(G, gold, dict(path=5, block=1024))
+    _check(G, gold, dict(path=3, block=512, heavy=256, batch=1))
+    cloud = np.array(gold["cloud"], dtype=np.uint64)
+    trees = np.array(gold["trees"], dtype=np.uint64)
+    assert len(cloud) == len(trees)
+    ft = cloud[:, 4].astype(np.int64) - gold["t0"]
+    assert np.array_equal(cloud[:, 0:2], trees[ft, 1:3])
     # every tree's frustrated edges, recounted by the exact counter from its state
     words, s0 = G.tree_state(gold["seed"], gold["t0"])
     got = int(G.count(torch.from_numpy(words.view(np.int64))).item())
@@ -144,6 +158,34 @@ def test_planted_powerlaw_all_paths():
     assert int(G.count(torch.from_numpy(w.view(np.int64))).item()) == gold["planted_flipped"]
     G.set_schedule(path=4, block=1024)
     _check_bounded(G, gold, fmax=3, chunk=3)
+    G.close()
+
+
+def test_planted_ten_thousand_trees_in_one_sweep():
+    # the planted configuration as benchmarked: 10^4 trees in one sweep on the
+    # automatic schedule.  Its first 32 trees against the oracle, and over all
+    # of them what Alg. alg-index and Eq. eq-cloud fix: the counts add up to
+    # K, each key carries one switch count (the readout checks every slot),
+    # each state's S is the switch count of its first tree, and the minimum
+    # is the smallest switch count at its first tree
+    gold = _golden("planted")
+    g = synth.config_planted_powerlaw(0)
+    K = 10_000
+    G = fr.Graph(g.row_ptr, g.col, g.sign, cloud_capacity=K)
+    G.set_schedule(**tune.default_schedule(G.n, G.nnz))
+    sw = G.sweep_range(0, K, gold["seed"], tree_switches=True).cpu().numpy().astype(np.uint64)
+    want = np.array(gold["trees"], dtype=np.uint64)
+    assert np.array_equal(sw[gold["t0"]:gold["t1"]], want[:, 0])
+    cloud = G.cloud()
+    assert 1 <= len(cloud) == G.cloud_size() <= K
+    assert int(cloud[:, 2].sum()) == K
+    assert np.array_equal(cloud[:, 3], sw[cloud[:, 4].astype(np.int64)])
+    assert len(np.unique(cloud[:, 4])) == len(cloud)
+    s, t = G.min_frustration()
+    assert s == int(sw.min()) and t == int(np.argmax(sw == sw.min()))
+    # every tree's switch count is one its state carries: the trees whose
+    # switch count no first tree has are repeats of some state with it
+    assert set(sw.tolist()) == set(cloud[:, 3].tolist())
     G.close()
 
 

@@ -76,6 +76,55 @@ def test_vertex_key_is_a_bijection():
     assert np.argsort(a).tolist() != np.argsort(b).tolist()
 
 
+def test_tree_keys_are_uniform_and_independent():
+    # The sampler shuffles each vertex's neighbours "with a uniformly
+    # distributed random seed" (Section "Tree-Sampling techniques"): over
+    # 10^5 trees of one 200-vertex component, (a) every vertex is the root
+    # (the minimum-key vertex) equally often, (b) each vertex's rank among
+    # the keys is uniform, (c) a pair's key order is a fair coin, (d)
+    # consecutive trees share a root with probability 1/n, and the roots of
+    # consecutive trees are independent.  Thresholds are p > 1e-4 (chi2) and
+    # 5 standard deviations (counts).
+    from scipy.stats import chi2
+    n, T, seed = 200, 100_000, 2024
+    roots = np.empty(T, np.int64)
+    ranks = np.zeros((4, n), np.int64)
+    pair_lt = np.zeros(6, np.int64)
+    pairs = [(0, 1), (0, 199), (5, 6), (17, 123), (64, 65), (198, 199)]
+    for t0 in range(0, T, 10_000):
+        k = oracle.vertex_keys(seed, t0, t0 + 10_000, n).astype(np.int64)
+        roots[t0:t0 + 10_000] = np.argmin(k, axis=1)
+        order = np.argsort(k, axis=1)
+        rk = np.empty_like(order)
+        np.put_along_axis(rk, order, np.arange(n)[None, :], axis=1)
+        for j, u in enumerate((0, 1, 100, 199)):
+            ranks[j] += np.bincount(rk[:, u], minlength=n)
+        for j, (u, v) in enumerate(pairs):
+            pair_lt[j] += int(np.count_nonzero(k[:, u] < k[:, v]))
+    cnt = np.bincount(roots, minlength=n)
+    stat = ((cnt - T / n) ** 2 / (T / n)).sum()
+    assert chi2.sf(stat, n - 1) > 1e-4, stat
+    for j in range(4):
+        stat = ((ranks[j] - T / n) ** 2 / (T / n)).sum()
+        assert chi2.sf(stat, n - 1) > 1e-4, (j, stat)
+    sd = (T * 0.25) ** 0.5
+    assert np.all(np.abs(pair_lt - T / 2) < 5 * sd), pair_lt
+    same = int(np.count_nonzero(roots[1:] == roots[:-1]))
+    p = 1.0 / n
+    assert abs(same - (T - 1) * p) < 5 * ((T - 1) * p * (1 - p)) ** 0.5, same
+    # joint law of consecutive roots, in 20 bins of 10 vertices each
+    a, b = roots[:-1] // 10, roots[1:] // 10
+    joint = np.bincount(a * 20 + b, minlength=400)
+    exp = (T - 1) / 400
+    stat = ((joint - exp) ** 2 / exp).sum()
+    assert chi2.sf(stat, 399) > 1e-4, stat
+    # and the roots the tree builder itself picks are these minima
+    g = synth.erdos_renyi_connected(n, 600, 0.8, 1)
+    for t in (0, 1, 77, 99_999):
+        level, _, _ = oracle.tree(g, seed, t)
+        assert int(np.flatnonzero(level == 0)[0]) == roots[t]
+
+
 # ------------------------------------------------------------ Figure fig-Balance
 
 def _fig():
@@ -360,3 +409,16 @@ def test_validate_accepts_generated():
     for g in [synth.config_small(0), synth.random_small(30, 60, 2), synth.figure_graph([1] * 5),
               synth.isolated_vertices(5)]:
         assert oracle.validate(g) == 0
+
+
+def test_cloud_joined_from_tree_rows_equals_the_sweep_cloud():
+    # the full-size goldens sweep one tree per process and join the rows:
+    # the join must give the std::map cloud of one sweep over the same trees
+    # (repeated states on K_7, all distinct on the 1,000-vertex graph)
+    for g, K, t0 in [(synth.complete_graph(7, -1), 60, 3), (synth.config_small(0), 40, 10)]:
+        whole = oracle.sweep(g, 9, t0, t0 + K, checks=True)
+        rows = np.concatenate([oracle.sweep(g, 9, t, t + 1, checks=False).trees
+                               for t in range(t0, t0 + K)])
+        cloud, best = oracle.cloud_from_trees(rows, t0)
+        assert np.array_equal(cloud, whole.cloud)
+        assert best == whole.best
