@@ -35,9 +35,11 @@
  *     workspace per graph (size from fi_graph_workspace_size), keeps it alive
  *     until fi_graph_destroy, and frees it afterwards.  Input CSR buffers are
  *     read only during fi_graph_create (the workspace keeps what it needs).
- *   - Errors found by kernels (a full cloud, a BFS deeper than 4094 levels,
- *     a key collision) are sticky on the handle and returned by the next
- *     blocking call (fi_graph_status, fi_min_frustration, fi_cloud_read).
+ *   - Errors found by kernels (a full cloud, a key collision) are sticky
+ *     on the handle and returned by the next blocking call
+ *     (fi_graph_status, fi_min_frustration, fi_cloud_read).
+ *   - Every spanning forest is reachable: BFS trees of any depth (a path
+ *     graph, a long grid) run on every schedule.
  *   - Results depend only on (graph, seed, tree indices), never on the
  *     schedule, the stream or how a tree range is split into calls.
  */
@@ -62,7 +64,7 @@ enum {
   FI_EUNSORTED = -7,   /* a row whose columns are not increasing */
   FI_ECAPACITY = -8,   /* more distinct balanced states than the cloud capacity */
   FI_EDEVICE = -9,     /* a HIP runtime call failed */
-  FI_EDEPTH = -10,     /* a BFS tree deeper than 4094 levels */
+  FI_EDEPTH = -10,     /* a BFS tree deeper than 2^31 - 2 levels (cannot occur: depth < n) */
   FI_ECOLLISION = -11, /* two different states met under one 64-bit key half */
   FI_EWORKSPACE = -12, /* workspace missing, too small or misaligned (256 B) */
   FI_EORDER = -13      /* a bounded-cloud merge whose trees do not follow the last one's */
@@ -182,7 +184,10 @@ int fi_tree_state(fi_graph* g, uint64_t seed, int64_t t, uint64_t* d_bits_out,
 /* Exact frustration count (the switch count of Alg. alg-index line "s =
  * edge signs difference count"): for B states given as bitmaps d_bits
  * uint64[B][ceil(n/64)] (set bit = vertex state -1), d_counts[b] = number of
- * undirected edges (u, v) with sign(u,v) * s_u * s_v = -1. */
+ * undirected edges (u, v) with sign(u,v) * s_u * s_v = -1.  Groups of 64
+ * states are transposed to one word per vertex and counted in one pass over
+ * the edge list.  Uses the graph's workspace: calls on one handle must not
+ * overlap. */
 int fi_count(fi_graph* g, const uint64_t* d_bits, int32_t B, uint64_t* d_counts, void* stream);
 
 /* ---------------------------------------------------------------- graphL */
@@ -239,7 +244,9 @@ int fi_graphl_scales(fi_graph* g, const void* d_aux, int32_t R, int32_t* d_out, 
 /* Alg. alg-gradient's final loop: theta = +1 where Gamma >= 0 else -1, then
  * the exact frustration count of every restart: d_counts uint64[R].
  * d_bits_out (uint64[R][ceil(n/64)], set = -1) receives the rounded states
- * if not NULL. */
+ * if not NULL.  Gamma is read once; all R restarts are counted in one pass
+ * over the edge list.  Uses the graph's workspace: calls on one handle must
+ * not overlap. */
 int fi_round_count(fi_graph* g, const float* d_gamma, int32_t R, uint64_t* d_counts,
                    uint64_t* d_bits_out, void* stream);
 
@@ -439,7 +446,8 @@ int fi_set_schedule(fi_graph* g, const fi_schedule* s);
 int fi_get_schedule(fi_graph* g, fi_schedule* out);
 
 /* Kernel timing with HIP events recorded on the launch stream around every
- * launch of the sweep kernel (0) and the count kernel (1).  Enable, run,
+ * launch of the sweep kernel (0) and of the exact count (1; in
+ * fi_round_count the rounding and the count).  Enable, run,
  * then read: fi_prof_read blocks and returns the summed milliseconds and the
  * number of launches since the last enable. */
 int fi_prof_enable(fi_graph* g, int on);

@@ -610,10 +610,6 @@ __global__ void __launch_bounds__(NT) k_batch_multi(BatchMArgs B) {
       __syncthreads();
       // the other parity's flag was last read before the barrier above
       if (tid == 0) s_any[pp] = 0;
-      if (L > kMaxLevel) {
-        if (tid == 0) atomicOr((unsigned long long*)(G.ctl + C_ERR), (unsigned long long)E_DEPTH);
-        break;
-      }
       uint64_t cnt = 0, deg = 0, fin = 0;
       for (int32_t w = wave; w < nw; w += NW) {
         const uint64_t bits = S.unf[w];

@@ -55,17 +55,19 @@ __device__ __forceinline__ uint32_t vkey_of(KeyMix k, uint32_t h) { return (h ^ 
 __device__ __forceinline__ uint32_t vkey(KeyMix k, uint32_t u) { return vkey_of(k, fmix32(u)); }
 
 // ----------------------------------------------------------------- tree words
-// One 64-bit word per vertex carries the BFS level (12 bits), the parent's
+// One 64-bit word per vertex carries the BFS level (31 bits), the parent's
 // key (32 bits) and the vertex's state bit (1 = state -1):
-//   level << 52 | key << 20 | bit.
+//   level << 33 | key << 1 | bit.
 // Unsigned order is (level, parent key), so an atomic minimum keeps the
 // earliest level and, within it, the minimum-key parent; words of earlier
-// levels are never overwritten.  All ones = not reached yet.
+// levels are never overwritten.  All ones = not reached yet.  A BFS level is
+// below n < 2^31, so every depth fits below that sentinel (a spanning forest
+// of any graph, Definition def-FundamentalCycle and its corollary).
 constexpr uint64_t kUnvisited = ~0ull;
-constexpr uint32_t kMaxLevel = 4094;
+constexpr uint32_t kMaxLevel = 0x7FFFFFFEu;
 
 __device__ __forceinline__ uint64_t tree_word(uint32_t level, uint32_t key, uint32_t bit) {
-  return ((uint64_t)level << 52) | ((uint64_t)key << 20) | bit;
+  return ((uint64_t)level << 33) | ((uint64_t)key << 1) | bit;
 }
 // Candidate word used to pick a component's root or a parent while its id
 // is still needed: key, then id, then a spare low bit.
@@ -225,7 +227,9 @@ void prof_end(fi_graph* g, hipStream_t s, void* token, int kernel);
 hipError_t launch_sweep(fi_graph* g, const SweepArgs& a, hipStream_t s);
 hipError_t launch_grid(fi_graph* g, const SweepArgs& a, hipStream_t s);
 hipError_t launch_multi(fi_graph* g, const SweepArgs& a, int words, hipStream_t s);
-hipError_t launch_count(const DevGraph& dg, const uint64_t* bits, int32_t B, uint64_t* counts,
+// exact count of up to 64 states given as one word per vertex (bit b = the
+// vertex's state in state b, set = -1): counts[b] += frustrated edges
+hipError_t launch_count(const DevGraph& dg, const uint64_t* st, int32_t nstates, uint64_t* counts,
                         hipStream_t s);
 hipError_t graphl_setup(fi_graph* g, hipStream_t s);
 

@@ -354,24 +354,82 @@ __global__ void k_cloud_load(DevGraph G, const uint64_t* e, int64_t count) {
 }
 
 // ------------------------------------------------------------ exact count
-// Frustrated edges of B states: the y-th row of blocks counts state y.
+// Frustrated edges of up to 64 states in one pass over the edge list.  st[v]
+// holds vertex v's state in every state of the group (bit b = state b,
+// set = -1).  Each lane takes one edge at a time: x = st[u] ^ st[v] ^ (all
+// ones for a negative edge) has bit b set when the edge is frustrated in
+// state b, and goes into 8 bit-sliced counter planes (a ripple-carry add of
+// one bit per state).  Every 255 edges the planes are read out by ballots
+// into per-state totals, lane b keeping state b's, and one LDS atomic per
+// wave and one global atomic per block and state finish the sum.
 constexpr int kCountBlock = 256;
+constexpr int kCountPlanes = 8;
 __global__ void __launch_bounds__(kCountBlock) k_count(const uint2* edges, int64_t m,
-                                                     const uint64_t* bits, int32_t nwords,
+                                                     const uint64_t* st, int nstates,
                                                      uint64_t* counts) {
-  __shared__ uint64_t s_tmp[kCountBlock / 64];
-  const uint64_t* b = bits + (size_t)blockIdx.y * nwords;
-  uint64_t c = 0;
-  for (int64_t e = blockIdx.x * (int64_t)kCountBlock + threadIdx.x; e < m;
-       e += (int64_t)gridDim.x * kCountBlock) {
-    uint2 uv = edges[e];
-    uint32_t v = uv.y & kVertexMask;
-    uint32_t bu = (uint32_t)(b[uv.x >> 6] >> (uv.x & 63)) & 1u;
-    uint32_t bv = (uint32_t)(b[v >> 6] >> (v & 63)) & 1u;
-    c += (uv.y >> 31) ^ bu ^ bv;
+  __shared__ uint64_t s_acc[64];
+  const int lane = lane_id();
+  if (threadIdx.x < 64) s_acc[threadIdx.x] = 0;
+  __syncthreads();
+  const uint64_t smask = nstates >= 64 ? ~0ull : ((1ull << nstates) - 1);
+  uint64_t c[kCountPlanes];
+#pragma unroll
+  for (int p = 0; p < kCountPlanes; ++p) c[p] = 0;
+  uint64_t mine = 0;
+  int it = 0;
+  auto flush = [&]() {
+    for (int b = 0; b < nstates; ++b) {
+      uint32_t tot = 0;
+#pragma unroll
+      for (int p = 0; p < kCountPlanes; ++p)
+        tot += (uint32_t)__popcll(__ballot((c[p] >> b) & 1)) << p;
+      if (lane == b) mine += tot;
+    }
+#pragma unroll
+    for (int p = 0; p < kCountPlanes; ++p) c[p] = 0;
+  };
+  // the loop bound is uniform over the block, so every wave reaches each flush
+  for (int64_t e0 = (int64_t)blockIdx.x * kCountBlock; e0 < m;
+       e0 += (int64_t)gridDim.x * kCountBlock) {
+    const int64_t e = e0 + threadIdx.x;
+    uint64_t x = 0;
+    if (e < m) {
+      const uint2 uv = edges[e];
+      const uint64_t neg = (uv.y >> 31) ? ~0ull : 0ull;
+      x = (st[uv.x] ^ st[uv.y & kVertexMask] ^ neg) & smask;
+    }
+#pragma unroll
+    for (int p = 0; p < kCountPlanes; ++p) {
+      const uint64_t carry = c[p] & x;
+      c[p] ^= x;
+      x = carry;
+    }
+    if (++it == 255) {
+      flush();
+      it = 0;
+    }
   }
-  uint64_t tot = block_sum_u64<kCountBlock>(c, s_tmp);
-  if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long*)(counts + blockIdx.y), (unsigned long long)tot);
+  flush();
+  if (mine) atomicAdd((unsigned long long*)&s_acc[lane], (unsigned long long)mine);
+  __syncthreads();
+  if (threadIdx.x < nstates && s_acc[threadIdx.x])
+    atomicAdd((unsigned long long*)(counts + threadIdx.x), (unsigned long long)s_acc[threadIdx.x]);
+}
+
+// States given as bitmaps (state b: words bits[b * nwords + i], vertex v is
+// bit v % 64 of word v / 64) turned into one word per vertex: bit b of st[v]
+// is v's bit in state b, for b < nstates (<= 64).  The 64 lanes of a wave
+// share each bitmap word, so every word is read once.
+__global__ void k_states_by_vertex(const uint64_t* bits, int32_t nwords, int32_t n, int nstates,
+                                   uint64_t* st) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = v >> 6;
+    const int sh = (int)(v & 63);
+    uint64_t w = 0;
+    for (int b = 0; b < nstates; ++b) w |= ((bits[(size_t)b * nwords + i] >> sh) & 1ull) << b;
+    st[v] = w;
+  }
 }
 
 int err_from_bits(uint64_t bits) {
@@ -556,7 +614,7 @@ const char* fi_strerror(int code) {
     case FI_EUNSORTED: return "row columns not increasing";
     case FI_ECAPACITY: return "frustration cloud capacity exceeded";
     case FI_EDEVICE: return "HIP runtime error";
-    case FI_EDEPTH: return "BFS tree deeper than 4094 levels";
+    case FI_EDEPTH: return "BFS tree deeper than the level field holds (2^31 - 2 levels)";
     case FI_ECOLLISION: return "state key collision";
     case FI_EWORKSPACE: return "workspace missing, too small or misaligned";
     case FI_EORDER: return "bounded-cloud merge out of tree order";
@@ -832,9 +890,19 @@ int fi_count(fi_graph* g, const uint64_t* d_bits, int32_t B, uint64_t* d_counts,
   if (!g || g->is_batch || B < 0 || (B > 0 && (!d_bits || !d_counts))) return FI_EINVAL;
   if (B == 0) return FI_OK;
   hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, d_counts, (int64_t)B, 0ull);
-  hipError_t e = launch_count(g->dg, d_bits, B, d_counts, s);
-  return e == hipSuccess ? FI_OK : FI_EDEVICE;
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(B, 256)), dim3(256), 0, s, d_counts, (int64_t)B, 0ull);
+  // groups of 64 states: transposed to one word per vertex in the scratch
+  // region (8 (n + 64) bytes), then one pass over the edge list per group
+  uint64_t* st = (uint64_t*)(g->ws + g->L.scratch);
+  const int32_t n = g->dg.n;
+  for (int32_t b0 = 0; b0 < B && n > 0; b0 += 64) {
+    const int nb = std::min<int32_t>(64, B - b0);
+    hipLaunchKernelGGL(k_states_by_vertex, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s,
+                       d_bits + (size_t)b0 * g->dg.nwords, g->dg.nwords, n, nb, st);
+    hipError_t e = launch_count(g->dg, st, nb, d_counts + b0, s);
+    if (e != hipSuccess) return FI_EDEVICE;
+  }
+  return hipGetLastError() == hipSuccess ? FI_OK : FI_EDEVICE;
 }
 
 int fi_set_schedule(fi_graph* g, const fi_schedule* sc) {
@@ -914,12 +982,13 @@ void prof_end(fi_graph* g, hipStream_t s, void* token, int kernel) {
   delete pe;
 }
 
-hipError_t launch_count(const DevGraph& dg, const uint64_t* bits, int32_t B, uint64_t* counts,
+hipError_t launch_count(const DevGraph& dg, const uint64_t* st, int32_t nstates, uint64_t* counts,
                         hipStream_t s) {
-  if (dg.m == 0) return hipSuccess;
-  int gx = grid_for(dg.m, kCountBlock, 2048);
-  hipLaunchKernelGGL(k_count, dim3(gx, B), dim3(kCountBlock), 0, s, dg.edges, dg.m, bits,
-                     dg.nwords, counts);
+  if (dg.m == 0 || nstates <= 0) return hipSuccess;
+  // a few edges per lane: one counter readout per lane at most at the 16M-vertex graph's 64M edges
+  const int gx = grid_for(dg.m, kCountBlock, 4096);
+  hipLaunchKernelGGL(k_count, dim3(gx), dim3(kCountBlock), 0, s, dg.edges, dg.m, st, (int)nstates,
+                     counts);
   return hipGetLastError();
 }
 

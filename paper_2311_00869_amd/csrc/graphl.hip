@@ -555,21 +555,52 @@ __global__ void k_fill_u32(uint32_t* p, int64_t len, uint32_t v) {
     p[i] = v;
 }
 
-// theta = +1 where Gamma >= 0, else -1; bit set = -1.  One wave per
-// (64-vertex word, restart).
-__global__ void k_gl_round(const float* gamma, int32_t n, int32_t nwords, int R, uint64_t* bits) {
+// theta = +1 where Gamma >= 0, else -1 (NaN: -1), as one word per vertex:
+// bit r of st[v] is set when restart r rounds v to -1.  When R divides 64 a
+// wave reads 64 consecutive floats of Gamma (64 / R whole vertices) and one
+// ballot gives all their words, so Gamma streams through once, coalesced;
+// otherwise each thread reads its own vertex's R floats.
+__global__ void k_gl_round(const float* gamma, int32_t n, int R, uint64_t* st) {
+  const int lane = lane_id();
+  const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
+  if (64 % R == 0) {
+    const int64_t total = (int64_t)n * R;
+    const int per = 64 / R;
+    const uint64_t rmask = R == 64 ? ~0ull : ((1ull << R) - 1);
+    // wave-uniform chunks of 64 elements (vertex-major, restart-minor)
+    for (int64_t e0 = (tid >> 6) << 6; e0 < total; e0 += (nthr >> 6) << 6) {
+      const int64_t e = e0 + lane;
+      const bool neg = e < total && !(gamma[e] >= 0.0f);
+      const uint64_t W = __ballot(neg);
+      const int64_t v = e0 / R + lane;
+      if (lane < per && v < n) st[v] = (W >> (lane * R)) & rmask;
+    }
+  } else {
+    for (int64_t v = tid; v < n; v += nthr) {
+      uint64_t w = 0;
+      for (int r = 0; r < R; ++r) w |= (uint64_t)!(gamma[(size_t)v * R + r] >= 0.0f) << r;
+      st[v] = w;
+    }
+  }
+}
+
+// The rounded states as bitmaps, restart by restart: bits[r * nwords + i],
+// vertex v is bit v % 64 of word v / 64 (set = -1).  One wave per word: each
+// lane reads its vertex's word once, R ballots transpose the 64 x R bits.
+__global__ void k_gl_unpack(const uint64_t* st, int32_t n, int32_t nwords, int R, uint64_t* bits) {
   const int lane = lane_id();
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  const int64_t total = (int64_t)nwords * R;
-  for (int64_t k = wave; k < total; k += nwaves) {
-    const int r = (int)(k / nwords);
-    const int64_t i = k - (int64_t)r * nwords;
+  for (int64_t i = wave; i < nwords; i += nwaves) {
     const int64_t v = i * 64 + lane;
-    bool neg = false;
-    if (v < n) neg = !(gamma[(size_t)v * R + r] >= 0.0f);
-    const uint64_t W = __ballot(neg);
-    if (lane == 0) bits[(size_t)r * nwords + i] = W;
+    const uint64_t x = v < n ? st[v] : 0ull;
+    uint64_t mine = 0;
+    for (int r = 0; r < R; ++r) {
+      const uint64_t W = __ballot((x >> r) & 1);
+      if (lane == r) mine = W;
+    }
+    if (lane < R) bits[(size_t)lane * nwords + i] = mine;
   }
 }
 
@@ -577,6 +608,10 @@ __global__ void k_zero_u64(uint64_t* p, int64_t len) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len;
        i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0;
+}
+
+int grid_for_gl(int64_t work, int block) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>((work + block - 1) / block, 65536));
 }
 
 int rows_grid(int32_t n, int R) {
@@ -775,16 +810,19 @@ int fi_round_count(fi_graph* g, const float* d_gamma, int32_t R, uint64_t* d_cou
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, d_counts, (int64_t)R);
   if (g->dg.n == 0) return hipGetLastError() == hipSuccess ? FI_OK : FI_EDEVICE;
   if (!d_gamma) return FI_EINVAL;
-  // rounded states go to the caller's buffer, or to the tree-word scratch
-  // (R * ceil(n/64) words <= 8n bytes for R <= 64)
-  uint64_t* bits = d_bits_out ? d_bits_out : (uint64_t*)(g->ws + g->L.scratch);
-  const int64_t waves = (int64_t)g->dg.nwords * R;
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((waves * 64 + 255) / 256, 65536));
-  hipLaunchKernelGGL(k_gl_round, dim3(grid), dim3(256), 0, s, d_gamma, g->dg.n, g->dg.nwords,
-                     (int)R, bits);
   void* tok = nullptr;
   if (prof_begin(g, s, &tok)) return FI_EDEVICE;
-  hipError_t e = launch_count(g->dg, bits, R, d_counts, s);
+  // rounded states, one word per vertex, in the scratch region (8 (n + 64) bytes)
+  uint64_t* st = (uint64_t*)(g->ws + g->L.scratch);
+  const int64_t work = 64 % R == 0 ? (int64_t)g->dg.n * R : (int64_t)g->dg.n;
+  hipLaunchKernelGGL(k_gl_round, dim3(grid_for_gl(work, 256)), dim3(256), 0, s, d_gamma, g->dg.n,
+                     (int)R, st);
+  if (d_bits_out) {
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((g->dg.nwords + 3) / 4, 65536));
+    hipLaunchKernelGGL(k_gl_unpack, dim3(grid), dim3(256), 0, s, st, g->dg.n, g->dg.nwords, (int)R,
+                       d_bits_out);
+  }
+  hipError_t e = launch_count(g->dg, st, R, d_counts, s);
   prof_end(g, s, tok, 1);
   return e == hipSuccess ? FI_OK : FI_EDEVICE;
 }

@@ -379,10 +379,6 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
       }
       __syncthreads();
       if (!uni(sh.active)) break;
-      if (L > (uint32_t)kMaxLevel) {
-        if (stid == 0) atomicOr((unsigned long long*)(G.ctl + C_ERR), (unsigned long long)E_DEPTH);
-        break;
-      }
       const bool push = uni(sh.mode) == 1;
       // counters and tickets of level L + 1 start from zero
       if (rank == 0 && tid < 8) {

@@ -173,3 +173,20 @@ def test_batch_validation_codes():
     assert B.lib.fi_sweep(B.handle, 4, 1, None) == -1
     assert B.lib.fi_min_frustration(B.handle, None, None, None) == -1
     B.close()
+
+
+def test_deep_graphs_in_a_batch():
+    # BFS trees of several thousand levels (a path, a ladder, a grid) beside
+    # small graphs, on both batch schedules
+    from test_sweep_gpu import _deep_graphs
+    graphs = list(_deep_graphs().values()) + [synth.config_small(0), synth.cycle_graph(33, (0, 5, 9))]
+    K, seed = 40, 8
+    want_min, want_distinct = _expect(graphs, K, seed)
+    B = fr.BatchGraph(graphs, cloud_capacity_per_graph=K)
+    for path, block in ((1, 256), (1, 1024), (4, 512), (0, 1024)):
+        B.set_schedule(block=block, path=path)
+        mn, ds = B.sweep(K, seed)
+        assert np.array_equal(mn.cpu().numpy(), want_min), (path, block)
+        assert np.array_equal(ds.cpu().numpy(), want_distinct), (path, block)
+    B.status()
+    B.close()

@@ -216,3 +216,25 @@ def test_fused_small_descent_policy():
     b, sb = G.graphl_descend(gamma0, steps, alpha, rescale_log2=9)
     assert np.array_equal(_true(b, sb), true)
     G.close()
+
+
+@pytest.mark.parametrize("R", [1, 3, 32, 48, 64])
+def test_round_count_every_restart_width(R):
+    # rounding reads Gamma vertex by vertex and counts all restarts in one pass
+    # over the edge list: every width (dividing 64 or not), zeros of both
+    # signs, NaN, several count blocks and a ragged tail
+    g = synth.chung_lu(5001, 40000, 2.3, 8, p_pos=0.8)
+    G = fr.Graph(g.row_ptr, g.col, g.sign, cloud_capacity=16)
+    gamma = torch.from_numpy(synth.graphl_init(g.n, R, 11)).cuda()
+    gamma[:7] = 0.0
+    gamma[7:13] = -0.0
+    gamma[13, 0] = float("nan")
+    counts, bits = G.round_count(gamma, return_bits=True)
+    theta = ogl.round_states(gamma.cpu().numpy())
+    assert counts.cpu().numpy().tolist() == ogl.frustration(g, theta).tolist()
+    want = np.zeros((R, G.nwords), np.uint64)
+    for r in range(R):
+        idx = np.flatnonzero(theta[:, r] < 0)
+        np.bitwise_or.at(want[r], idx // 64, np.left_shift(np.uint64(1), (idx % 64).astype(np.uint64)))
+    assert np.array_equal(bits.cpu().numpy().view(np.uint64).reshape(R, G.nwords), want)
+    G.close()

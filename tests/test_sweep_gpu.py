@@ -132,11 +132,13 @@ def test_capacity_error_is_reported():
     G.close()
 
 
-def test_exact_count_matches_oracle():
+@pytest.mark.parametrize("B", [1, 7, 64, 70])
+def test_exact_count_matches_oracle(B):
+    # groups of 64 states share one pass over the edge list: one state, a
+    # partial group, a full one, and a full one plus a partial one
     g = synth.chung_lu(5000, 40000, 2.3, 3, p_pos=0.8)
     G = _graph(g)
-    rng = np.random.default_rng(0)
-    B = 7
+    rng = np.random.default_rng(B)
     states = np.where(rng.random((B, g.n)) < 0.5, 1, -1).astype(np.int8)
     words = np.zeros((B, G.nwords), np.uint64)
     for b in range(B):
@@ -306,4 +308,58 @@ def test_autotune_keeps_a_schedule_with_oracle_results():
     sw = G.sweep_range(0, K, seed, tree_switches=True).cpu().numpy().astype(np.uint64)
     assert np.array_equal(sw, ref.trees[:, 0]), best
     assert np.array_equal(G.cloud(), ref.cloud), best
+    G.close()
+
+
+def _deep_graphs():
+    """Graphs whose BFS trees are thousands of levels deep: a 10,000-vertex
+    path and a 2 x 5,000 ladder (5,001 fundamental cycles), both with shuffled
+    vertex ids, and a 120 x 120 grid; mixed signs."""
+    rng = np.random.default_rng(3)
+    out = {}
+    n = 10000
+    perm = rng.permutation(n)
+    out["path10000"] = synth.csr_from_edges(n, perm[:-1], perm[1:],
+                                            np.where(rng.random(n - 1) < 0.7, 1, -1))
+    L = 5000
+    perm = rng.permutation(2 * L)
+    a = np.arange(L)
+    us = np.concatenate([a[:-1], a[:-1] + L, a])
+    vs = np.concatenate([a[1:], a[1:] + L, a + L])
+    out["ladder2x5000"] = synth.csr_from_edges(2 * L, perm[us], perm[vs],
+                                               np.where(rng.random(us.size) < 0.8, 1, -1))
+    k = 120
+    idx = np.arange(k * k).reshape(k, k)
+    us = np.concatenate([idx[:, :-1].ravel(), idx[:-1, :].ravel()])
+    vs = np.concatenate([idx[:, 1:].ravel(), idx[1:, :].ravel()])
+    out["grid120"] = synth.csr_from_edges(k * k, us, vs, np.where(rng.random(us.size) < 0.6, 1, -1))
+    return out
+
+
+@pytest.mark.parametrize("name", ["path10000", "ladder2x5000", "grid120"])
+def test_deep_trees_every_schedule(name):
+    # BFS trees deeper than any fixed level field of a few bits: every
+    # schedule, the automatic one included, matches the oracle
+    g = _deep_graphs()[name]
+    K, seed = 70, 41
+    ref = oracle.sweep(g, seed, 0, K, checks=True)
+    G = _graph(g, cap=128)
+    for s in [dict(path=0, block=256), dict(path=1, block=256), dict(path=1, block=1024),
+              dict(path=2, block=256), dict(path=3, block=256, batch=4),
+              dict(path=3, block=1024, batch=1), dict(path=4, block=1024, grid=16),
+              dict(path=5, block=1024, grid=16), dict(path=5, block=512)]:
+        if not _sched_ok(g, s):
+            continue
+        G.set_schedule(**s)
+        G.cloud_reset()
+        sw = G.sweep_range(0, K, seed, tree_switches=True).cpu().numpy().astype(np.uint64)
+        assert np.array_equal(sw, ref.trees[:, 0]), (name, s)
+        assert np.array_equal(G.cloud(), ref.cloud), (name, s)
+        assert G.min_frustration() == ref.best, (name, s)
+        G.status()
+    # one tree's canonical state through fi_tree_state
+    words, s0 = G.tree_state(seed, 5)
+    _, _, state = oracle.tree(g, seed, 5)
+    assert np.array_equal(words, oracle.canonical_words(g, state))
+    assert s0 == int(ref.trees[5, 0])
     G.close()
