@@ -26,13 +26,26 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
-def algorithmic_bytes_per_tree(n: int, nnz: int) -> int:
-    """Bytes one tree must move at minimum in this design: row offsets (4 per
-    vertex) and the packed adjacency (4 per CSR entry) once for the BFS, the
-    upper-triangle edge list (8 per undirected edge) once for the count, and
-    one 8-byte tree word written and read back per vertex."""
-    m = nnz // 2
-    return 4 * (n + 1) + 4 * nnz + 8 * m + 16 * n
+def model_bytes(n: int, nnz: int, trees: int, trees_per_pass: int) -> dict:
+    """Algorithmic HBM bytes of a sweep (the per-tree model of the hot path).
+
+    One tree, unbatched: two passes over the CSR (row offsets, 4-byte column
+    and 1-byte sign per entry; one pass builds the BFS tree, one counts the
+    frustrated edges), an 8-byte level/parent word written and read back per
+    vertex, and the n-bit state:  B_tree = 2 (4 (n+1) + 5 nnz) + 16 n + n/8.
+    Batched: trees that share a pass share its two CSR passes, so a launch of
+    K trees in passes of P trees moves ceil(K / P) CSR terms plus K per-tree
+    terms."""
+    csr = 2 * (4 * (n + 1) + 5 * nnz)
+    per_tree = 16 * n + n // 8
+    passes = -(-trees // max(trees_per_pass, 1))
+    return {"csr_bytes_per_pass": csr, "bytes_per_tree": per_tree, "passes": passes,
+            "trees_per_pass": trees_per_pass,
+            "bytes_per_launch": passes * csr + trees * per_tree,
+            "unbatched_bytes_per_launch": trees * (csr + per_tree)}
+
+
+TREES_PER_PASS = {1: 1, 2: 1, 3: 1, 4: 64, 5: 128}
 
 
 def kernel_source_sha() -> str:
@@ -72,7 +85,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graphl", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--cpu-trees", type=int, default=2)
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="oracle worker processes for the all-cores CPU figures "
+                         "(0 = min(16, os.cpu_count()))")
+    ap.add_argument("--cpu-runs", type=int, default=3, help="runs per CPU figure (median)")
+    ap.add_argument("--cpu-batch-runs", type=int, default=1,
+                    help="runs of the 256-graph CPU figure of the uneven batch")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch leg")
     ap.add_argument("--no-planted", action="store_true", help="skip the 10^4-tree planted leg")
     ap.add_argument("--no-bounded", action="store_true",
@@ -107,6 +125,13 @@ def main():
     from paper_2311_00869_amd import frustration as fr
     from paper_2311_00869_amd import synth
     from paper_2311_00869_amd import tune
+
+    # the oracle's worker processes are spawned before anything touches the GPU
+    pool = None
+    workers = args.cpu_workers or min(16, os.cpu_count() or 1)
+    if not args.no_cpu_baseline:
+        import multiprocessing as mp
+        pool = mp.get_context("spawn").Pool(workers)
 
     batch_graphs = None
     if not args.no_batch:
@@ -161,8 +186,8 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     best = None
-    for s in range(args.steps):
-        best = step(s)
+    for _ in range(args.steps):
+        best = step(0)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     kern_ms, launches = G.prof_read(0)
@@ -172,18 +197,28 @@ def main():
     print(f"# {args.steps} steps x {T} trees in {elapsed:.3f}s; min switches {best}, "
           f"{states} states in the last cloud", file=sys.stderr, flush=True)
 
-    bpt = algorithmic_bytes_per_tree(G.n, G.nnz)
+    path_used = G.get_schedule()["path"]
+    if path_used == 0:
+        path_used = 5 if G.n + G.m // 2 > 135000 else 2
+    mb = model_bytes(G.n, G.nnz, T, TREES_PER_PASS.get(path_used, 1))
     avg_launch_s = kern_ms / 1e3 / max(launches, 1)
-    achieved = bpt * T / avg_launch_s / 1e9
+    achieved = mb["bytes_per_launch"] / avg_launch_s / 1e9
     traffic = load_traffic(args.workload)
     roofline = {
-        "kernel": {3: "k_sweep_grid", 4: "k_sweep_multi", 5: "k_sweep_multi"}.get(
-            G.get_schedule()["path"], "k_sweep_wg"),
+        "kernel": {3: "k_sweep_grid", 4: "k_sweep_multi", 5: "k_sweep_multi"}.get(path_used,
+                                                                                 "k_sweep_wg"),
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": None if traffic is None else traffic["bytes_per_launch"],
-        "algorithmic_bytes_per_launch": bpt * T, "avg_launch_ms": round(avg_launch_s * 1e3, 3),
-        "launches": launches,
+        "traffic_raw": None if traffic is None else traffic.get("raw_bytes_per_launch"),
+        "traffic_GBps": None if traffic is None else round(
+            traffic["bytes_per_launch"] / avg_launch_s / 1e9, 1),
+        "traffic_raw_GBps": None if traffic is None or "raw_bytes_per_launch" not in traffic
+        else round(traffic["raw_bytes_per_launch"] / avg_launch_s / 1e9, 1),
+        "algorithmic_bytes_per_launch": mb["bytes_per_launch"],
+        "model": mb,
+        "model_unbatched_GBps": round(mb["unbatched_bytes_per_launch"] / avg_launch_s / 1e9, 1),
+        "avg_launch_ms": round(avg_launch_s * 1e3, 3), "launches": launches,
     }
 
     sched_used = G.get_schedule()
@@ -217,9 +252,16 @@ def main():
     if not args.no_samplers:
         extra["samplers"] = bench_samplers(fr, synth, torch)
 
-    cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(g, args.cpu_trees)
+        extra["small"] = bench_small(fr, synth, tune, torch)
+
+    cpu = None
+    if pool is not None:
+        try:
+            cpu = cpu_baseline(pool, workers, g, wname, args.cpu_runs, args.cpu_batch_runs)
+        finally:
+            pool.close()
+            pool.join()
 
     out = {
         "metric": "spanning trees/sec + GB/s vs HBM peak (16M-vertex graph); graphL steps/sec",
@@ -234,7 +276,7 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": wname, "trees_per_step": T, "seed": "step index",
+        "config": {"workload": wname, "trees_per_step": T, "seed": 0,
                    "schedule": sched_used},
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -256,9 +298,9 @@ def bench_bounded(fr, torch, G, T, steps, unbounded_best, fmax=100, chunk=250):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     best = None
-    for s in range(steps):
+    for _ in range(steps):
         C.reset()
-        G.sweep_bounded(C, 0, T, s, chunk=chunk)
+        G.sweep_bounded(C, 0, T, 0, chunk=chunk)
         best = C.min_frustration()
     el = time.perf_counter() - t0
     held = C.size()
@@ -267,7 +309,7 @@ def bench_bounded(fr, torch, G, T, steps, unbounded_best, fmax=100, chunk=250):
     ev = []
     for a in range(0, T, chunk):
         b = min(T, a + chunk)
-        G.sweep_range(a, b, steps - 1)
+        G.sweep_range(a, b, 0)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         C.merge(G, a, b)
@@ -427,12 +469,16 @@ def _counter_per_dispatch(path, counter):
 
 
 def summarize_traffic(fetch_csv, write_csv, args):
-    """HBM bytes per launch of the sweep kernel: FETCH_SIZE and WRITE_SIZE (KiB)
-    of its dispatches, each scaled by what the same counter reads for the copy
-    probe (copy_probe_mib MiB read and as many written)."""
+    """HBM bytes per launch of the sweep kernel from two rocprofv3 counter
+    collections.  FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are sums of
+    the L2's memory requests by size (32-, 64- and 128-byte reads, 64-byte
+    and other writes); `raw` is what they read.  Each is also scaled by what
+    the same counter reads for the copy probe (copy_probe_mib MiB read and as
+    many written by one elementwise kernel), which gives the calibrated
+    `bytes_per_launch`."""
     out = {"workload": args.workload, "kernel_sha": kernel_source_sha(),
            "copy_probe_mib": args.copy_probe_mib}
-    total = 0.0
+    total = raw = 0.0
     for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         per = _counter_per_dispatch(path, name)
         copies = [v for k, v in per.values() if "elementwise" in k.lower()]
@@ -441,11 +487,14 @@ def summarize_traffic(fetch_csv, write_csv, args):
             raise SystemExit(f"{path}: no copy probe or no sweep dispatch for {name}")
         probe_kib = max(copies)
         scale = (args.copy_probe_mib << 20) / probe_kib  # bytes per counted KiB
-        per_launch = sum(sweeps) / len(sweeps) * scale
+        kib = sum(sweeps) / len(sweeps)
         out[name] = {"probe_kib": probe_kib, "bytes_per_counted_kib": scale,
-                     "sweep_dispatches": len(sweeps), "bytes_per_launch": per_launch}
-        total += per_launch
+                     "sweep_dispatches": len(sweeps), "kib_per_launch": kib,
+                     "raw_bytes_per_launch": kib * 1024, "bytes_per_launch": kib * scale}
+        total += kib * scale
+        raw += kib * 1024
     out["bytes_per_launch"] = total
+    out["raw_bytes_per_launch"] = raw
     dst = os.path.join(ROOT, "profiles", f"traffic_sweep_{args.workload}.json")
     with open(dst, "w") as f:
         json.dump(out, f, indent=1)
@@ -561,16 +610,191 @@ def bench_samplers(fr, synth, torch):
     return out
 
 
-def cpu_baseline(g, trees):
-    """The CPU oracle, untuned and single-threaded, on `trees` trees of the same
-    graph (trees/s)."""
-    import oracle
+def bench_small(fr, synth, tune, torch, trees=1000, reps=20):
+    """The 1,000-vertex graph, K = 1,000 trees, seed 0: one launch for all
+    trees on the automatic schedule (one tree per workgroup, persistent
+    workgroups) against the plain per-tree path (one launch per tree)."""
+    g = synth.config_small(0)
+    G = fr.Graph(g.row_ptr, g.col, g.sign, cloud_capacity=trees)
+    G.set_schedule(**tune.default_schedule(G.n, G.nnz))
+    G.sweep(trees, 1)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        G.cloud_reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        G.sweep(trees, 0)
+        best = G.min_frustration()
+        times.append(time.perf_counter() - t0)
+    G.cloud_reset()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    oracle.sweep(g, 0, 0, trees, checks=False)
-    el = time.perf_counter() - t0
-    return {"value": round(trees / el, 5), "unit": "trees/s", "cores": 1, "kind": "oracle",
-            "sample": f"trees 0..{trees - 1} of the same graph, seed 0, single thread, "
-                      f"{el:.1f}s"}
+    for t in range(trees):
+        G.sweep_range(t, t + 1, 0)
+    plain_best = G.min_frustration()
+    plain = time.perf_counter() - t0
+    assert plain_best == best
+    out = {"workload": "path+uniform n=1,000 m=5,000 p+=0.8, K=1,000 trees, seed 0",
+           "trees_per_s": round(trees / sorted(times)[len(times) // 2], 1),
+           "plain_per_tree_trees_per_s": round(trees / plain, 1),
+           "schedule": G.get_schedule(), "min_switches": best[0], "distinct_states": G.cloud_size()}
+    G.close()
+    return out
+
+
+# ---------------------------------------------------------------- CPU oracle
+# The oracle as it stands (single-threaded per call), timed on this host's
+# cores: one process per tree for the all-cores figures.  Graphs reach the
+# worker processes as .npy files in shared memory, mapped read-only.
+
+_WGRAPHS = {}
+
+
+def _w_graph(spec):
+    g = _WGRAPHS.get(spec)
+    if g is None:
+        import numpy as np
+        from paper_2311_00869_amd import synth
+        prefix, n = spec
+        g = synth.SignedCSR(n=n, row_ptr=np.load(prefix + "_rp.npy", mmap_mode="r"),
+                            col=np.load(prefix + "_col.npy", mmap_mode="r"),
+                            sign=np.load(prefix + "_sign.npy", mmap_mode="r"))
+        _WGRAPHS.clear()
+        _WGRAPHS[spec] = g
+    return g
+
+
+def _w_touch(spec):
+    _w_graph(spec)
+    return 0
+
+
+def _w_sweep(job):
+    spec, seed, t0, t1 = job
+    import oracle
+    g = _w_graph(spec)
+    t = time.perf_counter()
+    oracle.sweep(g, seed, t0, t1, checks=False)
+    return time.perf_counter() - t
+
+
+def _w_batch_graph(job):
+    """Make graph gi of the uneven batch and save it for the timed runs."""
+    from paper_2311_00869_amd import synth
+    gi, d = job
+    g = synth.config_batch(4096, 0, indices=[gi])[0]
+    return _shm_write(g, os.path.join(d, f"b{gi}")), g.nnz // 2
+
+
+def _shm_write(g, prefix):
+    import numpy as np
+    np.save(prefix + "_rp.npy", np.ascontiguousarray(g.row_ptr))
+    np.save(prefix + "_col.npy", np.ascontiguousarray(g.col))
+    np.save(prefix + "_sign.npy", np.ascontiguousarray(g.sign))
+    return (prefix, int(g.n))
+
+
+def cpu_baseline(pool, workers, g, wname, runs=3, batch_runs=1):
+    """CPU oracle figures, each the median of `runs` runs:
+    - the main graph: one tree per run in this process (single thread), and
+      `workers` trees per run in as many processes (all cores);
+    - the 1,000-vertex graph: all 1,000 trees, single thread;
+    - the planted 1M-vertex graph: trees 0..31 on all cores, extrapolated
+      linearly to 10^4 trees;
+    - the uneven batch: 256 of its 4,096 graphs (every 16th) x 64 trees on all
+      cores, scaled to the whole batch by edge count;
+    - graphL on the 1,000-vertex graph: 32 restarts x 500 float64 steps,
+      rounding and the exact count, single thread."""
+    import shutil
+    import statistics
+    import tempfile
+
+    import numpy as np
+    import oracle
+    from oracle import graphl as ogl
+    from paper_2311_00869_amd import synth
+
+    med = statistics.median
+    d = tempfile.mkdtemp(prefix="fi_oracle_", dir="/dev/shm" if os.path.isdir("/dev/shm") else None)
+    out = {}
+    try:
+        spec = _shm_write(g, os.path.join(d, "main"))
+        single = []
+        for r in range(runs):
+            t0 = time.perf_counter()
+            oracle.sweep(g, 0, r, r + 1, checks=False)
+            single.append(time.perf_counter() - t0)
+        pool.map(_w_touch, [spec] * (2 * workers), chunksize=1)  # map the graph
+        allc = []
+        for r in range(runs):
+            jobs = [(spec, 0, workers * r + i, workers * r + i + 1) for i in range(workers)]
+            t0 = time.perf_counter()
+            pool.map(_w_sweep, jobs, chunksize=1)
+            allc.append(time.perf_counter() - t0)
+        st, ac = med(single), med(allc)
+        out = {"value": round(workers / ac, 5), "unit": "trees/s", "cores": workers,
+               "kind": "oracle",
+               "sample": f"{wname}: {workers} trees (one process per tree) per run, seed 0, "
+                         f"median of {runs} runs ({ac:.1f}s); single thread: one tree per run, "
+                         f"median of {runs} ({st:.1f}s per tree)",
+               "cpu_count": os.cpu_count(),
+               "single_thread": {"value": round(1.0 / st, 5), "unit": "trees/s", "cores": 1},
+               "runs": runs, "configs": {}}
+        cfg = out["configs"]
+        # the 1,000-vertex graph, all 1,000 trees
+        small = synth.config_small(0)
+        ts = []
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            oracle.sweep(small, 0, 0, 1000, checks=False)
+            ts.append(time.perf_counter() - t0)
+        cfg["small_1000_trees"] = {"seconds": round(med(ts), 3),
+                                   "trees_per_s": round(1000 / med(ts), 1), "cores": 1}
+        # planted: trees 0..31, all cores
+        pspec = _shm_write(synth.config_planted_powerlaw(0), os.path.join(d, "planted"))
+        pool.map(_w_touch, [pspec] * (2 * workers), chunksize=1)
+        tp = []
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            pool.map(_w_sweep, [(pspec, 0, t, t + 1) for t in range(32)], chunksize=1)
+            tp.append(time.perf_counter() - t0)
+        cfg["planted_trees_0_31"] = {
+            "seconds": round(med(tp), 3), "trees_per_s": round(32 / med(tp), 3), "cores": workers,
+            "extrapolated_seconds_10000_trees": round(med(tp) * 10000 / 32, 1)}
+        # the uneven batch: 256 sampled graphs x 64 trees
+        made = pool.map(_w_batch_graph, [(gi, d) for gi in range(0, 4096, 16)], chunksize=1)
+        specs = [m[0] for m in made]
+        edges_sample = sum(m[1] for m in made)
+        shapes = synth.config_batch_shapes(4096, 0)
+        edges_all = int(shapes[1].sum())
+        tb, tsum = [], []
+        for _ in range(batch_runs):
+            t0 = time.perf_counter()
+            per = pool.map(_w_sweep, [(sp, 0, 0, 64) for sp in specs], chunksize=1)
+            tb.append(time.perf_counter() - t0)
+            tsum.append(sum(per))
+        scale = edges_all / edges_sample
+        cfg["batch_256_of_4096_graphs_64_trees"] = {
+            "seconds": round(med(tb), 3), "cores": workers, "runs": batch_runs,
+            "single_thread_seconds": round(med(tsum), 3),
+            "extrapolated_seconds_4096_graphs": round(med(tb) * scale, 1),
+            "extrapolated_trees_per_s": round(4096 * 64 / (med(tb) * scale), 1),
+            "edge_scale": round(scale, 3)}
+        # graphL, float64: 32 restarts x 500 steps, then rounding and the count
+        gamma0 = synth.graphl_init(small.n, 32, 0)
+        tg = []
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            fin = ogl.descent(small, gamma0, 500, 0.001)
+            ogl.frustration(small, ogl.round_states(fin))
+            tg.append(time.perf_counter() - t0)
+        cfg["graphl_small_32x500_float64"] = {
+            "seconds": round(med(tg), 3), "steps_per_s": round(500 / med(tg), 1),
+            "restart_steps_per_s": round(500 * 32 / med(tg), 1), "cores": 1}
+    finally:
+        shutil.rmtree(d, ignore_errors=True)
+    return out
 
 
 if __name__ == "__main__":
