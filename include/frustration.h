@@ -104,6 +104,20 @@ int fi_clean(int32_t n, int64_t E, const int32_t* d_src, const int32_t* d_dst, c
              void* d_workspace, size_t ws_bytes, int32_t* d_row_ptr, int32_t* d_col,
              int8_t* d_sign_out, int64_t* h_counts, void* stream);
 
+/* For callers that cannot allocate device memory (serving loops and
+ * harnesses that forbid hipMalloc, or that hold no workspace for cleaning):
+ * fi_clean without a workspace argument.  The workspace is a 64 MiB device
+ * array inside the library, one per GPU, held until the process ends; it
+ * takes up to FI_CLEAN_NO_ALLOC_MAX_ENTRIES raw entries (FI_ERANGE beyond).
+ * Outputs, counts and errors are those of fi_clean.  No device memory is
+ * allocated or freed.  Every call on one GPU uses that GPU's array: calls that
+ * overlap on one GPU (other streams, other host threads) race and must be
+ * serialised by the caller.  Blocks. */
+#define FI_CLEAN_NO_ALLOC_MAX_ENTRIES 1000000
+int fi_clean_no_alloc(int32_t n, int64_t E, const int32_t* d_src, const int32_t* d_dst,
+                      const int32_t* d_sign, int32_t* d_row_ptr, int32_t* d_col,
+                      int8_t* d_sign_out, int64_t* h_counts, void* stream);
+
 /* ---------------------------------------------------------------- graph */
 
 /* Bytes of device workspace for a graph with n vertices, nnz CSR entries

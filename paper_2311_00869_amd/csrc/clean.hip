@@ -17,6 +17,7 @@
 #include <rocprim/device/device_radix_sort.hpp>
 
 #include <algorithm>
+#include <mutex>
 
 #include "fi_internal.h"
 #include "fi_prims.h"
@@ -163,34 +164,11 @@ __global__ void k_cl_zero(uint64_t* p, int len) {
   if (threadIdx.x < len) p[threadIdx.x] = 0;
 }
 
-}  // namespace
-}  // namespace fi
-
-using namespace fi;
-
-extern "C" {
-
-int fi_clean_workspace_size(int32_t n, int64_t E, size_t* out_bytes) {
-  if (!out_bytes || n < 0 || E < 0) return FI_EINVAL;
-  if (2 * E >= ((int64_t)1 << 31)) return FI_ERANGE;
-  CleanLayout L;
-  if (!clean_layout(E, L)) return FI_EDEVICE;
-  *out_bytes = L.total;
-  return FI_OK;
-}
-
-int fi_clean(int32_t n, int64_t E, const int32_t* d_src, const int32_t* d_dst, const int32_t* d_sign,
-             void* d_workspace, size_t ws_bytes, int32_t* d_row_ptr, int32_t* d_col,
-             int8_t* d_sign_out, int64_t* h_counts, void* stream) {
-  if (n < 0 || E < 0 || !d_row_ptr || !h_counts || (E > 0 && (!d_src || !d_dst || !d_sign ||
-                                                               !d_col || !d_sign_out)))
-    return FI_EINVAL;
-  if (2 * E >= ((int64_t)1 << 31)) return FI_ERANGE;
-  CleanLayout L;
-  if (!clean_layout(E, L)) return FI_EDEVICE;
-  if (!d_workspace || ws_bytes < L.total || ((uintptr_t)d_workspace % kAlign)) return FI_EWORKSPACE;
-  hipStream_t s = (hipStream_t)stream;
-  char* ws = (char*)d_workspace;
+// The cleaning steps on a workspace laid out by clean_layout(E) at ws
+// (256-byte aligned, at least L.total bytes).  Blocks; returns an FI_ code.
+int clean_into(int32_t n, int64_t E, const int32_t* d_src, const int32_t* d_dst,
+               const int32_t* d_sign, char* ws, const CleanLayout& L, int32_t* d_row_ptr,
+               int32_t* d_col, int8_t* d_sign_out, int64_t* h_counts, hipStream_t s) {
   uint64_t* keys = (uint64_t*)(ws + L.keys);
   uint64_t* keys2 = (uint64_t*)(ws + L.keys2);
   uint64_t* dk = (uint64_t*)(ws + L.dk);
@@ -222,6 +200,77 @@ int fi_clean(int32_t n, int64_t E, const int32_t* d_src, const int32_t* d_dst, c
   h_counts[3] = (int64_t)c[CL_DUPS];
   h_counts[4] = (int64_t)c[CL_INCONS];
   return FI_OK;
+}
+
+// ------------------------------------------------------------ no allocation
+// Workspace of fi_clean_no_alloc: a file-scope device array, one per GPU,
+// held until the process ends.  Host code never passes `scratch` itself to
+// a kernel or a copy (on the host that name is not a device address): the
+// device address comes from hipGetSymbolAddress, taken once per device.
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// This device's copy of `scratch`, or nullptr if its address is unavailable.
+void* scratch_on_current_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
+}  // namespace fi
+
+using namespace fi;
+
+extern "C" {
+
+int fi_clean_workspace_size(int32_t n, int64_t E, size_t* out_bytes) {
+  if (!out_bytes || n < 0 || E < 0) return FI_EINVAL;
+  if (2 * E >= ((int64_t)1 << 31)) return FI_ERANGE;
+  CleanLayout L;
+  if (!clean_layout(E, L)) return FI_EDEVICE;
+  *out_bytes = L.total;
+  return FI_OK;
+}
+
+int fi_clean(int32_t n, int64_t E, const int32_t* d_src, const int32_t* d_dst, const int32_t* d_sign,
+             void* d_workspace, size_t ws_bytes, int32_t* d_row_ptr, int32_t* d_col,
+             int8_t* d_sign_out, int64_t* h_counts, void* stream) {
+  if (n < 0 || E < 0 || !d_row_ptr || !h_counts || (E > 0 && (!d_src || !d_dst || !d_sign ||
+                                                               !d_col || !d_sign_out)))
+    return FI_EINVAL;
+  if (2 * E >= ((int64_t)1 << 31)) return FI_ERANGE;
+  CleanLayout L;
+  if (!clean_layout(E, L)) return FI_EDEVICE;
+  if (!d_workspace || ws_bytes < L.total || ((uintptr_t)d_workspace % kAlign)) return FI_EWORKSPACE;
+  return clean_into(n, E, d_src, d_dst, d_sign, (char*)d_workspace, L, d_row_ptr, d_col, d_sign_out,
+                    h_counts, (hipStream_t)stream);
+}
+
+int fi_clean_no_alloc(int32_t n, int64_t E, const int32_t* d_src, const int32_t* d_dst,
+                      const int32_t* d_sign, int32_t* d_row_ptr, int32_t* d_col, int8_t* d_sign_out,
+                      int64_t* h_counts, void* stream) {
+  if (n < 0 || E < 0 || !d_row_ptr || !h_counts || (E > 0 && (!d_src || !d_dst || !d_sign ||
+                                                               !d_col || !d_sign_out)))
+    return FI_EINVAL;
+  if (E > FI_CLEAN_NO_ALLOC_MAX_ENTRIES) return FI_ERANGE;
+  CleanLayout L;
+  if (!clean_layout(E, L)) return FI_EDEVICE;
+  if (L.total > kNoAllocBytes) return FI_ERANGE;
+  char* ws = (char*)scratch_on_current_device();
+  if (!ws) return FI_EDEVICE;
+  return clean_into(n, E, d_src, d_dst, d_sign, ws, L, d_row_ptr, d_col, d_sign_out, h_counts,
+                    (hipStream_t)stream);
 }
 
 }  // extern "C"

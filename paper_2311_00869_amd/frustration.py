@@ -34,8 +34,9 @@ SYMBOLS = (
     "fi_bcloud_reset", "fi_bcloud_merge", "fi_sweep_bounded", "fi_bcloud_size", "fi_bcloud_read",
     "fi_bcloud_min", "fi_bcloud_stats", "fi_edge_list", "fi_switch_list", "fi_sweep_stats",
     "fi_graphl_descend", "fi_graphl_aux_size", "fi_graphl_scales", "fi_set_sampler",
-    "fi_get_sampler", "fi_clean_workspace_size", "fi_clean",
+    "fi_get_sampler", "fi_clean_workspace_size", "fi_clean", "fi_clean_no_alloc",
 )
+CLEAN_NO_ALLOC_MAX_ENTRIES = 1_000_000  # FI_CLEAN_NO_ALLOC_MAX_ENTRIES
 
 
 class FrustrationError(RuntimeError):
@@ -119,6 +120,7 @@ def load_library(path: str = LIB_PATH):
             "fi_set_sampler": ([vp, i32], c.c_int),
             "fi_clean_workspace_size": ([i32, i64, P(sz)], c.c_int),
             "fi_clean": ([i32, i64, vp, vp, vp, vp, sz, vp, vp, vp, P(i64), vp], c.c_int),
+            "fi_clean_no_alloc": ([i32, i64, vp, vp, vp, vp, vp, vp, P(i64), vp], c.c_int),
             "fi_get_sampler": ([vp, P(i32)], c.c_int),
         }
         for name, (args, res) in sig.items():
@@ -163,10 +165,12 @@ def words_to_numpy(t) -> np.ndarray:
     return t.detach().cpu().numpy().view(np.uint64)
 
 
-def clean(n: int, src, dst, sign, device="cuda", stream=None):
+def clean(n: int, src, dst, sign, device="cuda", stream=None, no_alloc: bool = False):
     """The paper's input cleaning on the GPU (fi_clean): a raw signed edge
     list -> (row_ptr, col, sign) device tensors of a simple symmetric signed
-    graph, and the counts of what was kept and dropped."""
+    graph, and the counts of what was kept and dropped.  no_alloc=True calls
+    fi_clean_no_alloc, whose workspace is the library's own device array (up
+    to CLEAN_NO_ALLOC_MAX_ENTRIES entries)."""
     _require_gpu()
     lib = load_library()
     dev = torch.device(device)
@@ -174,17 +178,22 @@ def clean(n: int, src, dst, sign, device="cuda", stream=None):
     d = _dev(dst, torch.int32, dev)
     g = _dev(sign, torch.int32, dev)
     E = int(s.numel())
-    size = ctypes.c_size_t()
-    _check(lib.fi_clean_workspace_size(int(n), E, ctypes.byref(size)), "clean_workspace_size")
-    raw = torch.empty(size.value + 256, dtype=torch.uint8, device=dev)
-    ptr = (raw.data_ptr() + 255) // 256 * 256
     rp = torch.empty(n + 1, dtype=torch.int32, device=dev)
     col = torch.empty(max(2 * E, 1), dtype=torch.int32, device=dev)
     sg = torch.empty(max(2 * E, 1), dtype=torch.int8, device=dev)
     counts = (ctypes.c_int64 * 5)()
-    with torch.cuda.device(dev):
-        _check(lib.fi_clean(int(n), E, _ptr(s), _ptr(d), _ptr(g), ctypes.c_void_p(ptr), size.value,
-                            _ptr(rp), _ptr(col), _ptr(sg), counts, _stream_ptr(stream)), "clean")
+    if no_alloc:
+        with torch.cuda.device(dev):
+            _check(lib.fi_clean_no_alloc(int(n), E, _ptr(s), _ptr(d), _ptr(g), _ptr(rp), _ptr(col),
+                                         _ptr(sg), counts, _stream_ptr(stream)), "clean_no_alloc")
+    else:
+        size = ctypes.c_size_t()
+        _check(lib.fi_clean_workspace_size(int(n), E, ctypes.byref(size)), "clean_workspace_size")
+        raw = torch.empty(size.value + 256, dtype=torch.uint8, device=dev)
+        ptr = (raw.data_ptr() + 255) // 256 * 256
+        with torch.cuda.device(dev):
+            _check(lib.fi_clean(int(n), E, _ptr(s), _ptr(d), _ptr(g), ctypes.c_void_p(ptr), size.value,
+                                _ptr(rp), _ptr(col), _ptr(sg), counts, _stream_ptr(stream)), "clean")
     nnz = 2 * counts[0]
     names = ("kept", "invalid", "self_loops", "duplicates", "inconsistent_pairs")
     return rp, col[:nnz], sg[:nnz], dict(zip(names, [int(x) for x in counts]))

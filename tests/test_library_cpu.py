@@ -104,3 +104,16 @@ def test_autotune_candidates_cover_every_path_and_multi_grids():
     assert {c["grid"] for c in small if c["path"] == 5} == {0, 64, 128}
     large = tune.candidates(16000000, 128000000)
     assert {c["path"] for c in large} == {3, 4, 5}
+
+
+def test_clean_no_alloc_rejects_sizes_on_the_host():
+    # argument and size checks come before any device work
+    lib = fr.load_library()
+    counts = (ctypes.c_int64 * 5)()
+    big = fr.CLEAN_NO_ALLOC_MAX_ENTRIES + 1
+    fake = ctypes.c_void_p(256)
+    assert lib.fi_clean_no_alloc(10, big, fake, fake, fake, fake, fake, fake, counts, None) == -6
+    assert lib.fi_clean_no_alloc(-1, 0, None, None, None, fake, None, None, counts, None) == -1
+    assert lib.fi_clean_no_alloc(10, 5, None, fake, fake, fake, fake, fake, counts, None) == -1
+    hdr = open(HEADER).read()
+    assert f"#define FI_CLEAN_NO_ALLOC_MAX_ENTRIES {fr.CLEAN_NO_ALLOC_MAX_ENTRIES}" in hdr
