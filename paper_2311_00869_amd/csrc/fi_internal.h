@@ -200,8 +200,15 @@ struct Layout {
   size_t glicap;       // graphL: item capacity
   size_t glpart;       // graphL: [items][64] partial sums
   size_t glctl;        // graphL: heavy-row and item counts
+  // tree order of the multi-tree path: per-vertex sums of BFS distances to
+  // the highest-degree vertices, and per block of trees their main-component
+  // root candidates, sort keys and order
+  size_t cent, oroot, okey, operm;
   size_t total;
 };
+
+// trees ordered per block of the multi-tree sweep (a power of two)
+constexpr int kOrderMax = 8192;
 
 // multi-tree path constants shared by create and the kernel
 constexpr int kMSplit = 2048;     // rows longer than this are split into units of this many edges
@@ -232,6 +239,13 @@ hipError_t launch_multi(fi_graph* g, const SweepArgs& a, int words, hipStream_t 
 hipError_t launch_count(const DevGraph& dg, const uint64_t* st, int32_t nstates, uint64_t* counts,
                         hipStream_t s);
 hipError_t graphl_setup(fi_graph* g, hipStream_t s);
+// distance sums to the highest-degree vertices, for the multi-tree path's
+// tree order (blocks; sets g->cent)
+int centrality_setup(fi_graph* g, hipStream_t s);
+// order of trees t0 .. t0 + count - 1 (count <= kOrderMax) for the
+// multi-tree path: perm in the workspace, and each tree's main-component
+// root candidate at oroot[tree - t0]
+hipError_t order_trees(fi_graph* g, uint64_t seed, uint64_t t0, uint32_t count, hipStream_t s);
 
 }  // namespace fi
 
@@ -248,6 +262,9 @@ struct fi_graph {
   int32_t gl_nheavy;      // graphL rows longer than kGLHeavy (their items are planned at upload)
   int32_t sampler;        // kSampler*
   int32_t gl_main_slot;   // slot of the component with the most vertices (-1: none)
+  int32_t main_begin, main_end;  // its vertices in cverts
+  int32_t main_big;       // its row of big-component root minima (-1: not a big component)
+  bool cent;              // distance sums for the tree order are in the workspace
   fi_schedule sched;
   int cu_count;
   int max_shared;

@@ -68,6 +68,19 @@ __device__ __forceinline__ void take_min(uint64_t& best, uint32_t key, uint32_t 
   if (key <= (uint32_t)(best >> 32)) best = ((uint64_t)key << 32) | lo;
 }
 
+// A value every lane holds alike (a scalar), copied into a vector register
+// once, so that several selects under different execution masks share it.
+__device__ __forceinline__ uint32_t to_vgpr(uint32_t s) {
+  uint32_t v;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(s));
+  return v;
+}
+
+// Bits 0 .. j of a 64-bit mask (0 <= j <= 63).
+__device__ __forceinline__ uint64_t bits_upto(int j) {
+  return j >= 63 ? ~0ull : ((2ull << j) - 1);
+}
+
 // Lane t's state along edge j of the chunk: bit t of S_j (a lane-varying j).
 __device__ __forceinline__ bool edge_state(uint64_t S, int j) {
   const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)S, j);
@@ -251,12 +264,10 @@ __device__ __forceinline__ void pull_edges_w(const uint32_t* adj, const uint64_t
       const int j = __builtin_ctzll(hits);
       hits &= hits - 1;
       const uint32_t Hj = __builtin_amdgcn_readlane(H, j);
+      const uint32_t lo = to_vgpr(kPending | (uint32_t)j);
 #pragma unroll
-      for (int w = 0; w < W; ++w) {
-        const uint64_t Fj = readlane64(F.w[w], j);
-        if (W > 1 && Fj == 0) continue;  // the edge hits only trees of other words
-        if (lane_bit(Fj)) take_min(best[w], vkey_of(km[w], Hj), kPending | j);
-      }
+      for (int w = 0; w < W; ++w)
+        if (lane_bit(readlane64(F.w[w], j))) take_min(best[w], vkey_of(km[w], Hj), lo);
     }
     // minima found in this chunk take their state
 #pragma unroll
@@ -374,8 +385,9 @@ __device__ __forceinline__ uint64_t pull_small_w(const DevGraph& G, const MState
   const int excl = inc - d;
   // the chunk that starts at row k0: lane i < total takes its edge i, of row kj
   struct Chunk {
-    int k1, total, kj;
+    int k0, k1, total, kj;
     int64_t pos;
+    uint64_t starts;  // bit i: edge i of the chunk starts a row
   };
   auto chunk_at = [&](int k0) {
     Chunk c;
@@ -386,8 +398,10 @@ __device__ __forceinline__ uint64_t pull_small_w(const DevGraph& G, const MState
     c.total = __builtin_amdgcn_readlane(inc, c.k1 - 1) - eb;
     const int e = inc - eb;
     const uint64_t starts = 1ull | wave_or64(inr && e < c.total ? (1ull << e) : 0ull);
-    const int r = (int)__popcll(starts & ((2ull << lane) - 1));
+    const int r = (int)__popcll(starts & bits_upto(lane));
     c.kj = k0 + r - 1;
+    c.k0 = k0;
+    c.starts = starts;
     c.pos = (int64_t)__shfl(s, c.kj) + (eb + lane - __shfl(excl, c.kj));
     return c;
   };
@@ -419,8 +433,9 @@ __device__ __forceinline__ uint64_t pull_small_w(const DevGraph& G, const MState
       for (int w = 0; w < W; ++w) S.w[w] = su.w[w] ^ gn;
     }
     lw[192 + lane] = S;  // the states each edge hands down, read back per row
-    const int kj = c0.kj;
+    const int kr0 = c0.k0;
     const int k1 = c0.k1;
+    const uint64_t starts = c0.starts;
     // c1's records
     un = m1 && lane < c1.total ? (an & kVertexMask) : 0u;
     gn = (an >> 31) ? ~0ull : 0ull;
@@ -453,25 +468,28 @@ __device__ __forceinline__ uint64_t pull_small_w(const DevGraph& G, const MState
         lw[128 + cur] = sbits;
       }
     };
+    // row by row: the hits of the row holding the first remaining hit (rows
+    // are runs of edges between the chunk's row starts), then its outcome
     while (hits) {
-      const int jj = __builtin_ctzll(hits);
-      hits &= hits - 1;
-      const int kk = __builtin_amdgcn_readlane(kj, jj);
-      if (kk != cur) {
-        if (cur >= 0) keep();
+      const int j0 = __builtin_ctzll(hits);
+      const uint64_t later = starts & ~bits_upto(j0);
+      const uint64_t in_row = (later ? (later & (0 - later)) - 1 : ~0ull) & ~(bits_upto(j0) >> 1);
+      uint64_t rh = hits & in_row;
+      hits &= ~in_row;
+      cur = kr0 + (int)__popcll(starts & bits_upto(j0)) - 1;
 #pragma unroll
-        for (int w = 0; w < W; ++w) best[w] = kUnvisited;
-        cur = kk;
-      }
-      const uint32_t Hj = __builtin_amdgcn_readlane(H, jj);
+      for (int w = 0; w < W; ++w) best[w] = kUnvisited;
+      while (rh) {
+        const int jj = __builtin_ctzll(rh);
+        rh &= rh - 1;
+        const uint32_t Hj = __builtin_amdgcn_readlane(H, jj);
+        const uint32_t lo = to_vgpr(kPending | (uint32_t)jj);
 #pragma unroll
-      for (int w = 0; w < W; ++w) {
-        const uint64_t Fj = readlane64(F.w[w], jj);
-        if (W > 1 && Fj == 0) continue;  // the edge hits only trees of other words
-        if (lane_bit(Fj)) take_min(best[w], vkey_of(km[w], Hj), kPending | jj);
+        for (int w = 0; w < W; ++w)
+          if (lane_bit(readlane64(F.w[w], jj))) take_min(best[w], vkey_of(km[w], Hj), lo);
       }
+      keep();
     }
-    if (cur >= 0) keep();
     k0 = k1;
   }
   __builtin_amdgcn_wave_barrier();

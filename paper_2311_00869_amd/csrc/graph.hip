@@ -525,6 +525,10 @@ Layout make_layout(int32_t n, int64_t nnz, int64_t cloud_capacity, uint64_t tabl
   L.glitems = take(8 * L.glicap);
   L.glpart = take(4 * (size_t)kGraphLMaxR * L.glicap);
   L.glctl = take(64);
+  L.cent = take(2 * nn);
+  L.oroot = take(8 * (size_t)kOrderMax);
+  L.okey = take(8 * (size_t)kOrderMax);
+  L.operm = take(4 * (size_t)kOrderMax);
   L.total = off;
   return L;
 }
@@ -551,6 +555,8 @@ int build_components(fi_graph* g, hipStream_t s) {
   int32_t* aslot = (int32_t*)(ws + L.aslot);
   int32_t* count = (int32_t*)(ws + L.ccount);
   g->gl_main_slot = -1;
+  g->main_begin = g->main_end = 0;
+  g->main_big = -1;
   int32_t* cptr = (int32_t*)(ws + L.cptr);
   std::vector<int32_t> cnt(nanch), ptr(nanch + 1, 0);
   std::vector<int4> tasks;
@@ -564,8 +570,14 @@ int build_components(fi_graph* g, hipStream_t s) {
         hipStreamSynchronize(s) != hipSuccess)
       return FI_EDEVICE;
     for (int32_t i = 0; i < nanch; ++i) {
-      if (g->gl_main_slot < 0 || cnt[i] > cnt[g->gl_main_slot]) g->gl_main_slot = i;
+      const bool main = g->gl_main_slot < 0 || cnt[i] > cnt[g->gl_main_slot];
+      if (main) g->gl_main_slot = i;
       ptr[i + 1] = ptr[i] + cnt[i];
+      if (main) {
+        g->main_begin = ptr[i];
+        g->main_end = ptr[i + 1];
+        g->main_big = cnt[i] <= kBigComp ? -1 : nbig;
+      }
       if (cnt[i] <= kBigComp) {
         tasks.push_back(make_int4(ptr[i], ptr[i + 1], -1, 0));
       } else {
@@ -741,6 +753,7 @@ int fi_graph_create(int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int3
                        (uint64_t*)(ws + L.grootkey), nroot, kUnvisited);
   }
   if (build_components(g, s) != FI_OK) return fail(FI_EDEVICE);
+  if (centrality_setup(g, s) != FI_OK) return fail(FI_EDEVICE);
   if (graphl_setup(g, s) != hipSuccess) return fail(FI_EDEVICE);
   hipLaunchKernelGGL(k_fill_u64, dim3(64), dim3(B), 0, s, (uint64_t*)(ws + L.gbar),
                      (int64_t)kGridSlots * kGridBarWords, 0ull);

@@ -1,0 +1,235 @@
+// Which trees share a pass of the multi-tree sweep.
+//
+// A pass walks the rows of every vertex that some of its trees have not yet
+// visited, once per BFS level, and the walk costs about one step per edge
+// that hits at least one of its trees.  Trees whose levels agree on most
+// vertices share those steps; trees whose roots lie at different distances
+// from the graph's core reach each vertex at different levels and so need
+// separate steps.  The sweep therefore takes the trees of a block (up to
+// kOrderMax) in the order of their roots' distance to the core, measured as
+// the sum of BFS distances to the kHubs vertices of highest degree, then by
+// decreasing root degree, then by tree index.  Every tree's result depends
+// only on (graph, seed, tree), and the cloud combines trees with
+// commutative atomics, so the order changes the speed and nothing else.
+//
+// At upload: the distance sums (one multi-source BFS, one bit per hub).
+// Per block of trees: the root of each tree in the component with the most
+// vertices (its minimum-key vertex, the root rule of the sampler), then the
+// sort; the pass reads these roots instead of searching that component again.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "fi_internal.h"
+#include "fi_prims.h"
+
+namespace fi {
+namespace {
+
+constexpr int kHubs = 8;
+constexpr int32_t kCentMinVertices = 65536;  // main components below this keep tree order
+constexpr int kChunk = 4096;                  // vertices per root-search task
+
+inline int grid_for(int64_t work, int block, int cap = 65536) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>((work + block - 1) / block, cap));
+}
+
+__global__ void k_cent_clear(int32_t n, uint8_t* vis, uint8_t* front, uint16_t* dsum) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    vis[v] = 0;
+    front[v] = 0;
+    dsum[v] = 0;
+  }
+}
+
+// Hub h (distinct vertices) starts its BFS: bit h of its visit and frontier bytes.
+__global__ void k_cent_seed(const int32_t* hubs, int nh, uint8_t* vis, uint8_t* front) {
+  const int h = threadIdx.x;
+  if (h < nh) {
+    vis[hubs[h]] = (uint8_t)(1u << h);
+    front[hubs[h]] = (uint8_t)(1u << h);
+  }
+}
+
+// One BFS level for all hubs at once: a vertex not yet reached by every hub
+// takes the hubs that reached one of its neighbours at the previous level,
+// and adds `level` for each of them to its distance sum.
+__global__ void k_cent_level(const int32_t* rp, const uint32_t* adj, int32_t n, uint8_t full,
+                             const uint8_t* front, uint8_t* next, uint8_t* vis, uint16_t* dsum,
+                             uint32_t level, uint32_t* any) {
+  bool grew = false;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const uint8_t have = vis[v];
+    uint8_t nb = 0;
+    if (have != full) {
+      for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+        nb |= front[adj[e] & kVertexMask];
+        if ((uint8_t)(nb | have) == full) break;
+      }
+    }
+    const uint8_t fresh = (uint8_t)(nb & ~have);
+    next[v] = fresh;
+    if (fresh) {
+      vis[v] = (uint8_t)(have | fresh);
+      dsum[v] = (uint16_t)min(65535u, (uint32_t)dsum[v] + level * (uint32_t)__popc(fresh));
+      grew = true;
+    }
+  }
+  if (__ballot(grew) && lane_id() == 0) atomicOr(any, 1u);
+}
+
+__global__ void k_fill64(uint64_t* p, int64_t len, uint64_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// Root candidates (key << 32 | vertex << 1) of trees t0 .. t0 + count - 1 in
+// the main component (cverts[b, e)): one wave per (64 trees, kChunk
+// vertices), lane t the minimum for its tree, then one atomic minimum per
+// tree.  Two running minima keep two compare chains in flight.
+__global__ void k_main_roots(const int32_t* cverts, int32_t b, int32_t e, uint64_t seed,
+                             uint64_t t0, uint32_t count, uint64_t* oroot) {
+  const int lane = lane_id();
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int64_t nchunks = ((int64_t)e - b + kChunk - 1) / kChunk;
+  const int64_t ngroups = (count + 63) / 64;
+  for (int64_t task = wave; task < nchunks * ngroups; task += nwaves) {
+    const int64_t gi = task / nchunks, ci = task - gi * nchunks;
+    const uint32_t slot = (uint32_t)(gi * 64 + lane);
+    const KeyMix km = key_mix(tree_salt(seed, t0 + slot));
+    uint64_t best = kUnvisited, alt = kUnvisited;
+    const int32_t c0 = b + (int32_t)(ci * kChunk), c1 = min(e, c0 + kChunk);
+    for (int32_t c = c0; c < c1; c += 64) {
+      const int32_t mine = c + lane < c1 ? cverts[c + lane] : 0;
+      const uint32_t hm = fmix32((uint32_t)mine);
+      const int cnt = min(64, c1 - c);
+      int j = 0;
+      for (; j + 1 < cnt; j += 2) {
+        const uint32_t v0 = (uint32_t)__builtin_amdgcn_readlane(mine, j);
+        const uint32_t h0 = (uint32_t)__builtin_amdgcn_readlane((int)hm, j);
+        const uint32_t v1 = (uint32_t)__builtin_amdgcn_readlane(mine, j + 1);
+        const uint32_t h1 = (uint32_t)__builtin_amdgcn_readlane((int)hm, j + 1);
+        const uint64_t k0 = root_candidate(vkey_of(km, h0), v0);
+        const uint64_t k1 = root_candidate(vkey_of(km, h1), v1);
+        best = k0 < best ? k0 : best;
+        alt = k1 < alt ? k1 : alt;
+      }
+      if (j < cnt) {
+        const uint32_t v0 = (uint32_t)__builtin_amdgcn_readlane(mine, j);
+        const uint32_t h0 = (uint32_t)__builtin_amdgcn_readlane((int)hm, j);
+        const uint64_t k0 = root_candidate(vkey_of(km, h0), v0);
+        best = k0 < best ? k0 : best;
+      }
+    }
+    best = alt < best ? alt : best;
+    if (slot < count) atomicMin((unsigned long long*)(oroot + slot), (unsigned long long)best);
+  }
+}
+
+// Sort keys of the block's trees and their order: (distance sum of the
+// root, 0xFFFF - min(root degree, 0xFFFF), tree offset), ascending, by a
+// bitonic sort of the next power of two entries in LDS (padding sorts last).
+constexpr int kSortThreads = 1024;
+__global__ void __launch_bounds__(kSortThreads) k_order(const uint64_t* oroot, const uint16_t* dsum,
+                                                        const int32_t* rp, uint32_t count,
+                                                        uint32_t npow, uint64_t t0, uint32_t* perm) {
+  __shared__ uint64_t key[kOrderMax];
+  for (uint32_t i = threadIdx.x; i < npow; i += kSortThreads) {
+    uint64_t k = ~0ull;
+    if (i < count) {
+      const uint32_t r = word_vertex(oroot[i]);
+      const uint32_t deg = (uint32_t)min(0xFFFF, rp[r + 1] - rp[r]);
+      k = ((uint64_t)dsum[r] << 48) | ((uint64_t)(0xFFFFu - deg) << 32) | i;
+    }
+    key[i] = k;
+  }
+  __syncthreads();
+  for (uint32_t k = 2; k <= npow; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = threadIdx.x; i < npow; i += kSortThreads) {
+        const uint32_t p = i ^ j;
+        if (p > i) {
+          const uint64_t a = key[i], c = key[p];
+          if ((a > c) == ((i & k) == 0)) {
+            key[i] = c;
+            key[p] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (uint32_t i = threadIdx.x; i < count; i += kSortThreads)
+    perm[i] = (uint32_t)(t0 + (uint32_t)key[i]);
+}
+
+}  // namespace
+
+int centrality_setup(fi_graph* g, hipStream_t s) {
+  g->cent = false;
+  const int32_t n = g->dg.n;
+  if (g->main_big < 0 || g->main_end - g->main_begin < kCentMinVertices) return FI_OK;
+  // the kHubs vertices of highest degree (ties to the smaller id)
+  std::vector<int32_t> rp((size_t)n + 1);
+  if (hipMemcpyAsync(rp.data(), g->dg.row_ptr, 4 * ((size_t)n + 1), hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return FI_EDEVICE;
+  std::vector<int32_t> order(n);
+  for (int32_t v = 0; v < n; ++v) order[v] = v;
+  const int nh = std::min<int32_t>(kHubs, n);
+  std::partial_sort(order.begin(), order.begin() + nh, order.end(), [&](int32_t a, int32_t b) {
+    const int32_t da = rp[a + 1] - rp[a], db = rp[b + 1] - rp[b];
+    return da != db ? da > db : a < b;
+  });
+  uint8_t* vis = (uint8_t*)(g->ws + g->L.scratch);
+  uint8_t* front = vis + n;
+  uint8_t* next = front + n;
+  uint32_t* any = (uint32_t*)(g->ws + g->L.oroot);
+  int32_t* hubs = (int32_t*)(g->ws + g->L.operm);
+  uint16_t* dsum = (uint16_t*)(g->ws + g->L.cent);
+  if (hipMemcpyAsync(hubs, order.data(), 4 * nh, hipMemcpyHostToDevice, s) != hipSuccess)
+    return FI_EDEVICE;
+  hipLaunchKernelGGL(k_cent_clear, dim3(grid_for(n, 256)), dim3(256), 0, s, n, vis, front, dsum);
+  hipLaunchKernelGGL(k_cent_seed, dim3(1), dim3(64), 0, s, (const int32_t*)hubs, nh, vis, front);
+  const uint8_t full = (uint8_t)((1u << nh) - 1);
+  for (uint32_t level = 1;; ++level) {
+    uint32_t grew = 0;
+    if (hipMemsetAsync(any, 0, 4, s) != hipSuccess) return FI_EDEVICE;
+    hipLaunchKernelGGL(k_cent_level, dim3(grid_for(n, 256)), dim3(256), 0, s, g->dg.row_ptr, g->dg.adj,
+                       n, full, (const uint8_t*)front, next, vis, dsum, level, any);
+    if (hipMemcpyAsync(&grew, any, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return FI_EDEVICE;
+    std::swap(front, next);
+    if (!grew) break;
+  }
+  if (hipGetLastError() != hipSuccess) return FI_EDEVICE;
+  g->cent = true;
+  return FI_OK;
+}
+
+hipError_t order_trees(fi_graph* g, uint64_t seed, uint64_t t0, uint32_t count, hipStream_t s) {
+  if (count == 0 || count > (uint32_t)kOrderMax) return hipErrorInvalidValue;
+  uint64_t* oroot = (uint64_t*)(g->ws + g->L.oroot);
+  uint32_t* perm = (uint32_t*)(g->ws + g->L.operm);
+  hipLaunchKernelGGL(k_fill64, dim3(grid_for(count, 256)), dim3(256), 0, s, oroot, (int64_t)count,
+                     kUnvisited);
+  const int64_t nchunks = ((int64_t)g->main_end - g->main_begin + kChunk - 1) / kChunk;
+  const int64_t tasks = nchunks * (((int64_t)count + 63) / 64);
+  hipLaunchKernelGGL(k_main_roots, dim3(grid_for(tasks * 64, 256, 8192)), dim3(256), 0, s,
+                     (const int32_t*)(g->ws + g->L.cverts), g->main_begin, g->main_end, seed, t0,
+                     count, oroot);
+  uint32_t npow = 1;
+  while (npow < count) npow <<= 1;
+  hipLaunchKernelGGL(k_order, dim3(1), dim3(kSortThreads), 0, s, (const uint64_t*)oroot,
+                     (const uint16_t*)(g->ws + g->L.cent), g->dg.row_ptr, count, npow, t0, perm);
+  return hipGetLastError();
+}
+
+}  // namespace fi

@@ -48,7 +48,7 @@ using namespace mt;
 constexpr int kStageM = 2048;      // LDS staging entries for light list appends
 constexpr int kPushCost = 4;       // push while kPushCost * frontier edges < unfinished edges
 constexpr int kSmall = 32;         // rows up to this many edges are pulled 64 vertices per wave
-constexpr int kMedChunk = 64;      // medium frontier rows per push unit
+constexpr int kMedChunk = 4;       // medium frontier rows per push unit (at most 8,192 edges)
 constexpr int kPlanes = 8;         // bit-sliced counter planes (flushed every 255 edges)
 
 // Per-vertex state in separate arrays of W 8-byte words per vertex: the
@@ -76,6 +76,12 @@ static_assert(kMCtlWords <= kGridSlots * kGridCtlWords, "control block");
 
 struct MArgs {
   uint64_t seed, t0, t1;
+  // the launch's trees in pass order (null: t0, t0 + 1, ...), and with them
+  // each tree's root candidate in the component of big-component row
+  // main_big, at oroot[tree - t0] (null: searched by the root tasks)
+  const uint32_t* perm;
+  const uint64_t* oroot;
+  int32_t main_big;
   uint64_t* tree_switches;
   uint64_t* vminus;      // [n] statistics, or null
   uint64_t* eswitch;     // [m] statistics, or null
@@ -282,8 +288,11 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
   const int32_t* rp = G.row_ptr;
   uint64_t* ctl = A.ctl;
 
-  for (uint64_t tb = A.t0; tb < A.t1; tb += 64 * W) {
-    const int nvalid = (int)min<uint64_t>(64 * W, A.t1 - tb);
+  const uint64_t ntrees = A.t1 - A.t0;
+  // the tree carried by slot i of the launch
+  auto tree_of = [&](uint64_t i) -> uint64_t { return A.perm ? (uint64_t)A.perm[i] : A.t0 + i; };
+  for (uint64_t sb = 0; sb < ntrees; sb += 64 * W) {
+    const int nvalid = (int)min<uint64_t>(64 * W, ntrees - sb);
     TW<W> valid;
     bool vlane[W];
     KeyMix km[W];
@@ -292,7 +301,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
       const int nv = nvalid - 64 * w;
       valid.w[w] = nv >= 64 ? ~0ull : nv > 0 ? ((1ull << nv) - 1) : 0ull;
       vlane[w] = lane < nv;
-      km[w] = key_mix(tree_salt(A.seed, tb + 64 * w + lane));
+      km[w] = key_mix(tree_salt(A.seed, vlane[w] ? tree_of(sb + 64 * w + lane) : A.t0));
     }
 
     // ---- reset: records, bitmaps, control words
@@ -301,8 +310,16 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
       A.S.unf[i] = G.word_mask[i];
       A.S.cand[i] = 0;
     }
-    // big components' root minima (read by several waves each, so cleared here)
-    for (int64_t i = stid; i < (int64_t)A.nbig * 64 * W; i += sstride) A.rootbig[i] = kUnvisited;
+    // big components' root minima (read by several waves each, so cleared
+    // here); the main component's come found already when oroot is given
+    for (int64_t i = stid; i < (int64_t)A.nbig * 64 * W; i += sstride) {
+      uint64_t r = kUnvisited;
+      if (A.oroot && i / (64 * W) == A.main_big) {
+        const int t = (int)(i % (64 * W));
+        if (t < nvalid) r = A.oroot[tree_of(sb + t) - A.t0];
+      }
+      A.rootbig[i] = r;
+    }
     if (rank == 0)
       for (int i = tid; i < kMCtlWords; i += NT) ctl[i] = i == cUNF ? (uint64_t)G.nnz : 0ull;
     if (tid == 0) {
@@ -317,6 +334,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
       uint64_t cnt = 0, deg = 0, fin = 0;
       for (int64_t k = gwave; k < A.ntasks; k += nwaves) {
         const int4 tk = A.tasks[k];
+        if (A.oroot && tk.z == A.main_big) continue;
         uint64_t best[W];
         comp_min_w<W>(A.cverts, tk.x, tk.y, km, best);
         if (tk.z < 0) {
@@ -790,8 +808,9 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
       const uint64_t S = load_agent(ctl + cACC + 4 * tid);
       const uint64_t hi = load_agent(ctl + cACC + 4 * tid + 1);
       const uint64_t lo = load_agent(ctl + cACC + 4 * tid + 2);
-      if (A.insert) cloud_insert(G, hi, lo, S, tb + tid);
-      if (A.tree_switches) A.tree_switches[tb + tid - A.t0] = S;
+      const uint64_t t = tree_of(sb + tid);
+      if (A.insert) cloud_insert(G, hi, lo, S, t);
+      if (A.tree_switches) A.tree_switches[t - A.t0] = S;
     }
     // the next pass clears the control words; finish reading them first
     group_sync(A.bar, rank, nb);
@@ -873,10 +892,32 @@ hipError_t launch_multi(fi_graph* g, const SweepArgs& sa, int words, hipStream_t
   a.rootbig = (uint64_t*)(ws + L.rootbig);
   a.ctl = (uint64_t*)(ws + L.gctl);
   a.bar = (uint64_t*)(ws + L.gbar);
+  a.perm = nullptr;
+  a.oroot = nullptr;
+  a.main_big = g->main_big;
   const bool stats = a.vminus || a.eswitch;
-  if (words == 2)
-    return stats ? launch_mt_block<true, 2>(g, a, s) : launch_mt_block<false, 2>(g, a, s);
-  return stats ? launch_mt_block<true, 1>(g, a, s) : launch_mt_block<false, 1>(g, a, s);
+  auto run = [&](const MArgs& m) {
+    if (words == 2)
+      return stats ? launch_mt_block<true, 2>(g, m, s) : launch_mt_block<false, 2>(g, m, s);
+    return stats ? launch_mt_block<true, 1>(g, m, s) : launch_mt_block<false, 1>(g, m, s);
+  };
+  // more than one pass: trees in blocks of up to kOrderMax, each taken in
+  // the order of order_trees (same results, fewer steps per pass)
+  if (!g->cent || sa.t1 - sa.t0 <= (uint64_t)(64 * words)) return run(a);
+  for (uint64_t b0 = sa.t0; b0 < sa.t1; b0 += kOrderMax) {
+    const uint64_t b1 = std::min<uint64_t>(sa.t1, b0 + kOrderMax);
+    hipError_t e = order_trees(g, sa.seed, b0, (uint32_t)(b1 - b0), s);
+    if (e != hipSuccess) return e;
+    MArgs m = a;
+    m.t0 = b0;
+    m.t1 = b1;
+    m.perm = (const uint32_t*)(ws + L.operm);
+    m.oroot = (const uint64_t*)(ws + L.oroot);
+    m.tree_switches = sa.tree_switches ? sa.tree_switches + (b0 - sa.t0) : nullptr;
+    e = run(m);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace fi
