@@ -46,10 +46,11 @@ namespace {
 using namespace mt;
 
 constexpr int kStageM = 2048;      // LDS staging entries for light list appends
-constexpr int kPushCost = 4;       // push while kPushCost * frontier edges < unfinished edges
+constexpr int kPushCost = 32;      // push while kPushCost * frontier edges < unfinished edges
 constexpr int kSmall = 32;         // rows up to this many edges are pulled 64 vertices per wave
 constexpr int kMedChunk = 4;       // medium frontier rows per push unit (at most 8,192 edges)
-constexpr int kPlanes = 8;         // bit-sliced counter planes (flushed every 255 edges)
+constexpr int kPlanes = 8;         // bit-sliced counter planes (flushed before 255 edges)
+constexpr int kCountBatch = 4;     // edges per lane in flight in the count
 
 // Per-vertex state in separate arrays of W 8-byte words per vertex: the
 // trees that discovered the vertex at the last even / odd level, its state
@@ -720,37 +721,54 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
             for (int b = 0; b < kPlanes; ++b) c[w][b] = 0;
           }
         };
-        // frustrated iff the edge is negative xor the endpoint states differ
-        for (int64_t e0 = (int64_t)rank * NT; e0 < G.m; e0 += sstride) {
-          const int64_t e = e0 + tid;
-          TW<W> x{};
-          if (e < G.m) {
-            const uint2 uv = G.edges[e];
-            const TW<W> su = get_final<W>(A.S.stc, uv.x), sv = get_final<W>(A.S.stc, uv.y & kVertexMask);
-            const uint64_t neg = (uv.y >> 31) ? ~0ull : 0ull;
+        // frustrated iff the edge is negative xor the endpoint states differ;
+        // kCountBatch edges per lane at a time keep that many gather chains in
+        // flight (past the end a lane reads vertex 0 and adds nothing)
+        for (int64_t e0 = (int64_t)rank * NT * kCountBatch; e0 < G.m;
+             e0 += sstride * kCountBatch) {
+          uint2 uv[kCountBatch];
 #pragma unroll
-            for (int w = 0; w < W; ++w) x.w[w] = su.w[w] ^ sv.w[w] ^ neg;
-            // one owner per edge word in every pass
-            if constexpr (STATS) {
-              if (A.eswitch) {
-                uint64_t k = 0;
+          for (int k = 0; k < kCountBatch; ++k) {
+            const int64_t e = e0 + (int64_t)k * NT + tid;
+            uv[k] = e < G.m ? G.edges[e] : make_uint2(0u, 0u);
+          }
+          TW<W> su[kCountBatch], sv[kCountBatch];
 #pragma unroll
-                for (int w = 0; w < W; ++w) k += (uint64_t)__popcll(x.w[w] & valid.w[w]);
-                A.eswitch[e] += k;
+          for (int k = 0; k < kCountBatch; ++k) {
+            su[k] = get_final<W>(A.S.stc, uv[k].x);
+            sv[k] = get_final<W>(A.S.stc, uv[k].y & kVertexMask);
+          }
+#pragma unroll
+          for (int k = 0; k < kCountBatch; ++k) {
+            const int64_t e = e0 + (int64_t)k * NT + tid;
+            TW<W> x{};
+            if (e < G.m) {
+              const uint64_t neg = (uv[k].y >> 31) ? ~0ull : 0ull;
+#pragma unroll
+              for (int w = 0; w < W; ++w) x.w[w] = su[k].w[w] ^ sv[k].w[w] ^ neg;
+              // one owner per edge word in every pass
+              if constexpr (STATS) {
+                if (A.eswitch) {
+                  uint64_t c1 = 0;
+#pragma unroll
+                  for (int w = 0; w < W; ++w) c1 += (uint64_t)__popcll(x.w[w] & valid.w[w]);
+                  A.eswitch[e] += c1;
+                }
+              }
+            }
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+              uint64_t xw = x.w[w];
+#pragma unroll
+              for (int b = 0; b < kPlanes; ++b) {
+                const uint64_t carry = c[w][b] & xw;
+                c[w][b] ^= xw;
+                xw = carry;
               }
             }
           }
-#pragma unroll
-          for (int w = 0; w < W; ++w) {
-            uint64_t xw = x.w[w];
-#pragma unroll
-            for (int b = 0; b < kPlanes; ++b) {
-              const uint64_t carry = c[w][b] & xw;
-              c[w][b] ^= xw;
-              xw = carry;
-            }
-          }
-          if (++it == 255) {
+          it += kCountBatch;
+          if (it + kCountBatch > 255) {
             flush();
             it = 0;
           }
