@@ -101,6 +101,9 @@ def main():
                     help="skip the leg timing the other tree samplers")
     ap.add_argument("--no-graphl-large", action="store_true",
                     help="skip graphL on the main graph (32 restarts x 500 steps)")
+    ap.add_argument("--phases", action="store_true",
+                    help="after the timed steps, one more sweep with the multi-tree kernel's phase "
+                         "log on; prints microseconds per pass by phase and BFS level")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy this many MiB device to device (a kernel of known traffic "
                          "for scaling hardware byte counters)")
@@ -197,6 +200,9 @@ def main():
     print(f"# {args.steps} steps x {T} trees in {elapsed:.3f}s; min switches {best}, "
           f"{states} states in the last cloud", file=sys.stderr, flush=True)
 
+    phases = None
+    if args.phases:
+        phases = phase_table(G, T, torch)
     path_used = G.get_schedule()["path"]
     if path_used == 0:
         path_used = 5 if G.n + G.m // 2 > 135000 else 2
@@ -283,9 +289,33 @@ def main():
         "min_switches_last_step": best[0] if best else None,
         "distinct_states_last_step": states,
     }
+    if phases is not None:
+        out["phases_us_per_pass"] = phases
     out.update(extra)
     G.close()
     print(json.dumps(out), flush=True)
+
+
+def phase_table(G, T, torch):
+    """One sweep of T trees with the phase log on: microseconds per pass of
+    each (phase, level), averaged over the launch's passes."""
+    G.phase_log(1 << 14)
+    G.cloud_reset()
+    G.sweep(T, 0)
+    G.min_frustration()
+    torch.cuda.synchronize()
+    recs = G.phase_records()
+    G.phase_log(0)
+    G.cloud_reset()
+    passes = sum(1 for ph, _, _ in recs if ph == 8) or 1
+    tot = {}
+    for ph, lv, us in recs:
+        key = f"{G.PHASES[ph]}" + (f" L{lv}" if ph in (4, 5, 6) else "")
+        tot[key] = tot.get(key, 0.0) + us
+    table = {k: round(v / passes, 1) for k, v in tot.items()}
+    print(f"# phases over {passes} passes (us per pass): " +
+          ", ".join(f"{k} {v}" for k, v in table.items()), file=sys.stderr, flush=True)
+    return table
 
 
 def bench_bounded(fr, torch, G, T, steps, unbounded_best, fmax=100, chunk=250):
@@ -507,7 +537,7 @@ def bench_batch(fr, tune, torch, graphs, steps, trees=64):
     a sample of the graphs (the plain path)."""
     G = len(graphs)
     B = fr.BatchGraph(graphs, cloud_capacity_per_graph=trees)
-    sched, _ = tune.autotune_batch(B, trees=2, save=False)
+    sched, _ = tune.autotune_batch(B, trees=trees, save=False)
     mn = torch.zeros((G, 2), dtype=torch.int64, device="cuda")
     ds = torch.zeros(G, dtype=torch.int64, device="cuda")
     side = torch.cuda.Stream()

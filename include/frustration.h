@@ -302,6 +302,14 @@ int fi_batch_create(int32_t G, const int64_t* h_vertex_offsets, const int64_t* h
 int fi_batch_sweep(fi_graph* b, int64_t trees_per_graph, uint64_t seed, uint64_t* d_min_per_graph,
                    uint64_t* d_distinct_per_graph, void* stream);
 
+/* The cloud of graph `graph` (0 .. G-1) of a batch after fi_batch_sweep
+ * (Eq. eq-cloud per graph): copied to host memory sorted by (key_hi,
+ * key_lo), as fi_cloud_read does for a single graph; first_tree counts the
+ * graph's own trees from 0.  Blocks; returns the batch's sticky error, if
+ * any, or FI_ECOLLISION. */
+int fi_batch_cloud_read(fi_graph* b, int32_t graph, fi_cloud_entry* h_out, int64_t cap,
+                        int64_t* written, void* stream);
+
 /* ---------------------------------------------------------------- tree samplers */
 
 /* The spanning-tree sampler of the sweep (Section "Tree-Sampling techniques
@@ -466,6 +474,17 @@ int fi_get_schedule(fi_graph* g, fi_schedule* out);
  * number of launches since the last enable. */
 int fi_prof_enable(fi_graph* g, int on);
 int fi_prof_read(fi_graph* g, int kernel, double* out_ms, int64_t* out_launches);
+
+/* Phase log of the multi-tree sweep (paths 4 and 5), for profiling: while
+ * d_log (device, uint64[cap], cap >= 4) is set, workgroup 0 of every
+ * launch appends after each grid-wide barrier a record (phase << 32 |
+ * BFS level, time): d_log[0] counts the records (the caller zeroes it),
+ * record i sits at d_log[2 + 2 i] and d_log[3 + 2 i], records past cap are
+ * dropped, and time is the GPU's constant-rate real-time counter (100 MHz).
+ * Phases: 0 launch start, 1 reset, 2 root search, 3 big-component roots,
+ * 4 lists of a level, 5 pull of a level, 6 split rows of a level, 7 counts
+ * and keys, 8 cloud insert.  NULL turns the log off. */
+int fi_prof_phases(fi_graph* g, uint64_t* d_log, int64_t cap);
 
 const char* fi_strerror(int code);
 

@@ -1061,4 +1061,15 @@ int fi_batch_sweep(fi_graph* h, int64_t trees_per_graph, uint64_t seed, uint64_t
   return hipGetLastError() == hipSuccess ? FI_OK : FI_EDEVICE;
 }
 
+int fi_batch_cloud_read(fi_graph* h, int32_t graph, fi_cloud_entry* h_out, int64_t cap,
+                        int64_t* written, void* stream) {
+  if (!h || !h->is_batch || cap < 0 || (cap > 0 && !h_out)) return FI_EINVAL;
+  auto* bi = (BatchInfo*)h->batch;
+  if (graph < 0 || graph >= bi->G) return FI_EINVAL;
+  const int e = fi_graph_status(h, stream);
+  if (e) return e;
+  const CloudSlot* table = (const CloudSlot*)(h->ws + bi->L.clouds) + (size_t)graph * bi->tsize;
+  return read_cloud_table(table, bi->tsize, h_out, cap, written, (hipStream_t)stream);
+}
+
 }  // extern "C"

@@ -218,6 +218,10 @@ constexpr int kRootChunk = 1024;  // vertices per root-finding task of a big com
 Layout make_layout(int32_t n, int64_t nnz, int64_t cloud_capacity, uint64_t table_size);
 int64_t switch_tiles(int64_t m);  // tiles of the switch-list compaction over m edges
 uint64_t table_size_for(int64_t cloud_capacity);
+// a cloud table (tsize slots of device memory) to host entries sorted by key
+// (blocks); FI_ECOLLISION if a slot met two key_hi or two switch counts
+int read_cloud_table(const CloudSlot* d_table, uint64_t tsize, fi_cloud_entry* h_out, int64_t cap,
+                     int64_t* written, hipStream_t s);
 
 constexpr int kGraphLMaxR = 64;
 constexpr int kGraphLBlocks = 1024;
@@ -265,6 +269,8 @@ struct fi_graph {
   int32_t main_begin, main_end;  // its vertices in cverts
   int32_t main_big;       // its row of big-component root minima (-1: not a big component)
   bool cent;              // distance sums for the tree order are in the workspace
+  uint64_t* plog;         // phase log of the multi-tree kernel (null: off)
+  int64_t pcap;           // its length in words
   fi_schedule sched;
   int cu_count;
   int max_shared;

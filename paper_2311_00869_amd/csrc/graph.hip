@@ -446,6 +446,28 @@ struct ProfEvent {
 
 }  // namespace
 
+int read_cloud_table(const CloudSlot* d_table, uint64_t tsize, fi_cloud_entry* h_out, int64_t cap,
+                     int64_t* written, hipStream_t s) {
+  std::vector<CloudSlot> table(tsize);
+  if (hipMemcpyAsync(table.data(), d_table, sizeof(CloudSlot) * tsize, hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return FI_EDEVICE;
+  std::vector<fi_cloud_entry> rows;
+  for (const CloudSlot& c : table) {
+    if (c.tag == kEmpty) continue;
+    if (c.khi_min != c.khi_max || c.s_min != c.s_max) return FI_ECOLLISION;
+    rows.push_back(fi_cloud_entry{c.khi_min, c.tag, c.freq, c.s_min, c.first});
+  }
+  std::sort(rows.begin(), rows.end(), [](const fi_cloud_entry& a, const fi_cloud_entry& b) {
+    return a.key_hi != b.key_hi ? a.key_hi < b.key_hi : a.key_lo < b.key_lo;
+  });
+  const int64_t k = std::min<int64_t>(cap, (int64_t)rows.size());
+  if (k > 0) std::memcpy(h_out, rows.data(), sizeof(fi_cloud_entry) * k);
+  if (written) *written = (int64_t)rows.size();
+  return FI_OK;
+}
+
 uint64_t table_size_for(int64_t cloud_capacity) {
   uint64_t want = (uint64_t)std::max<int64_t>(cloud_capacity, 1) * 2;
   uint64_t s = 64;
@@ -773,6 +795,8 @@ int fi_graph_create(int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int3
   g->prof_ms[0] = g->prof_ms[1] = 0;
   g->prof_n[0] = g->prof_n[1] = 0;
   g->prof_events = new std::vector<ProfEvent>();
+  g->plog = nullptr;
+  g->pcap = 0;
   g->is_batch = false;
   g->batch = nullptr;
   *out = g;
@@ -845,27 +869,12 @@ int fi_cloud_size(fi_graph* g, int64_t* out, void* stream) {
 int fi_cloud_read(fi_graph* g, fi_cloud_entry* h_out, int64_t cap, int64_t* written, void* stream) {
   if (!g || g->is_batch || cap < 0 || (cap > 0 && !h_out)) return FI_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  std::vector<CloudSlot> table(g->table_size);
   uint64_t bits = 0;
-  FI_HIP(hipMemcpyAsync(table.data(), g->dg.cloud, sizeof(CloudSlot) * g->table_size,
-                        hipMemcpyDeviceToHost, s));
   FI_HIP(hipMemcpyAsync(&bits, g->dg.ctl + C_ERR, 8, hipMemcpyDeviceToHost, s));
   FI_HIP(hipStreamSynchronize(s));
   int e = err_from_bits(bits);
   if (e) return e;
-  std::vector<fi_cloud_entry> rows;
-  for (const CloudSlot& c : table) {
-    if (c.tag == kEmpty) continue;
-    if (c.khi_min != c.khi_max || c.s_min != c.s_max) return FI_ECOLLISION;
-    rows.push_back(fi_cloud_entry{c.khi_min, c.tag, c.freq, c.s_min, c.first});
-  }
-  std::sort(rows.begin(), rows.end(), [](const fi_cloud_entry& a, const fi_cloud_entry& b) {
-    return a.key_hi != b.key_hi ? a.key_hi < b.key_hi : a.key_lo < b.key_lo;
-  });
-  int64_t k = std::min<int64_t>(cap, (int64_t)rows.size());
-  if (k > 0) std::memcpy(h_out, rows.data(), sizeof(fi_cloud_entry) * k);
-  if (written) *written = (int64_t)rows.size();
-  return FI_OK;
+  return read_cloud_table(g->dg.cloud, g->table_size, h_out, cap, written, s);
 }
 
 int fi_cloud_reset(fi_graph* g, void* stream) {
@@ -947,6 +956,13 @@ int fi_prof_enable(fi_graph* g, int on) {
   g->prof = on != 0;
   g->prof_ms[0] = g->prof_ms[1] = 0;
   g->prof_n[0] = g->prof_n[1] = 0;
+  return FI_OK;
+}
+
+int fi_prof_phases(fi_graph* g, uint64_t* d_log, int64_t cap) {
+  if (!g || g->is_batch || cap < 0 || (d_log && cap < 4)) return FI_EINVAL;
+  g->plog = d_log;
+  g->pcap = d_log ? cap : 0;
   return FI_OK;
 }
 

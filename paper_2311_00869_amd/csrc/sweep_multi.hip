@@ -83,6 +83,11 @@ struct MArgs {
   const uint32_t* perm;
   const uint64_t* oroot;
   int32_t main_big;
+  // phase log (null: off): plog[0] counts records; record i is
+  // plog[2 + 2 i] = phase << 32 | level and plog[3 + 2 i] = the constant-rate
+  // real-time counter (100 MHz), taken by workgroup 0 after each grid barrier
+  uint64_t* plog;
+  int64_t pcap;
   uint64_t* tree_switches;
   uint64_t* vminus;      // [n] statistics, or null
   uint64_t* eswitch;     // [m] statistics, or null
@@ -190,6 +195,22 @@ __device__ __forceinline__ void mlist_global(bool in, int32_t v, int dv, int32_t
   }
 }
 
+// Phases of a pass, as logged (fi_prof_phases).
+enum : uint32_t {
+  kPhReset = 1, kPhRoots = 2, kPhBigRoots = 3, kPhLists = 4, kPhPull = 5, kPhSplit = 6,
+  kPhCountKey = 7, kPhInsert = 8
+};
+__device__ __forceinline__ void log_phase(const MArgs& A, uint32_t rank, uint32_t phase,
+                                          uint32_t level) {
+  if (A.plog && rank == 0 && threadIdx.x == 0) {
+    const uint64_t i = atomicAdd((unsigned long long*)A.plog, 1ull);
+    if ((int64_t)(2 + 2 * i + 1) < A.pcap) {
+      A.plog[2 + 2 * i] = ((uint64_t)phase << 32) | level;
+      A.plog[3 + 2 * i] = __builtin_amdgcn_s_memrealtime();
+    }
+  }
+}
+
 // Root vertex r0 of the trees in `mine`: its records, the level-0 lists
 // (once), and the wave's counters (fin in lane 0: the degree of a root
 // already visited by every tree).
@@ -289,6 +310,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
   const int32_t* rp = G.row_ptr;
   uint64_t* ctl = A.ctl;
 
+  log_phase(A, rank, 0, 0);  // launch start
   const uint64_t ntrees = A.t1 - A.t0;
   // the tree carried by slot i of the launch
   auto tree_of = [&](uint64_t i) -> uint64_t { return A.perm ? (uint64_t)A.perm[i] : A.t0 + i; };
@@ -328,6 +350,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
       sh.qn2 = 0;
     }
     group_sync(A.bar, rank, nb);
+    log_phase(A, rank, kPhReset, 0);
 
     // ---- roots: the minimum key of every component, per tree; they form
     // the lists of level 0, all reached
@@ -348,6 +371,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
         }
       }
       group_sync(A.bar, rank, nb);
+      log_phase(A, rank, kPhRoots, 0);
       for (int64_t it = gwave; it < (int64_t)A.nbig * 64 * W; it += nwaves) {
         const int t = (int)(it % (64 * W));
         if (t < nvalid)
@@ -364,6 +388,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
       }
     }
     group_sync(A.bar, rank, nb);
+    log_phase(A, rank, kPhBigRoots, 0);
 
     // ---- levels
     for (uint32_t L = 1;; ++L) {
@@ -529,6 +554,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
       }
       mflush<NT>(sh, pln, pmn, rf);
       group_sync(A.bar, rank, nb);
+      log_phase(A, rank, kPhLists, L);
 
       // ---- phase 2: pull
       if (tid == 0) {
@@ -663,6 +689,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
       }
       const uint32_t nheavy = uni(sh.nh);
       group_sync(A.bar, rank, nb);
+      log_phase(A, rank, kPhPull, L);
 
       // ---- phase 3: split rows take their minima (one wave per row)
       if (nheavy > 0) {
@@ -690,6 +717,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
           if (fin) aadd64(ctl + cUNF, (uint64_t)0 - fin);
         }
         group_sync(A.bar, rank, nb);
+        log_phase(A, rank, kPhSplit, L);
       }
     }
 
@@ -820,6 +848,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
       }
     }
     group_sync(A.bar, rank, nb);
+    log_phase(A, rank, kPhCountKey, 0);
 
     // ---- the trees of the pass enter the cloud
     if (rank == 0 && tid < nvalid) {
@@ -832,6 +861,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
     }
     // the next pass clears the control words; finish reading them first
     group_sync(A.bar, rank, nb);
+    log_phase(A, rank, kPhInsert, 0);
   }
 }
 
@@ -913,6 +943,8 @@ hipError_t launch_multi(fi_graph* g, const SweepArgs& sa, int words, hipStream_t
   a.perm = nullptr;
   a.oroot = nullptr;
   a.main_big = g->main_big;
+  a.plog = g->plog;
+  a.pcap = g->pcap;
   const bool stats = a.vminus || a.eswitch;
   auto run = [&](const MArgs& m) {
     if (words == 2)

@@ -35,6 +35,7 @@ SYMBOLS = (
     "fi_bcloud_min", "fi_bcloud_stats", "fi_edge_list", "fi_switch_list", "fi_sweep_stats",
     "fi_graphl_descend", "fi_graphl_aux_size", "fi_graphl_scales", "fi_set_sampler",
     "fi_get_sampler", "fi_clean_workspace_size", "fi_clean", "fi_clean_no_alloc",
+    "fi_batch_cloud_read", "fi_prof_phases",
 )
 CLEAN_NO_ALLOC_MAX_ENTRIES = 1_000_000  # FI_CLEAN_NO_ALLOC_MAX_ENTRIES
 
@@ -121,6 +122,8 @@ def load_library(path: str = LIB_PATH):
             "fi_clean_workspace_size": ([i32, i64, P(sz)], c.c_int),
             "fi_clean": ([i32, i64, vp, vp, vp, vp, sz, vp, vp, vp, P(i64), vp], c.c_int),
             "fi_clean_no_alloc": ([i32, i64, vp, vp, vp, vp, vp, vp, P(i64), vp], c.c_int),
+            "fi_batch_cloud_read": ([vp, i32, vp, i64, P(i64), vp], c.c_int),
+            "fi_prof_phases": ([vp, vp, i64], c.c_int),
             "fi_get_sampler": ([vp, P(i32)], c.c_int),
         }
         for name, (args, res) in sig.items():
@@ -445,6 +448,34 @@ class Graph:
         _check(self.lib.fi_prof_read(self.handle, kernel, ctypes.byref(ms), ctypes.byref(k)), "prof_read")
         return float(ms.value), int(k.value)
 
+    PHASES = {0: "start", 1: "reset", 2: "roots", 3: "big roots", 4: "lists", 5: "pull",
+              6: "split rows", 7: "counts+keys", 8: "insert"}
+
+    def phase_log(self, records: int = 1 << 16):
+        """Turn the multi-tree kernel's phase log on (a zeroed device buffer
+        of `records` records) or, with records=0, off.  Returns the buffer."""
+        if records <= 0:
+            _check(self.lib.fi_prof_phases(self.handle, None, 0), "prof_phases")
+            self._plog = None
+            return None
+        self._plog = torch.zeros(2 + 2 * records, dtype=torch.int64, device=self.device)
+        _check(self.lib.fi_prof_phases(self.handle, _ptr(self._plog), self._plog.numel()),
+               "prof_phases")
+        return self._plog
+
+    def phase_records(self):
+        """The logged (phase, level, microseconds since the previous record)
+        of every record after a launch start, in order."""
+        log = self._plog.cpu().numpy().view(np.uint64)
+        k = min(int(log[0]), (log.size - 2) // 2)
+        tags, t = log[2:2 + 2 * k:2], log[3:3 + 2 * k:2].astype(np.int64)
+        out = []
+        for i in range(1, k):
+            ph, lv = int(tags[i]) >> 32, int(tags[i]) & 0xFFFFFFFF
+            if ph != 0:
+                out.append((ph, lv, (t[i] - t[i - 1]) / 100.0))
+        return out
+
 
 class BoundedCloud:
     """Memory-bound frustration cloud of Alg. alg-scale: the F_max best
@@ -613,6 +644,18 @@ class BatchGraph:
 
     def status(self, stream=None):
         _check(self.lib.fi_graph_status(self.handle, _stream_ptr(stream)), "batch_status")
+
+    def cloud(self, graph: int, stream=None) -> np.ndarray:
+        """Graph `graph`'s cloud after the last sweep: uint64 [E, 5] rows
+        (key_hi, key_lo, freq, switches, first_tree) sorted by key."""
+        n = ctypes.c_int64(0)
+        _check(self.lib.fi_batch_cloud_read(self.handle, int(graph), None, 0, ctypes.byref(n),
+                                            _stream_ptr(stream)), "batch_cloud_read")
+        buf = (CloudEntry * max(n.value, 1))()
+        _check(self.lib.fi_batch_cloud_read(self.handle, int(graph), buf, n.value, ctypes.byref(n),
+                                            _stream_ptr(stream)), "batch_cloud_read")
+        return np.array([[e.key_hi, e.key_lo, e.freq, e.switches, e.first_tree] for e in buf[: n.value]],
+                        dtype=np.uint64).reshape(-1, 5)
 
     def set_schedule(self, block=256, grid=0, path=0):
         """path 0: 64 trees of a graph per workgroup pass when at least 16 trees

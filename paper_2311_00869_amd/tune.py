@@ -1,7 +1,9 @@
 """Schedule choice for the sweep: a default by graph size, and an autotuner
-that times candidate schedules on a few trees and keeps the fastest.
-Schedules never change results (every path computes the same trees), so
-tuning only trades speed.
+that times candidate schedules and keeps the fastest.  Schedules never
+change results (every path computes the same trees), so tuning only trades
+speed.  Candidates are timed on as many trees as the caller will sweep (by
+default two full passes of the 128-tree path), so that the multi-tree paths
+run with every lane busy and with their tree order in effect.
 """
 from __future__ import annotations
 
@@ -57,8 +59,10 @@ def _load():
     return {}
 
 
-def autotune(graph, trees: int = 16, seed: int = 12345, save: bool = True, verbose=False):
-    """Time each candidate schedule on `trees` trees; keep the fastest."""
+def autotune(graph, trees: int = 256, seed: int = 12345, save: bool = True, verbose=False):
+    """Time each candidate schedule on `trees` trees (pass the number of trees
+    the sweep will take; at least 128 fills a pass of the multi-tree path);
+    keep the fastest."""
     import torch
 
     best = None
@@ -104,21 +108,23 @@ def default_batch_schedule(batch):
     return dict(block=512, grid=0, path=0)
 
 
-def autotune_batch(batch, trees: int = 4, seed: int = 12345, save: bool = True, verbose=False):
-    """Time each block size of the batched sweep on `trees` trees per graph;
+def autotune_batch(batch, trees: int = 64, seed: int = 12345, save: bool = True, verbose=False):
+    """Time the batched sweep's two schedules (path 1: one tree per
+    workgroup; path 4: 64 trees of one graph per workgroup) at each block
+    size on `trees` trees per graph (pass the number the sweep will take);
     keep the fastest (results do not depend on the choice)."""
     import torch
 
     best, results = None, []
-    for b in (256, 512, 1024):
-        batch.set_schedule(block=b, path=0)
+    for path, b in [(p, b) for p in (1, 4) for b in (256, 512, 1024)]:
+        batch.set_schedule(block=b, path=path)
         batch.sweep(1, seed)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         batch.sweep(trees, seed)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        s = dict(block=b, grid=0, path=0)
+        s = dict(block=b, grid=0, path=path)
         results.append((el, s))
         if verbose:
             print(f"# tune batch {s}: {trees * batch.G / el:.1f} trees/s", flush=True)

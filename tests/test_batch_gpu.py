@@ -36,19 +36,22 @@ def _mixed():
     ]
 
 
-def _expect(graphs, K, seed):
+def _expect(graphs, K, seed, clouds=None):
     mins, distinct = [], []
     for g in graphs:
         r = oracle.sweep(g, seed, 0, K, checks=False)
         mins.append(r.best)
         distinct.append(len(r.cloud))
+        if clouds is not None:
+            clouds.append(r.cloud)
     return np.asarray(mins, np.int64), np.asarray(distinct, np.int64)
 
 
 def test_mixed_batch_matches_oracle_per_graph():
     graphs = _mixed()
     K, seed = 40, 4242
-    want_min, want_distinct = _expect(graphs, K, seed)
+    want_clouds = []
+    want_min, want_distinct = _expect(graphs, K, seed, want_clouds)
     B = fr.BatchGraph(graphs, cloud_capacity_per_graph=K)
     # path 1: one workgroup per tree; path 4: 64 trees per workgroup pass
     for path in (1, 4):
@@ -57,6 +60,9 @@ def test_mixed_batch_matches_oracle_per_graph():
             mn, ds = B.sweep(K, seed)
             assert np.array_equal(mn.cpu().numpy(), want_min), (path, block)
             assert np.array_equal(ds.cpu().numpy(), want_distinct), (path, block)
+            # every graph's whole cloud: keys, counts, switch counts, first trees
+            for i in range(len(graphs)):
+                assert np.array_equal(B.cloud(i), want_clouds[i]), (path, block, i)
     # more than one pass of 64 trees per graph, and a partial one
     K2 = 150
     w2_min, w2_distinct = _expect(graphs, K2, seed + 1)

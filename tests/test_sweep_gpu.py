@@ -301,7 +301,7 @@ def test_autotune_keeps_a_schedule_with_oracle_results():
     K, seed = 40, 23
     ref = oracle.sweep(g, seed, 0, K, checks=False)
     G = _graph(g, cap=64)
-    best, results = tune.autotune(G, trees=8, save=False)
+    best, results = tune.autotune(G, trees=128, save=False)
     assert len(results) == len(tune.candidates(G.n, G.nnz))
     assert G.get_schedule()["path"] == best["path"]
     G.cloud_reset()
@@ -386,4 +386,37 @@ def test_tree_order_blocks_match_oracle_and_plain_path():
     for t in (0, 1, 127, 4000, 8191, 8192, 8299):
         ref = oracle.sweep(g, seed, t, t + 1, checks=False)
         assert int(ref.trees[0, 0]) == int(plain[t]), t
+    G.close()
+
+
+def test_autotune_picks_the_multi_tree_pass_past_the_crossover():
+    # on a 100,000-vertex graph with the sweep's own tree count, the tuner
+    # ranks the candidates on full passes and keeps the 128-tree path
+    from paper_2311_00869_amd import tune
+    g = synth.chung_lu(100000, 500000, 2.3, 0, p_pos=0.85)
+    G = _graph(g, cap=1024)
+    best, results = tune.autotune(G, trees=1024, save=False)
+    assert best["path"] == 5, sorted((round(t, 4), s["path"], s["block"], s["grid"]) for t, s in results)[:5]
+    G.close()
+
+
+def test_phase_log_records_every_pass_and_changes_nothing():
+    # the multi-tree kernel's phase log: one record per grid barrier from
+    # workgroup 0, the passes' inserts counted, results unchanged
+    g = synth.chung_lu(100000, 500000, 2.3, 0, p_pos=0.85)
+    K, seed = 300, 5
+    G = _graph(g, cap=K)
+    G.set_schedule(path=5, block=1024)
+    want = G.sweep_range(0, K, seed, tree_switches=True).cpu().numpy()
+    G.cloud_reset()
+    G.phase_log(4096)
+    got = G.sweep_range(0, K, seed, tree_switches=True).cpu().numpy()
+    recs = G.phase_records()
+    G.phase_log(0)
+    assert np.array_equal(got, want)
+    phases = [p for p, _, _ in recs]
+    assert phases.count(8) == 3 and phases.count(1) == 3  # three passes of up to 128 trees
+    assert all(us >= 0 for _, _, us in recs)
+    levels = {lv for p, lv, _ in recs if p == 5}
+    assert min(levels) == 1 and max(levels) >= 3
     G.close()
