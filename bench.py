@@ -418,6 +418,20 @@ def bench_graphl_large(synth, torch, G, R=32, steps=500, alpha=0.001):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     step_ms = e0.elapsed_time(e1) / steps
+    # rounding and the exact count of all restarts: one read of Gamma, one
+    # pass over the edge list (median of 10, events on the launch stream)
+    rc_ms = []
+    for _ in range(10):
+        r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        r0.record()
+        G.round_count(out)
+        r1.record()
+        torch.cuda.synchronize()
+        rc_ms.append(r0.elapsed_time(r1))
+    rc_ms = sorted(rc_ms)[len(rc_ms) // 2]
+    # Gamma read once (4 n R bytes), the edge list once (8 m), one 8-byte state
+    # word per vertex written and gathered twice per edge
+    rc_bytes = 4 * G.n * R + 8 * G.m + 8 * G.n + 2 * 8 * G.m
     # per step: row offsets and adjacency once, R floats gathered per CSR
     # entry, each vertex's R floats read and written
     nbytes = 4 * (G.n + 1) + 4 * G.nnz + 4 * G.nnz * R + 8 * G.n * R
@@ -427,6 +441,8 @@ def bench_graphl_large(synth, torch, G, R=32, steps=500, alpha=0.001):
         "step_ms": round(step_ms, 3), "algorithmic_bytes_per_step": nbytes,
         "GB_per_s": round(nbytes / step_ms / 1e6, 1),
         "best_rounded_frustration": int(counts.min()), "max_log2_scale": int(scales().max()),
+        "round_count_ms": round(rc_ms, 3),
+        "round_count_GB_per_s": round(rc_bytes / rc_ms / 1e6, 1),
     }
     del gamma0, out
     return res

@@ -685,12 +685,7 @@ __global__ void __launch_bounds__(NT) k_batch_multi(BatchMArgs B) {
         const int32_t v = i * 64 + lane;
         uint64_t cs = 0;
         if (v < n) cs = mt::ldw<1>(S.stw, v).w[0] ^ mt::ldw<1>(S.stw, G.comp[v]).w[0];
-        uint64_t W = 0;
-        for (int t = 0; t < 64; ++t) {
-          const uint64_t bb = __ballot((cs >> t) & 1);
-          if (lane == t) W = bb;
-        }
-        key_terms((uint64_t)i, W, khi, klo);
+        key_terms((uint64_t)i, mt::transpose64(cs), khi, klo);
       }
       atomicAdd((unsigned long long*)&s_acc[0][lane], (unsigned long long)myS);
       atomicAdd((unsigned long long*)&s_acc[1][lane], (unsigned long long)khi);

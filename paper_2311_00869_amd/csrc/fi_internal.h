@@ -239,8 +239,9 @@ hipError_t launch_sweep(fi_graph* g, const SweepArgs& a, hipStream_t s);
 hipError_t launch_grid(fi_graph* g, const SweepArgs& a, hipStream_t s);
 hipError_t launch_multi(fi_graph* g, const SweepArgs& a, int words, hipStream_t s);
 // exact count of up to 64 states given as one word per vertex (bit b = the
-// vertex's state in state b, set = -1): counts[b] += frustrated edges
-hipError_t launch_count(const DevGraph& dg, const uint64_t* st, int32_t nstates, uint64_t* counts,
+// vertex's state in state b, set = -1; uint32 words for up to 32 states,
+// else uint64): counts[b] += frustrated edges
+hipError_t launch_count(const DevGraph& dg, const void* st, int32_t nstates, uint64_t* counts,
                         hipStream_t s);
 hipError_t graphl_setup(fi_graph* g, hipStream_t s);
 // distance sums to the highest-degree vertices, for the multi-tree path's

@@ -76,6 +76,26 @@ __device__ __forceinline__ uint32_t to_vgpr(uint32_t s) {
   return v;
 }
 
+// 64 x 64 bit transpose across a wavefront: lane l holds row l on entry,
+// and on return lane t holds the word whose bit l is bit t of row l.  Six
+// stages, each swapping the off-diagonal blocks of size s = 32, 16, ..., 1
+// with the partner lane l ^ s (mask: the bit positions c with c & s == 0).
+__device__ __forceinline__ uint64_t transpose64(uint64_t x) {
+  const int lane = lane_id();
+  const uint64_t kMask[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                             0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int s = 32 >> k;
+    const uint64_t m = kMask[k];
+    const uint32_t ylo = (uint32_t)__shfl_xor((int)(uint32_t)x, s);
+    const uint32_t yhi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), s);
+    const uint64_t y = ((uint64_t)yhi << 32) | ylo;
+    x = (lane & s) ? ((x & ~m) | ((y & ~m) >> s)) : ((x & m) | ((y & m) << s));
+  }
+  return x;
+}
+
 // Bits 0 .. j of a 64-bit mask (0 <= j <= 63).
 __device__ __forceinline__ uint64_t bits_upto(int j) {
   return j >= 63 ? ~0ull : ((2ull << j) - 1);

@@ -364,15 +364,18 @@ __global__ void k_cloud_load(DevGraph G, const uint64_t* e, int64_t count) {
 // wave and one global atomic per block and state finish the sum.
 constexpr int kCountBlock = 256;
 constexpr int kCountPlanes = 8;
-__global__ void __launch_bounds__(kCountBlock) k_count(const uint2* edges, int64_t m,
-                                                     const uint64_t* st, int nstates,
-                                                     uint64_t* counts) {
+constexpr int kCountEdges = 4;
+// T: uint32_t for up to 32 states (a 4-byte word per vertex, half the
+// gathered bytes), uint64_t for up to 64.
+template <typename T>
+__global__ void __launch_bounds__(kCountBlock) k_count(const uint2* edges, int64_t m, const T* st,
+                                                     int nstates, uint64_t* counts) {
   __shared__ uint64_t s_acc[64];
   const int lane = lane_id();
   if (threadIdx.x < 64) s_acc[threadIdx.x] = 0;
   __syncthreads();
-  const uint64_t smask = nstates >= 64 ? ~0ull : ((1ull << nstates) - 1);
-  uint64_t c[kCountPlanes];
+  const T smask = nstates >= (int)(8 * sizeof(T)) ? (T)~(T)0 : (T)(((T)1 << nstates) - 1);
+  T c[kCountPlanes];
 #pragma unroll
   for (int p = 0; p < kCountPlanes; ++p) c[p] = 0;
   uint64_t mine = 0;
@@ -388,23 +391,37 @@ __global__ void __launch_bounds__(kCountBlock) k_count(const uint2* edges, int64
 #pragma unroll
     for (int p = 0; p < kCountPlanes; ++p) c[p] = 0;
   };
-  // the loop bound is uniform over the block, so every wave reaches each flush
-  for (int64_t e0 = (int64_t)blockIdx.x * kCountBlock; e0 < m;
-       e0 += (int64_t)gridDim.x * kCountBlock) {
-    const int64_t e = e0 + threadIdx.x;
-    uint64_t x = 0;
-    if (e < m) {
-      const uint2 uv = edges[e];
-      const uint64_t neg = (uv.y >> 31) ? ~0ull : 0ull;
-      x = (st[uv.x] ^ st[uv.y & kVertexMask] ^ neg) & smask;
+  // kCountEdges edges per lane at a time keep that many gather chains in
+  // flight (past the end a lane reads vertex 0 and adds nothing); the loop
+  // bound is uniform over the block, so every wave reaches each flush
+  for (int64_t e0 = (int64_t)blockIdx.x * kCountBlock * kCountEdges; e0 < m;
+       e0 += (int64_t)gridDim.x * kCountBlock * kCountEdges) {
+    uint2 uv[kCountEdges];
+#pragma unroll
+    for (int k = 0; k < kCountEdges; ++k) {
+      const int64_t e = e0 + (int64_t)k * kCountBlock + threadIdx.x;
+      uv[k] = e < m ? edges[e] : make_uint2(0u, 0u);
+    }
+    T su[kCountEdges], sv[kCountEdges];
+#pragma unroll
+    for (int k = 0; k < kCountEdges; ++k) {
+      su[k] = st[uv[k].x];
+      sv[k] = st[uv[k].y & kVertexMask];
     }
 #pragma unroll
-    for (int p = 0; p < kCountPlanes; ++p) {
-      const uint64_t carry = c[p] & x;
-      c[p] ^= x;
-      x = carry;
+    for (int k = 0; k < kCountEdges; ++k) {
+      const int64_t e = e0 + (int64_t)k * kCountBlock + threadIdx.x;
+      const T neg = (uv[k].y >> 31) ? (T)~(T)0 : (T)0;
+      T x = e < m ? (T)((su[k] ^ sv[k] ^ neg) & smask) : (T)0;
+#pragma unroll
+      for (int p = 0; p < kCountPlanes; ++p) {
+        const T carry = c[p] & x;
+        c[p] ^= x;
+        x = carry;
+      }
     }
-    if (++it == 255) {
+    it += kCountEdges;
+    if (it + kCountEdges > 255) {
       flush();
       it = 0;
     }
@@ -418,16 +435,17 @@ __global__ void __launch_bounds__(kCountBlock) k_count(const uint2* edges, int64
 
 // States given as bitmaps (state b: words bits[b * nwords + i], vertex v is
 // bit v % 64 of word v / 64) turned into one word per vertex: bit b of st[v]
-// is v's bit in state b, for b < nstates (<= 64).  The 64 lanes of a wave
-// share each bitmap word, so every word is read once.
+// is v's bit in state b, for b < nstates (<= 8 sizeof(T)).  The 64 lanes of
+// a wave share each bitmap word, so every word is read once.
+template <typename T>
 __global__ void k_states_by_vertex(const uint64_t* bits, int32_t nwords, int32_t n, int nstates,
-                                   uint64_t* st) {
+                                   T* st) {
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
        v += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = v >> 6;
     const int sh = (int)(v & 63);
-    uint64_t w = 0;
-    for (int b = 0; b < nstates; ++b) w |= ((bits[(size_t)b * nwords + i] >> sh) & 1ull) << b;
+    T w = 0;
+    for (int b = 0; b < nstates; ++b) w |= (T)((bits[(size_t)b * nwords + i] >> sh) & 1ull) << b;
     st[v] = w;
   }
 }
@@ -913,14 +931,20 @@ int fi_count(fi_graph* g, const uint64_t* d_bits, int32_t B, uint64_t* d_counts,
   if (B == 0) return FI_OK;
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(B, 256)), dim3(256), 0, s, d_counts, (int64_t)B, 0ull);
-  // groups of 64 states: transposed to one word per vertex in the scratch
-  // region (8 (n + 64) bytes), then one pass over the edge list per group
-  uint64_t* st = (uint64_t*)(g->ws + g->L.scratch);
+  // groups of 64 states: transposed to one word per vertex (4 bytes for up
+  // to 32 states, else 8) in the scratch region (8 (n + 64) bytes), then one
+  // pass over the edge list per group
+  void* st = g->ws + g->L.scratch;
   const int32_t n = g->dg.n;
   for (int32_t b0 = 0; b0 < B && n > 0; b0 += 64) {
     const int nb = std::min<int32_t>(64, B - b0);
-    hipLaunchKernelGGL(k_states_by_vertex, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s,
-                       d_bits + (size_t)b0 * g->dg.nwords, g->dg.nwords, n, nb, st);
+    const uint64_t* bits = d_bits + (size_t)b0 * g->dg.nwords;
+    if (nb <= 32)
+      hipLaunchKernelGGL(k_states_by_vertex<uint32_t>, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s,
+                         bits, g->dg.nwords, n, nb, (uint32_t*)st);
+    else
+      hipLaunchKernelGGL(k_states_by_vertex<uint64_t>, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s,
+                         bits, g->dg.nwords, n, nb, (uint64_t*)st);
     hipError_t e = launch_count(g->dg, st, nb, d_counts + b0, s);
     if (e != hipSuccess) return FI_EDEVICE;
   }
@@ -1011,13 +1035,17 @@ void prof_end(fi_graph* g, hipStream_t s, void* token, int kernel) {
   delete pe;
 }
 
-hipError_t launch_count(const DevGraph& dg, const uint64_t* st, int32_t nstates, uint64_t* counts,
+hipError_t launch_count(const DevGraph& dg, const void* st, int32_t nstates, uint64_t* counts,
                         hipStream_t s) {
   if (dg.m == 0 || nstates <= 0) return hipSuccess;
-  // a few edges per lane: one counter readout per lane at most at the 16M-vertex graph's 64M edges
-  const int gx = grid_for(dg.m, kCountBlock, 4096);
-  hipLaunchKernelGGL(k_count, dim3(gx), dim3(kCountBlock), 0, s, dg.edges, dg.m, st, (int)nstates,
-                     counts);
+  // a few rounds of kCountEdges edges per lane (64M edges: 16 per lane)
+  const int gx = grid_for((dg.m + kCountEdges - 1) / kCountEdges, kCountBlock, 4096);
+  if (nstates <= 32)
+    hipLaunchKernelGGL(k_count<uint32_t>, dim3(gx), dim3(kCountBlock), 0, s, dg.edges, dg.m,
+                       (const uint32_t*)st, (int)nstates, counts);
+  else
+    hipLaunchKernelGGL(k_count<uint64_t>, dim3(gx), dim3(kCountBlock), 0, s, dg.edges, dg.m,
+                       (const uint64_t*)st, (int)nstates, counts);
   return hipGetLastError();
 }
 

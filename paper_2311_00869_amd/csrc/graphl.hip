@@ -556,11 +556,13 @@ __global__ void k_fill_u32(uint32_t* p, int64_t len, uint32_t v) {
 }
 
 // theta = +1 where Gamma >= 0, else -1 (NaN: -1), as one word per vertex:
-// bit r of st[v] is set when restart r rounds v to -1.  When R divides 64 a
-// wave reads 64 consecutive floats of Gamma (64 / R whole vertices) and one
-// ballot gives all their words, so Gamma streams through once, coalesced;
-// otherwise each thread reads its own vertex's R floats.
-__global__ void k_gl_round(const float* gamma, int32_t n, int R, uint64_t* st) {
+// bit r of st[v] is set when restart r rounds v to -1 (T: uint32_t for up to
+// 32 restarts, else uint64_t).  When R divides 64 a wave reads 64
+// consecutive floats of Gamma (64 / R whole vertices) and one ballot gives
+// all their words, so Gamma streams through once, coalesced; otherwise each
+// thread reads its own vertex's R floats.
+template <typename T>
+__global__ void k_gl_round(const float* gamma, int32_t n, int R, T* st) {
   const int lane = lane_id();
   const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t nthr = (int64_t)gridDim.x * blockDim.x;
@@ -574,13 +576,13 @@ __global__ void k_gl_round(const float* gamma, int32_t n, int R, uint64_t* st) {
       const bool neg = e < total && !(gamma[e] >= 0.0f);
       const uint64_t W = __ballot(neg);
       const int64_t v = e0 / R + lane;
-      if (lane < per && v < n) st[v] = (W >> (lane * R)) & rmask;
+      if (lane < per && v < n) st[v] = (T)((W >> (lane * R)) & rmask);
     }
   } else {
     for (int64_t v = tid; v < n; v += nthr) {
       uint64_t w = 0;
       for (int r = 0; r < R; ++r) w |= (uint64_t)!(gamma[(size_t)v * R + r] >= 0.0f) << r;
-      st[v] = w;
+      st[v] = (T)w;
     }
   }
 }
@@ -588,13 +590,14 @@ __global__ void k_gl_round(const float* gamma, int32_t n, int R, uint64_t* st) {
 // The rounded states as bitmaps, restart by restart: bits[r * nwords + i],
 // vertex v is bit v % 64 of word v / 64 (set = -1).  One wave per word: each
 // lane reads its vertex's word once, R ballots transpose the 64 x R bits.
-__global__ void k_gl_unpack(const uint64_t* st, int32_t n, int32_t nwords, int R, uint64_t* bits) {
+template <typename T>
+__global__ void k_gl_unpack(const T* st, int32_t n, int32_t nwords, int R, uint64_t* bits) {
   const int lane = lane_id();
   const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t i = wave; i < nwords; i += nwaves) {
     const int64_t v = i * 64 + lane;
-    const uint64_t x = v < n ? st[v] : 0ull;
+    const uint64_t x = v < n ? (uint64_t)st[v] : 0ull;
     uint64_t mine = 0;
     for (int r = 0; r < R; ++r) {
       const uint64_t W = __ballot((x >> r) & 1);
@@ -812,15 +815,23 @@ int fi_round_count(fi_graph* g, const float* d_gamma, int32_t R, uint64_t* d_cou
   if (!d_gamma) return FI_EINVAL;
   void* tok = nullptr;
   if (prof_begin(g, s, &tok)) return FI_EDEVICE;
-  // rounded states, one word per vertex, in the scratch region (8 (n + 64) bytes)
-  uint64_t* st = (uint64_t*)(g->ws + g->L.scratch);
+  // rounded states, one word per vertex (4 bytes for up to 32 restarts, else
+  // 8), in the scratch region (8 (n + 64) bytes)
+  void* st = g->ws + g->L.scratch;
   const int64_t work = 64 % R == 0 ? (int64_t)g->dg.n * R : (int64_t)g->dg.n;
-  hipLaunchKernelGGL(k_gl_round, dim3(grid_for_gl(work, 256)), dim3(256), 0, s, d_gamma, g->dg.n,
-                     (int)R, st);
-  if (d_bits_out) {
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((g->dg.nwords + 3) / 4, 65536));
-    hipLaunchKernelGGL(k_gl_unpack, dim3(grid), dim3(256), 0, s, st, g->dg.n, g->dg.nwords, (int)R,
-                       d_bits_out);
+  const int ugrid = (int)std::max<int64_t>(1, std::min<int64_t>((g->dg.nwords + 3) / 4, 65536));
+  if (R <= 32) {
+    hipLaunchKernelGGL(k_gl_round<uint32_t>, dim3(grid_for_gl(work, 256)), dim3(256), 0, s, d_gamma,
+                       g->dg.n, (int)R, (uint32_t*)st);
+    if (d_bits_out)
+      hipLaunchKernelGGL(k_gl_unpack<uint32_t>, dim3(ugrid), dim3(256), 0, s, (const uint32_t*)st,
+                         g->dg.n, g->dg.nwords, (int)R, d_bits_out);
+  } else {
+    hipLaunchKernelGGL(k_gl_round<uint64_t>, dim3(grid_for_gl(work, 256)), dim3(256), 0, s, d_gamma,
+                       g->dg.n, (int)R, (uint64_t*)st);
+    if (d_bits_out)
+      hipLaunchKernelGGL(k_gl_unpack<uint64_t>, dim3(ugrid), dim3(256), 0, s, (const uint64_t*)st,
+                         g->dg.n, g->dg.nwords, (int)R, d_bits_out);
   }
   hipError_t e = launch_count(g->dg, st, R, d_counts, s);
   prof_end(g, s, tok, 1);

@@ -34,6 +34,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "fi_internal.h"
 #include "fi_prims.h"
@@ -212,12 +213,13 @@ __device__ __forceinline__ void log_phase(const MArgs& A, uint32_t rank, uint32_
 }
 
 // Root vertex r0 of the trees in `mine`: its records, the level-0 lists
-// (once), and the wave's counters (fin in lane 0: the degree of a root
-// already visited by every tree).
-template <int W>
+// (once; through the block's LDS staging when sh is given, else straight to
+// the global lists), and the wave's counters (fin in lane 0: the degree of a
+// root already visited by every tree).
+template <int W, class SH>
 __device__ __forceinline__ void put_root(uint32_t r0, const TW<W>& mine, const TW<W>& valid,
                                          const MArgs& A, const int32_t* rp, uint64_t& cnt,
-                                         uint64_t& deg, uint64_t& fin) {
+                                         uint64_t& deg, uint64_t& fin, SH* sh) {
   const int lane = lane_id();
   const int dv = rp[r0 + 1] - rp[r0];
   const bool full = eq_w(mine, valid);
@@ -230,7 +232,8 @@ __device__ __forceinline__ void put_root(uint32_t r0, const TW<W>& mine, const T
       fin += (uint64_t)dv;
     }
   }
-  mlist_global(lane == 0, (int32_t)r0, dv, A.pl, A.pm, A.ph, A.ctl + cF(0));
+  if constexpr (std::is_void_v<SH>) mlist_global(lane == 0, (int32_t)r0, dv, A.pl, A.pm, A.ph, A.ctl + cF(0));
+  else mlist(lane == 0, (int32_t)r0, dv, *sh, A.ph, A.ctl + cF(0));
   cnt += 1;
   deg += (uint64_t)dv;
 }
@@ -238,10 +241,10 @@ __device__ __forceinline__ void put_root(uint32_t r0, const TW<W>& mine, const T
 // Roots of one component (the wave owns it): each distinct root vertex, over
 // all W words, gets the trees it roots in its records and enters the level-0
 // lists once.
-template <int W>
+template <int W, class SH>
 __device__ __forceinline__ void set_roots(const uint64_t* best, const bool* vlane,
                                           const TW<W>& valid, const MArgs& A, const int32_t* rp,
-                                          uint64_t& cnt, uint64_t& deg, uint64_t& fin) {
+                                          uint64_t& cnt, uint64_t& deg, uint64_t& fin, SH* sh) {
   bool ok[W];
   uint32_t r[W];
   uint64_t rem[W];
@@ -267,7 +270,7 @@ __device__ __forceinline__ void set_roots(const uint64_t* best, const bool* vlan
       mine.w[w] = __ballot(ok[w] && r[w] == r0);
       rem[w] &= ~mine.w[w];
     }
-    put_root<W>(r0, mine, valid, A, rp, cnt, deg, fin);
+    put_root<W>(r0, mine, valid, A, rp, cnt, deg, fin, sh);
   }
 }
 
@@ -295,7 +298,7 @@ __device__ __forceinline__ void big_root(const uint64_t* rb, int t, const bool* 
     mine.w[w] = __ballot(vlane[w] && best[w] != kUnvisited && r[w] == rt);
     if (mine.w[w]) first = 64 * w + __builtin_ctzll(mine.w[w]);
   }
-  if (first == t) put_root<W>(rt, mine, valid, A, rp, cnt, deg, fin);
+  if (first == t) put_root<W, void>(rt, mine, valid, A, rp, cnt, deg, fin, nullptr);
 }
 
 template <int NT, bool STATS, int W>
@@ -356,19 +359,25 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
     // the lists of level 0, all reached
     {
       uint64_t cnt = 0, deg = 0, fin = 0;
-      for (int64_t k = gwave; k < A.ntasks; k += nwaves) {
-        const int4 tk = A.tasks[k];
-        if (A.oroot && tk.z == A.main_big) continue;
-        uint64_t best[W];
-        comp_min_w<W>(A.cverts, tk.x, tk.y, km, best);
-        if (tk.z < 0) {
-          set_roots<W>(best, vlane, valid, A, rp, cnt, deg, fin);
-        } else {
+      // a round of one task per wave, then the block's staged level-0 list
+      // entries go out with one reservation (at most 64 W roots per wave fit
+      // the staging lists); the loop bound is uniform over the block
+      for (int64_t k0 = (int64_t)rank * NW; k0 < A.ntasks; k0 += nwaves) {
+        const int64_t k = k0 + wave;
+        const int4 tk = k < A.ntasks ? A.tasks[k] : make_int4(0, 0, -2, 0);
+        if (k < A.ntasks && !(A.oroot && tk.z == A.main_big)) {
+          uint64_t best[W];
+          comp_min_w<W>(A.cverts, tk.x, tk.y, km, best);
+          if (tk.z < 0) {
+            set_roots<W>(best, vlane, valid, A, rp, cnt, deg, fin, &sh);
+          } else {
 #pragma unroll
-          for (int w = 0; w < W; ++w)
-            if (vlane[w] && best[w] != kUnvisited)
-              amin64(A.rootbig + (size_t)tk.z * 64 * W + 64 * w + lane, best[w]);
+            for (int w = 0; w < W; ++w)
+              if (vlane[w] && best[w] != kUnvisited)
+                amin64(A.rootbig + (size_t)tk.z * 64 * W + 64 * w + lane, best[w]);
+          }
         }
+        mflush<NT>(sh, A.pl, A.pm, A.ctl + cF(0));
       }
       group_sync(A.bar, rank, nb);
       log_phase(A, rank, kPhRoots, 0);
@@ -825,14 +834,7 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
           }
         }
 #pragma unroll
-        for (int w = 0; w < W; ++w) {
-          uint64_t Wd = 0;
-          for (int t = 0; t < 64; ++t) {
-            const uint64_t b = __ballot((cs.w[w] >> t) & 1);
-            if (lane == t) Wd = b;
-          }
-          key_terms((uint64_t)i, Wd, khi[w], klo[w]);
-        }
+        for (int w = 0; w < W; ++w) key_terms((uint64_t)i, transpose64(cs.w[w]), khi[w], klo[w]);
       }
 #pragma unroll
       for (int w = 0; w < W; ++w) {
