@@ -27,7 +27,7 @@ __host__ __device__ __forceinline__ uint64_t mix64(uint64_t x) {
 }
 
 // MurmurHash3's 32-bit finalizer (Appleby, public domain).
-__host__ __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+__host__ __device__ __forceinline__ constexpr uint32_t fmix32(uint32_t h) {
   h ^= h >> 16;
   h *= 0x85EBCA6Bu;
   h ^= h >> 13;

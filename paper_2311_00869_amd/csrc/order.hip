@@ -16,6 +16,7 @@
 // Per block of trees: the root of each tree in the component with the most
 // vertices (its minimum-key vertex, the root rule of the sampler), then the
 // sort; the pass reads these roots instead of searching that component again.
+// A large component's roots come from inverting the key (k_main_roots_inv).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,6 +31,35 @@ namespace {
 constexpr int kHubs = 8;
 constexpr int32_t kCentMinVertices = 65536;  // main components below this keep tree order
 constexpr int kChunk = 4096;                  // vertices per root-search task
+constexpr int32_t kInvertMin = 1 << 20;       // main components from this size invert the key
+constexpr int kInvPerLane = 4;                // candidate keys per lane and step
+
+// Inverse of an odd a mod 2^32 by Newton's iteration x <- x (2 - a x): a is
+// its own inverse mod 8, and every step doubles the number of correct bits.
+__host__ __device__ constexpr uint32_t inv_odd(uint32_t a) {
+  uint32_t x = a;
+  for (int i = 0; i < 4; ++i) x *= 2u - a * x;
+  return x;
+}
+
+// Inverse of fmix32: its five steps undone in reverse order.  A shift-xor
+// y = x ^ (x >> s) is undone by x = y ^ (y >> s) ^ (y >> 2s) ^ ... while
+// the shifts stay below 32 bits.
+__host__ __device__ constexpr uint32_t fmix32_inv(uint32_t h) {
+  h ^= h >> 16;
+  h *= inv_odd(0xC2B2AE35u);
+  h ^= (h >> 13) ^ (h >> 26);
+  h *= inv_odd(0x85EBCA6Bu);
+  h ^= h >> 16;
+  return h;
+}
+static_assert(inv_odd(0x85EBCA6Bu) * 0x85EBCA6Bu == 1u && inv_odd(0xC2B2AE35u) * 0xC2B2AE35u == 1u,
+              "inverse of an odd multiplier");
+static_assert(fmix32_inv(fmix32(0u)) == 0u && fmix32_inv(fmix32(1u)) == 1u &&
+                  fmix32_inv(fmix32(0x7FFFFFFFu)) == 0x7FFFFFFFu &&
+                  fmix32_inv(fmix32(0xDEADBEEFu)) == 0xDEADBEEFu &&
+                  fmix32_inv(fmix32(16000000u)) == 16000000u,
+              "fmix32 inverse");
 
 inline int grid_for(int64_t work, int block, int cap = 65536) {
   return (int)std::max<int64_t>(1, std::min<int64_t>((work + block - 1) / block, cap));
@@ -131,6 +161,47 @@ __global__ void k_main_roots(const int32_t* cverts, int32_t b, int32_t e, uint64
   }
 }
 
+// The same root candidates for a main component of at least kInvertMin
+// vertices, by inverting the key instead of scanning the component.  A
+// tree's key is a bijection of the 32-bit vertex id, so its smallest key on
+// the component is the first k = 0, 1, 2, ... whose preimage
+// u = fmix32^-1((k * m^-1) xor x) is a vertex (u < n) of that component:
+// about 2^32 / |component| candidates per tree instead of |component|.  One
+// wave per tree tests 64 kInvPerLane consecutive keys per step; every key
+// has a preimage and some vertex of the component holds a key, so the walk
+// ends by k = 2^32 - 1 at the latest.
+__global__ void k_main_roots_inv(const int32_t* comp, const int32_t* cverts, int32_t b, int32_t n,
+                                 uint64_t seed, uint64_t t0, uint32_t count, uint64_t* oroot) {
+  const int lane = lane_id();
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int32_t label = comp[cverts[b]];
+  for (int64_t t = wave; t < count; t += nwaves) {
+    const KeyMix km = key_mix(tree_salt(seed, t0 + (uint64_t)t));
+    const uint32_t minv = inv_odd(km.m);
+    uint64_t found = kUnvisited;
+    for (uint64_t base = 0; base < (1ull << 32) && found == kUnvisited; base += 64 * kInvPerLane) {
+      uint32_t u[kInvPerLane];
+      bool hit[kInvPerLane];
+#pragma unroll
+      for (int i = 0; i < kInvPerLane; ++i)
+        u[i] = fmix32_inv(((uint32_t)base + (uint32_t)(64 * i + lane)) * minv ^ km.x);
+#pragma unroll
+      for (int i = 0; i < kInvPerLane; ++i) hit[i] = u[i] < (uint32_t)n && comp[u[i]] == label;
+#pragma unroll
+      for (int i = 0; i < kInvPerLane; ++i) {
+        const uint64_t bal = __ballot(hit[i]);
+        if (bal && found == kUnvisited) {
+          const int j = __ffsll((unsigned long long)bal) - 1;
+          const uint32_t k = (uint32_t)base + (uint32_t)(64 * i + j);
+          found = root_candidate(k, (uint32_t)__builtin_amdgcn_readlane((int)u[i], j));
+        }
+      }
+    }
+    if (lane == 0) oroot[t] = found;
+  }
+}
+
 // Sort keys of the block's trees and their order: (distance sum of the
 // root, 0xFFFF - min(root degree, 0xFFFF), tree offset), ascending, by a
 // bitonic sort of the next power of two entries in LDS (padding sorts last).
@@ -218,13 +289,18 @@ hipError_t order_trees(fi_graph* g, uint64_t seed, uint64_t t0, uint32_t count, 
   if (count == 0 || count > (uint32_t)kOrderMax) return hipErrorInvalidValue;
   uint64_t* oroot = (uint64_t*)(g->ws + g->L.oroot);
   uint32_t* perm = (uint32_t*)(g->ws + g->L.operm);
-  hipLaunchKernelGGL(k_fill64, dim3(grid_for(count, 256)), dim3(256), 0, s, oroot, (int64_t)count,
-                     kUnvisited);
-  const int64_t nchunks = ((int64_t)g->main_end - g->main_begin + kChunk - 1) / kChunk;
-  const int64_t tasks = nchunks * (((int64_t)count + 63) / 64);
-  hipLaunchKernelGGL(k_main_roots, dim3(grid_for(tasks * 64, 256, 8192)), dim3(256), 0, s,
-                     (const int32_t*)(g->ws + g->L.cverts), g->main_begin, g->main_end, seed, t0,
-                     count, oroot);
+  const int32_t* cverts = (const int32_t*)(g->ws + g->L.cverts);
+  if (g->main_end - g->main_begin >= kInvertMin) {
+    hipLaunchKernelGGL(k_main_roots_inv, dim3(grid_for((int64_t)count * 64, 256)), dim3(256), 0, s,
+                       g->dg.comp, cverts, g->main_begin, g->dg.n, seed, t0, count, oroot);
+  } else {
+    hipLaunchKernelGGL(k_fill64, dim3(grid_for(count, 256)), dim3(256), 0, s, oroot, (int64_t)count,
+                       kUnvisited);
+    const int64_t nchunks = ((int64_t)g->main_end - g->main_begin + kChunk - 1) / kChunk;
+    const int64_t tasks = nchunks * (((int64_t)count + 63) / 64);
+    hipLaunchKernelGGL(k_main_roots, dim3(grid_for(tasks * 64, 256, 8192)), dim3(256), 0, s, cverts,
+                       g->main_begin, g->main_end, seed, t0, count, oroot);
+  }
   uint32_t npow = 1;
   while (npow < count) npow <<= 1;
   hipLaunchKernelGGL(k_order, dim3(1), dim3(kSortThreads), 0, s, (const uint64_t*)oroot,

@@ -389,6 +389,29 @@ def test_tree_order_blocks_match_oracle_and_plain_path():
     G.close()
 
 
+def test_tree_order_on_a_component_above_2_20_vertices():
+    # a main component of 1.42M vertices (above 2^20): the roots that order
+    # each block of trees come from inverting the key (the smallest key held
+    # by a component vertex) instead of scanning the component.  300 trees
+    # are three passes; every tree's switch count equals the plain path's
+    # and, on sampled trees, the oracle's
+    g = synth.chung_lu(1500000, 6000000, 2.3, 3, p_pos=0.85)
+    K, seed = 300, 77
+    G = _graph(g, cap=K)
+    G.set_schedule(path=3, block=1024, batch=8)
+    plain = G.sweep_range(0, K, seed, tree_switches=True).cpu().numpy().astype(np.uint64)
+    plain_cloud = G.cloud()
+    G.set_schedule(path=5, block=1024)
+    G.cloud_reset()
+    sw = G.sweep_range(0, K, seed, tree_switches=True).cpu().numpy().astype(np.uint64)
+    assert np.array_equal(sw, plain)
+    assert np.array_equal(G.cloud(), plain_cloud)
+    for t in (0, 151, 299):
+        ref = oracle.sweep(g, seed, t, t + 1, checks=False)
+        assert int(ref.trees[0, 0]) == int(plain[t]), t
+    G.close()
+
+
 def test_autotune_picks_the_multi_tree_pass_past_the_crossover():
     # on a 100,000-vertex graph with the sweep's own tree count, the tuner
     # ranks the candidates on full passes and keeps the 128-tree path
