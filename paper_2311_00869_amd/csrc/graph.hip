@@ -636,10 +636,11 @@ int build_components(fi_graph* g, hipStream_t s) {
     hipLaunchKernelGGL(k_cfill, dim3(grid_for(n, B)), dim3(B), 0, s, G.row_ptr, G.comp, aslot, cptr,
                        n, count, (int32_t*)(ws + L.cverts));
   }
-  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(64 * (int64_t)L.mhcap, B)), dim3(B), 0, s,
-                     (uint64_t*)(ws + L.mhslot), 64 * (int64_t)L.mhcap, kUnvisited);
-  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(64 * (int64_t)L.nbigcap, B)), dim3(B), 0, s,
-                     (uint64_t*)(ws + L.rootbig), 64 * (int64_t)L.nbigcap, kUnvisited);
+  // every row of 128 minima (two tree words of 64 trees each)
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(128 * (int64_t)L.mhcap, B)), dim3(B), 0, s,
+                     (uint64_t*)(ws + L.mhslot), 128 * (int64_t)L.mhcap, kUnvisited);
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(128 * (int64_t)L.nbigcap, B)), dim3(B), 0, s,
+                     (uint64_t*)(ws + L.rootbig), 128 * (int64_t)L.nbigcap, kUnvisited);
   if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess) return FI_EDEVICE;
   g->mtasks = (int32_t)tasks.size();
   g->mnbig = nbig;

@@ -412,6 +412,39 @@ def test_tree_order_on_a_component_above_2_20_vertices():
     G.close()
 
 
+def test_dense_graph_every_row_split_matches_oracle():
+    # a complete graph on 2,200 vertices with random signs: every row is longer
+    # than the 2,048 edges at which the multi-tree pull splits a row, so the
+    # split-row minima use 2,200 rows, past half of their table.  The
+    # workspace is carved from memory that held zeros (a zero minimum would
+    # win every row if a row were not initialised).  Per-tree switches and
+    # clouds on paths 5 and 4 equal the oracle's
+    n = 2200
+    iu, ju = np.triu_indices(n, 1)
+    rng = np.random.default_rng(5)
+    sg = np.where(rng.random(iu.size) < 0.6, 1, -1).astype(np.int8)
+    g = synth.csr_from_edges(n, iu, ju, sg)
+    K, seed = 200, 9
+    ref = oracle.sweep(g, seed, 0, K, checks=False)
+    import ctypes
+    size = ctypes.c_size_t(0)
+    assert fr.load_library().fi_graph_workspace_size(g.n, len(g.col), K, ctypes.byref(size)) == 0
+    rp = torch.from_numpy(g.row_ptr).cuda()
+    cl = torch.from_numpy(g.col).cuda()
+    sgn = torch.from_numpy(g.sign).cuda()
+    z = torch.zeros(size.value + 256, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    del z
+    G = fr.Graph(rp, cl, sgn, cloud_capacity=K)
+    for s in (dict(path=5, block=1024), dict(path=4, block=1024)):
+        G.set_schedule(**s)
+        G.cloud_reset()
+        sw = G.sweep_range(0, K, seed, tree_switches=True).cpu().numpy().astype(np.uint64)
+        assert np.array_equal(sw, ref.trees[:, 0]), s
+        assert np.array_equal(G.cloud(), ref.cloud), s
+    G.close()
+
+
 def test_autotune_picks_the_multi_tree_pass_past_the_crossover():
     # on a 100,000-vertex graph with the sweep's own tree count, the tuner
     # ranks the candidates on full passes and keeps the 128-tree path
