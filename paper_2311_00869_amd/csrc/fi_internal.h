@@ -141,6 +141,8 @@ struct DevGraph {
   const int32_t* row_ptr;   // [n+1]
   const uint32_t* adj;      // [nnz] packed neighbour | neg << 31
   const uint2* edges;       // [m] (u, v | neg << 31), u < v
+  const uint2* cedges;      // [m] (v, u | neg << 31): each edge once, in the row of its
+                            // endpoint of lower rank (degree, then id), rows in order
   const int32_t* comp;      // [n] anchor (smallest id) of the component
   const int32_t* word_comp; // [nwords] smallest anchor among the word's vertices
                             // with an edge ("main" component), -2 if none
@@ -180,7 +182,7 @@ constexpr int kGridCtlWords = 128;          // control words per tree slot
 constexpr int kGridBarWords = 32 + 16 * 512;  // barrier words per tree slot
 
 struct Layout {
-  size_t row_ptr, adj, edges, comp, word_comp, word_mask, word_main, anchors, tmp, cloud, ctl;
+  size_t row_ptr, adj, edges, cedges, comp, word_comp, word_mask, word_main, anchors, tmp, cloud, ctl;
   size_t scratch;      // create temporaries, cloud staging, rounded graphL states
   size_t gl;           // graphL loss partials
   // whole-grid path: kGridSlots trees in flight

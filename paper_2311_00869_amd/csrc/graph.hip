@@ -150,6 +150,38 @@ __global__ void k_pack(const int32_t* rp, const int32_t* col, const int8_t* sign
   }
 }
 
+// The counting edge list: every edge once, from the endpoint of lower rank
+// (degree, then id) to the one of higher rank, in row order.  A count streams
+// the lower-ranked endpoint and gathers the other, so the gathers land on
+// high-degree vertices, whose words the caches hold.  One wave per row; with
+// out null it writes each row's entry count to cnt, else the entries at
+// off[v].
+__global__ void k_orient(const int32_t* rp, const uint32_t* adj, int32_t n, const int32_t* off,
+                         int32_t* cnt, uint2* out) {
+  const int lane = lane_id();
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t v = wave; v < n; v += nwaves) {
+    const int32_t b = rp[v], e = rp[v + 1], dv = e - b;
+    int32_t k = 0;
+    for (int32_t c = b; c < e; c += 64) {
+      const int32_t i = c + lane;
+      bool take = false;
+      uint32_t a = 0;
+      if (i < e) {
+        a = adj[i];
+        const int32_t u = (int32_t)(a & kVertexMask);
+        const int32_t du = rp[u + 1] - rp[u];
+        take = du > dv || (du == dv && u > (int32_t)v);
+      }
+      const uint64_t m = __ballot(take);
+      if (out && take) out[off[v] + k + (int32_t)lanes_below(m)] = make_uint2((uint32_t)v, a);
+      k += (int32_t)__popcll(m);
+    }
+    if (!out && lane == 0) cnt[v] = k;
+  }
+}
+
 __global__ void k_copy_i32(const int32_t* src, int32_t* dst, int64_t len) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -510,6 +542,7 @@ Layout make_layout(int32_t n, int64_t nnz, int64_t cloud_capacity, uint64_t tabl
   L.row_ptr = take(4 * (nn + 1));
   L.adj = take(4 * (size_t)nnz);
   L.edges = take(8 * m);
+  L.cedges = take(8 * m);
   L.comp = take(4 * nn);
   L.word_comp = take(4 * nw);
   L.word_mask = take(8 * nw);
@@ -723,6 +756,7 @@ int fi_graph_create(int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int3
   G.row_ptr = (const int32_t*)(ws + L.row_ptr);
   G.adj = (const uint32_t*)(ws + L.adj);
   G.edges = (const uint2*)(ws + L.edges);
+  G.cedges = (const uint2*)(ws + L.cedges);
   G.comp = (const int32_t*)(ws + L.comp);
   G.word_comp = (const int32_t*)(ws + L.word_comp);
   G.word_mask = (const uint64_t*)(ws + L.word_mask);
@@ -779,6 +813,21 @@ int fi_graph_create(int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int3
   if (nnz > 0)
     hipLaunchKernelGGL(k_pack, dim3(grid_for(nnz, B, 16384)), dim3(B), 0, s, d_row_ptr, d_col,
                        d_sign, n, nnz, upper_start, edge_off, (uint32_t*)G.adj, (uint2*)G.edges);
+  // the counting edge list (row counts, their scan, then the entries)
+  if (nnz > 0) {
+    const int gw = grid_for((int64_t)n * 64, B, 16384);
+    hipLaunchKernelGGL(k_orient, dim3(gw), dim3(B), 0, s, G.row_ptr, G.adj, n, (const int32_t*)nullptr,
+                       edge_off, (uint2*)nullptr);
+    int64_t ntiles = ((int64_t)n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(kScanBlock), 0, s, edge_off,
+                       (int64_t)n, tile_sums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, s, tile_sums, ntiles,
+                       tile_sums + ntiles);
+    hipLaunchKernelGGL(k_scan_add, dim3(grid_for(n, B)), dim3(B), 0, s, edge_off, (int64_t)n,
+                       tile_sums);
+    hipLaunchKernelGGL(k_orient, dim3(gw), dim3(B), 0, s, G.row_ptr, G.adj, n,
+                       (const int32_t*)edge_off, (int32_t*)nullptr, (uint2*)G.cedges);
+  }
   // components
   if (n > 0) {
     int32_t* comp = (int32_t*)G.comp;
@@ -1042,10 +1091,10 @@ hipError_t launch_count(const DevGraph& dg, const void* st, int32_t nstates, uin
   // a few rounds of kCountEdges edges per lane (64M edges: 16 per lane)
   const int gx = grid_for((dg.m + kCountEdges - 1) / kCountEdges, kCountBlock, 4096);
   if (nstates <= 32)
-    hipLaunchKernelGGL(k_count<uint32_t>, dim3(gx), dim3(kCountBlock), 0, s, dg.edges, dg.m,
+    hipLaunchKernelGGL(k_count<uint32_t>, dim3(gx), dim3(kCountBlock), 0, s, dg.cedges, dg.m,
                        (const uint32_t*)st, (int)nstates, counts);
   else
-    hipLaunchKernelGGL(k_count<uint64_t>, dim3(gx), dim3(kCountBlock), 0, s, dg.edges, dg.m,
+    hipLaunchKernelGGL(k_count<uint64_t>, dim3(gx), dim3(kCountBlock), 0, s, dg.cedges, dg.m,
                        (const uint64_t*)st, (int)nstates, counts);
   return hipGetLastError();
 }

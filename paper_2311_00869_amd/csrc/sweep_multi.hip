@@ -760,14 +760,17 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
         };
         // frustrated iff the edge is negative xor the endpoint states differ;
         // kCountBatch edges per lane at a time keep that many gather chains in
-        // flight (past the end a lane reads vertex 0 and adds nothing)
+        // flight (past the end a lane reads vertex 0 and adds nothing).  The
+        // per-edge statistics follow the edge list's order; the plain count
+        // takes the counting list, whose gathers land on high-degree vertices
+        const uint2* ce = STATS ? G.edges : G.cedges;
         for (int64_t e0 = (int64_t)rank * NT * kCountBatch; e0 < G.m;
              e0 += sstride * kCountBatch) {
           uint2 uv[kCountBatch];
 #pragma unroll
           for (int k = 0; k < kCountBatch; ++k) {
             const int64_t e = e0 + (int64_t)k * NT + tid;
-            uv[k] = e < G.m ? G.edges[e] : make_uint2(0u, 0u);
+            uv[k] = e < G.m ? ce[e] : make_uint2(0u, 0u);
           }
           TW<W> su[kCountBatch], sv[kCountBatch];
 #pragma unroll
