@@ -587,6 +587,53 @@ __global__ void k_gl_round(const float* gamma, int32_t n, int R, T* st) {
   }
 }
 
+// Bit i of the low 16 bits of x moved to bit 4 i.
+__device__ __forceinline__ uint64_t spread4(uint64_t x) {
+  x &= 0xFFFFull;
+  x = (x | (x << 24)) & 0x000000FF000000FFull;
+  x = (x | (x << 12)) & 0x000F000F000F000Full;
+  x = (x | (x << 6)) & 0x0303030303030303ull;
+  x = (x | (x << 3)) & 0x1111111111111111ull;
+  return x;
+}
+
+// The same rounding for R a multiple of 4 that divides 64, Gamma 16-byte
+// aligned: lane l of a wave reads floats 4 l .. 4 l + 3 of a 256-float chunk
+// (256 / R whole vertices, R / 4 lanes each), one ballot per float of the
+// four gives (vertex, restart) bits, and lane j < 256 / R interleaves vertex
+// j's bits from them into its word.  Each wave takes two chunks per step, so
+// two 16-byte loads per lane are in flight.
+template <typename T>
+__global__ void k_gl_round4(const float4* gamma4, int32_t n, int R, T* st) {
+  const int lane = lane_id();
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int64_t total4 = (int64_t)n * R / 4;
+  const int q = R / 4;       // lanes per vertex
+  const int per = 64 / q;    // vertices per chunk
+  const uint64_t qmask = q == 16 ? 0xFFFFull : ((1ull << q) - 1);
+  for (int64_t c0 = wave * 128; c0 < total4; c0 += nwaves * 128) {
+    float4 x[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t i = c0 + 64 * h + lane;
+      x[h] = i < total4 ? gamma4[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint64_t b0 = __ballot(!(x[h].x >= 0.0f)), b1 = __ballot(!(x[h].y >= 0.0f));
+      const uint64_t b2 = __ballot(!(x[h].z >= 0.0f)), b3 = __ballot(!(x[h].w >= 0.0f));
+      const int64_t v = (c0 + 64 * h) / q + lane;
+      if (lane < per && v < n) {
+        const int sh = lane * q;
+        const uint64_t w = spread4((b0 >> sh) & qmask) | (spread4((b1 >> sh) & qmask) << 1) |
+                           (spread4((b2 >> sh) & qmask) << 2) | (spread4((b3 >> sh) & qmask) << 3);
+        st[v] = (T)w;
+      }
+    }
+  }
+}
+
 // The rounded states as bitmaps, restart by restart: bits[r * nwords + i],
 // vertex v is bit v % 64 of word v / 64 (set = -1).  One wave per word: each
 // lane reads its vertex's word once, R ballots transpose the 64 x R bits.
@@ -820,15 +867,26 @@ int fi_round_count(fi_graph* g, const float* d_gamma, int32_t R, uint64_t* d_cou
   void* st = g->ws + g->L.scratch;
   const int64_t work = 64 % R == 0 ? (int64_t)g->dg.n * R : (int64_t)g->dg.n;
   const int ugrid = (int)std::max<int64_t>(1, std::min<int64_t>((g->dg.nwords + 3) / 4, 65536));
+  // 16-byte reads when each vertex's R floats fill whole float4s
+  const bool wide = R % 4 == 0 && 64 % R == 0 && ((uintptr_t)d_gamma & 15) == 0;
+  const int wgrid = grid_for_gl(((int64_t)g->dg.n * R / 4 + 127) / 128 * 64, 256);
   if (R <= 32) {
-    hipLaunchKernelGGL(k_gl_round<uint32_t>, dim3(grid_for_gl(work, 256)), dim3(256), 0, s, d_gamma,
-                       g->dg.n, (int)R, (uint32_t*)st);
+    if (wide)
+      hipLaunchKernelGGL(k_gl_round4<uint32_t>, dim3(wgrid), dim3(256), 0, s, (const float4*)d_gamma,
+                         g->dg.n, (int)R, (uint32_t*)st);
+    else
+      hipLaunchKernelGGL(k_gl_round<uint32_t>, dim3(grid_for_gl(work, 256)), dim3(256), 0, s, d_gamma,
+                         g->dg.n, (int)R, (uint32_t*)st);
     if (d_bits_out)
       hipLaunchKernelGGL(k_gl_unpack<uint32_t>, dim3(ugrid), dim3(256), 0, s, (const uint32_t*)st,
                          g->dg.n, g->dg.nwords, (int)R, d_bits_out);
   } else {
-    hipLaunchKernelGGL(k_gl_round<uint64_t>, dim3(grid_for_gl(work, 256)), dim3(256), 0, s, d_gamma,
-                       g->dg.n, (int)R, (uint64_t*)st);
+    if (wide)
+      hipLaunchKernelGGL(k_gl_round4<uint64_t>, dim3(wgrid), dim3(256), 0, s, (const float4*)d_gamma,
+                         g->dg.n, (int)R, (uint64_t*)st);
+    else
+      hipLaunchKernelGGL(k_gl_round<uint64_t>, dim3(grid_for_gl(work, 256)), dim3(256), 0, s, d_gamma,
+                         g->dg.n, (int)R, (uint64_t*)st);
     if (d_bits_out)
       hipLaunchKernelGGL(k_gl_unpack<uint64_t>, dim3(ugrid), dim3(256), 0, s, (const uint64_t*)st,
                          g->dg.n, g->dg.nwords, (int)R, d_bits_out);

@@ -218,7 +218,7 @@ def test_fused_small_descent_policy():
     G.close()
 
 
-@pytest.mark.parametrize("R", [1, 3, 32, 48, 64])
+@pytest.mark.parametrize("R", [1, 3, 4, 8, 16, 32, 48, 64])
 def test_round_count_every_restart_width(R):
     # rounding reads Gamma vertex by vertex and counts all restarts in one pass
     # over the edge list: every width (dividing 64 or not), zeros of both
@@ -229,12 +229,18 @@ def test_round_count_every_restart_width(R):
     gamma[:7] = 0.0
     gamma[7:13] = -0.0
     gamma[13, 0] = float("nan")
-    counts, bits = G.round_count(gamma, return_bits=True)
     theta = ogl.round_states(gamma.cpu().numpy())
-    assert counts.cpu().numpy().tolist() == ogl.frustration(g, theta).tolist()
     want = np.zeros((R, G.nwords), np.uint64)
     for r in range(R):
         idx = np.flatnonzero(theta[:, r] < 0)
         np.bitwise_or.at(want[r], idx // 64, np.left_shift(np.uint64(1), (idx % 64).astype(np.uint64)))
-    assert np.array_equal(bits.cpu().numpy().view(np.uint64).reshape(R, G.nwords), want)
+    # Gamma 16-byte aligned (16-byte reads when 4 divides R) and a view 4
+    # bytes in (the word-by-word path for every R)
+    whole = torch.empty(g.n * R + 4, dtype=torch.float32, device="cuda")
+    for off in (0, 1):
+        view = whole[off:off + g.n * R].view(g.n, R)
+        view.copy_(gamma)
+        counts, bits = G.round_count(view, return_bits=True)
+        assert counts.cpu().numpy().tolist() == ogl.frustration(g, theta).tolist(), off
+        assert np.array_equal(bits.cpu().numpy().view(np.uint64).reshape(R, G.nwords), want), off
     G.close()
