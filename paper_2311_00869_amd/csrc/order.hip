@@ -33,6 +33,7 @@ constexpr int32_t kCentMinVertices = 65536;  // main components below this keep 
 constexpr int kChunk = 4096;                  // vertices per root-search task
 constexpr int32_t kInvertMin = 1 << 20;       // main components from this size invert the key
 constexpr int kInvPerLane = 4;                // candidate keys per lane and step
+constexpr int32_t kCentWide = 256;            // rows longer than this take a wave each
 
 // Inverse of an odd a mod 2^32 by Newton's iteration x <- x (2 - a x): a is
 // its own inverse mod 8, and every step doubles the number of correct bits.
@@ -85,13 +86,26 @@ __global__ void k_cent_seed(const int32_t* hubs, int nh, uint8_t* vis, uint8_t* 
 
 // One BFS level for all hubs at once: a vertex not yet reached by every hub
 // takes the hubs that reached one of its neighbours at the previous level,
-// and adds `level` for each of them to its distance sum.
+// and adds `level` for each of them to its distance sum.  Rows longer than
+// kCentWide are left to k_cent_wide.
+__device__ __forceinline__ void cent_take(int32_t v, uint8_t have, uint8_t nb, uint8_t* next,
+                                          uint8_t* vis, uint16_t* dsum, uint32_t level, bool& grew) {
+  const uint8_t fresh = (uint8_t)(nb & ~have);
+  next[v] = fresh;
+  if (fresh) {
+    vis[v] = (uint8_t)(have | fresh);
+    dsum[v] = (uint16_t)min(65535u, (uint32_t)dsum[v] + level * (uint32_t)__popc(fresh));
+    grew = true;
+  }
+}
+
 __global__ void k_cent_level(const int32_t* rp, const uint32_t* adj, int32_t n, uint8_t full,
                              const uint8_t* front, uint8_t* next, uint8_t* vis, uint16_t* dsum,
                              uint32_t level, uint32_t* any) {
   bool grew = false;
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
        v += (int64_t)gridDim.x * blockDim.x) {
+    if (rp[v + 1] - rp[v] > kCentWide) continue;
     const uint8_t have = vis[v];
     uint8_t nb = 0;
     if (have != full) {
@@ -100,15 +114,35 @@ __global__ void k_cent_level(const int32_t* rp, const uint32_t* adj, int32_t n, 
         if ((uint8_t)(nb | have) == full) break;
       }
     }
-    const uint8_t fresh = (uint8_t)(nb & ~have);
-    next[v] = fresh;
-    if (fresh) {
-      vis[v] = (uint8_t)(have | fresh);
-      dsum[v] = (uint16_t)min(65535u, (uint32_t)dsum[v] + level * (uint32_t)__popc(fresh));
-      grew = true;
-    }
+    cent_take((int32_t)v, have, nb, next, vis, dsum, level, grew);
   }
   if (__ballot(grew) && lane_id() == 0) atomicOr(any, 1u);
+}
+
+// The same step for the rows longer than kCentWide (rows[0, nrows)), one
+// wave per row, its lanes over the row's entries.
+__global__ void k_cent_wide(const int32_t* rp, const uint32_t* adj, const int32_t* rows,
+                            int32_t nrows, uint8_t full, const uint8_t* front, uint8_t* next,
+                            uint8_t* vis, uint16_t* dsum, uint32_t level, uint32_t* any) {
+  const int lane = lane_id();
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  bool grew = false;
+  for (int64_t k = wave; k < nrows; k += nwaves) {
+    const int32_t v = rows[k];
+    const uint8_t have = vis[v];
+    uint32_t nb = 0;
+    if (have != full) {
+      const int32_t e1 = rp[v + 1];
+      for (int32_t c = rp[v]; c < e1; c += 64) {
+        if (c + lane < e1) nb |= front[adj[c + lane] & kVertexMask];
+        if ((uint8_t)(wave_or_u32(nb) | have) == full) break;
+      }
+      nb = wave_or_u32(nb);
+    }
+    if (lane == 0) cent_take(v, have, (uint8_t)nb, next, vis, dsum, level, grew);
+  }
+  if (lane == 0 && grew) atomicOr(any, 1u);
 }
 
 __global__ void k_fill64(uint64_t* p, int64_t len, uint64_t v) {
@@ -264,8 +298,16 @@ int centrality_setup(fi_graph* g, hipStream_t s) {
   uint32_t* any = (uint32_t*)(g->ws + g->L.oroot);
   int32_t* hubs = (int32_t*)(g->ws + g->L.operm);
   uint16_t* dsum = (uint16_t*)(g->ws + g->L.cent);
-  if (hipMemcpyAsync(hubs, order.data(), 4 * nh, hipMemcpyHostToDevice, s) != hipSuccess)
+  // the long rows, after the three byte maps (the scratch region holds 8 (n + 64) bytes)
+  std::vector<int32_t> wide;
+  for (int32_t v = 0; v < n; ++v)
+    if (rp[v + 1] - rp[v] > kCentWide) wide.push_back(v);
+  int32_t* rows = (int32_t*)(g->ws + g->L.scratch + ((3 * (size_t)n + 255) & ~(size_t)255));
+  if (hipMemcpyAsync(hubs, order.data(), 4 * nh, hipMemcpyHostToDevice, s) != hipSuccess ||
+      (!wide.empty() && hipMemcpyAsync(rows, wide.data(), 4 * wide.size(), hipMemcpyHostToDevice,
+                                       s) != hipSuccess))
     return FI_EDEVICE;
+  const int32_t nwide = (int32_t)wide.size();
   hipLaunchKernelGGL(k_cent_clear, dim3(grid_for(n, 256)), dim3(256), 0, s, n, vis, front, dsum);
   hipLaunchKernelGGL(k_cent_seed, dim3(1), dim3(64), 0, s, (const int32_t*)hubs, nh, vis, front);
   const uint8_t full = (uint8_t)((1u << nh) - 1);
@@ -274,6 +316,10 @@ int centrality_setup(fi_graph* g, hipStream_t s) {
     if (hipMemsetAsync(any, 0, 4, s) != hipSuccess) return FI_EDEVICE;
     hipLaunchKernelGGL(k_cent_level, dim3(grid_for(n, 256)), dim3(256), 0, s, g->dg.row_ptr, g->dg.adj,
                        n, full, (const uint8_t*)front, next, vis, dsum, level, any);
+    if (nwide > 0)
+      hipLaunchKernelGGL(k_cent_wide, dim3(grid_for((int64_t)nwide * 64, 256)), dim3(256), 0, s,
+                         g->dg.row_ptr, g->dg.adj, (const int32_t*)rows, nwide, full,
+                         (const uint8_t*)front, next, vis, dsum, level, any);
     if (hipMemcpyAsync(&grew, any, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       return FI_EDEVICE;
