@@ -429,9 +429,11 @@ def bench_graphl_large(synth, torch, G, R=32, steps=500, alpha=0.001):
         torch.cuda.synchronize()
         rc_ms.append(r0.elapsed_time(r1))
     rc_ms = sorted(rc_ms)[len(rc_ms) // 2]
-    # Gamma read once (4 n R bytes), the edge list once (8 m), one 8-byte state
-    # word per vertex written and gathered twice per edge
-    rc_bytes = 4 * G.n * R + 8 * G.m + 8 * G.n + 2 * 8 * G.m
+    # Gamma read once (4 n R bytes), the edge list once (8 m), one state word
+    # per vertex (4 bytes for up to 32 restarts, else 8) written and gathered
+    # twice per edge
+    word = 4 if R <= 32 else 8
+    rc_bytes = 4 * G.n * R + 8 * G.m + word * G.n + 2 * word * G.m
     # per step: row offsets and adjacency once, R floats gathered per CSR
     # entry, each vertex's R floats read and written
     nbytes = 4 * (G.n + 1) + 4 * G.nnz + 4 * G.nnz * R + 8 * G.n * R
