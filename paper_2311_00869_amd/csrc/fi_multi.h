@@ -497,6 +497,21 @@ __device__ __forceinline__ uint64_t pull_small_w(const DevGraph& G, const MState
       uint64_t rh = hits & in_row;
       hits &= ~in_row;
       cur = kr0 + (int)__popcll(starts & bits_upto(j0)) - 1;
+      if ((rh & (rh - 1)) == 0) {
+        // one edge of the row hits: its trees are the row's new trees and
+        // their states are the ones it hands down, no key to compare
+        TW<W> nbits, sbits;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          nbits.w[w] = readlane64(F.w[w], j0);
+          sbits.w[w] = nbits.w[w] & readlane64(S.w[w], j0);
+        }
+        if (lane == 0) {
+          lw[64 + cur] = nbits;
+          lw[128 + cur] = sbits;
+        }
+        continue;
+      }
 #pragma unroll
       for (int w = 0; w < W; ++w) best[w] = kUnvisited;
       while (rh) {
