@@ -549,16 +549,34 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
           __syncthreads();
         }
       } else {
-        // every vertex some tree has not visited yet
-        for (int64_t c0 = (int64_t)rank * NW; c0 < nw; c0 += (int64_t)nb * NW) {
-          const int64_t w = c0 + wave;
-          const uint64_t bits = w < nw ? A.S.unf[w] : 0ull;
+        // every vertex some tree has not visited yet; the bitmap word and the
+        // row offsets of a wave's next word are read while its current word's
+        // vertices are listed (nothing writes the bitmap in this phase)
+        const int64_t wstep = (int64_t)nb * NW;
+        int64_t w = (int64_t)rank * NW + wave;
+        auto fetch = [&](int64_t x, uint64_t& bx, int32_t& lo, int32_t& hi) {
+          const int64_t vx = x * 64 + lane;
+          const bool ok = x < nw && vx < n;
+          bx = x < nw ? A.S.unf[x] : 0ull;
+          lo = ok ? rp[vx] : 0;
+          hi = ok ? rp[vx + 1] : 0;
+        };
+        uint64_t bits;
+        int32_t r0, r1;
+        fetch(w, bits, r0, r1);
+        for (int64_t c0 = (int64_t)rank * NW; c0 < nw; c0 += wstep) {
+          uint64_t bn;
+          int32_t q0, q1;
+          fetch(w + wstep, bn, q0, q1);
           const bool in = (bits >> lane) & 1;
           const int32_t v = (int32_t)(w * 64 + lane);
-          const int dv = in ? rp[v + 1] - rp[v] : 0;
-          mlist(in, v, dv, sh, phn, rf);
+          mlist(in, v, in ? r1 - r0 : 0, sh, phn, rf);
           __syncthreads();
           if (sh.qn > kStageM - NT || sh.qn2 > kStageM - NT) mflush<NT>(sh, pln, pmn, rf);
+          w += wstep;
+          bits = bn;
+          r0 = q0;
+          r1 = q1;
         }
       }
       mflush<NT>(sh, pln, pmn, rf);
