@@ -15,6 +15,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -48,12 +49,25 @@ def model_bytes(n: int, nnz: int, trees: int, trees_per_pass: int) -> dict:
 TREES_PER_PASS = {1: 1, 2: 1, 3: 1, 4: 64, 5: 128}
 
 
-def kernel_source_sha() -> str:
+def _code_only(text: str) -> str:
+    """C++ source without comments and blank space (string literals in these
+    files hold no comment markers)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def kernel_source_sha(sources=None) -> str:
+    """Hash of the sweep kernels' code (comments and spacing ignored)."""
     h = hashlib.sha256()
     for f in ("sweep.hip", "sweep_grid.hip", "sweep_multi.hip", "fi_multi.h", "fi_prims.h",
               "fi_internal.h"):
-        with open(os.path.join(ROOT, "paper_2311_00869_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        if sources is not None:
+            text = sources[f]
+        else:
+            with open(os.path.join(ROOT, "paper_2311_00869_amd", "csrc", f)) as fh:
+                text = fh.read()
+        h.update(_code_only(text).encode())
     return h.hexdigest()[:16]
 
 

@@ -53,11 +53,11 @@ constexpr int kMedChunk = 4;       // medium frontier rows per push unit (at mos
 constexpr int kPlanes = 8;         // bit-sliced counter planes (flushed before 255 edges)
 constexpr int kCountBatch = 4;     // edges per lane in flight in the count
 
-// Per-vertex state in separate arrays of W 8-byte words per vertex: the
-// trees that discovered the vertex at the last even / odd level, its state
-// bits, the trees that have visited it.  A pull gathers the previous
-// parity's discovery words of every neighbour (128 MB per word at 16M
-// vertices) and the state words only for neighbours that hit some tree.
+// Per-vertex state: one record of four W-word fields per vertex (the trees
+// that discovered the vertex at the last even level, its state bits, the
+// trees that discovered it at the last odd level, the trees that have
+// visited it; 64 bytes at W = 2).  A pull gathers, for every neighbour, the
+// previous parity's discovery words and the state words from one record.
 
 // Control words; each group sits on its own 128-byte line.  r = level mod 4.
 //   F(r): the level's pull lists and frontier: small-row count, heavy
