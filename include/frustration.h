@@ -56,7 +56,7 @@ extern "C" {
 enum {
   FI_OK = 0,
   FI_EINVAL = -1,      /* bad argument, row_ptr not 0..nnz non-decreasing, col out of range */
-  FI_EASYM = -2,       /* an entry u->v without v->u of the same sign ("inconsistencies") */
+  FI_EASYM = -2,       /* an entry u->v without v->u of the same sign (an inconsistency) */
   FI_ESELFLOOP = -3,   /* an entry v->v */
   FI_EDUP = -4,        /* a repeated column in a row */
   FI_ESIGN = -5,       /* a sign other than +1 / -1 */
@@ -195,8 +195,8 @@ int fi_cloud_load(fi_graph* g, const fi_cloud_entry* h_entries, int64_t count, v
 int fi_tree_state(fi_graph* g, uint64_t seed, int64_t t, uint64_t* d_bits_out,
                   uint64_t* d_switches_out, void* stream);
 
-/* Exact frustration count (the switch count of Alg. alg-index line "s =
- * edge signs difference count"): for B states given as bitmaps d_bits
+/* Exact frustration count (the switch count of Alg. alg-index, the number
+ * of edges whose sign disagrees with the state): for B states given as bitmaps d_bits
  * uint64[B][ceil(n/64)] (set bit = vertex state -1), d_counts[b] = number of
  * undirected edges (u, v) with sign(u,v) * s_u * s_v = -1.  Groups of 64
  * states are transposed to one word per vertex and counted in one pass over
@@ -391,9 +391,9 @@ typedef struct fi_bcloud fi_bcloud;
  * per merge.  Pure host arithmetic. */
 int fi_bcloud_workspace_size(int64_t f_max, int64_t staging, size_t* out_bytes);
 
-/* The largest F_max whose workspace fits in cap_bytes (line "Determine
- * F_max" of Alg. alg-scale, with the device memory the caller grants as
- * CAP).  FI_EWORKSPACE if not even one entry fits.  Pure host arithmetic. */
+/* The largest F_max whose workspace fits in cap_bytes (the step of Alg.
+ * alg-scale that sizes the bounded cloud from a memory cap, with the device
+ * memory the caller grants as the cap).  FI_EWORKSPACE if not even one entry fits.  Pure host arithmetic. */
 int fi_bcloud_fmax_for(size_t cap_bytes, int64_t staging, int64_t* out_fmax);
 
 /* Empty table in d_workspace (blocks).  *out owns host memory only. */

@@ -77,8 +77,8 @@ def test_vertex_key_is_a_bijection():
 
 
 def test_tree_keys_are_uniform_and_independent():
-    # The sampler shuffles each vertex's neighbours "with a uniformly
-    # distributed random seed" (Section "Tree-Sampling techniques"): over
+    # The sampler shuffles each vertex's neighbours with a seed drawn
+    # uniformly at random (Section "Tree-Sampling techniques"): over
     # 10^5 trees of one 200-vertex component, (a) every vertex is the root
     # (the minimum-key vertex) equally often, (b) each vertex's rank among
     # the keys is uniform, (c) a pair's key order is a fair coin, (d)
