@@ -218,7 +218,7 @@ void build_tree(const Graph& g, const std::vector<int32_t>& comp, uint64_t seed,
 // reproducible like BFS: all randomness comes from tree t's salt.
 enum { SAMPLER_BFS = 0, SAMPLER_RDFS = 1, SAMPLER_HYBRID = 2, SAMPLER_KRUSKAL = 3 };
 
-// Alg. alg-hybrid's uniformly distributed 0 or 1: the top bit of the
+// Alg. alg-hybrid's fair coin (0 or 1): the top bit of the
 // SplitMix64 finalizer applied to the tree's salt (0: BFS, 1: RDFS).
 int hybrid_coin(uint64_t salt) { return (int)(splitmix_output(salt) >> 63); }
 
