@@ -210,7 +210,7 @@ struct Layout {
 };
 
 // trees ordered per block of the multi-tree sweep (a power of two)
-constexpr int kOrderMax = 8192;
+constexpr int kOrderMax = 16384;
 
 // multi-tree path constants shared by create and the kernel
 constexpr int kMSplit = 2048;     // rows longer than this are split into units of this many edges

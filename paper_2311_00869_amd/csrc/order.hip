@@ -31,7 +31,7 @@ namespace {
 constexpr int kHubs = 8;
 constexpr int32_t kCentMinVertices = 65536;  // main components below this keep tree order
 constexpr int kChunk = 4096;                  // vertices per root-search task
-constexpr int32_t kInvertMin = 1 << 20;       // main components from this size invert the key
+constexpr int32_t kInvertMin = 1 << 18;       // main components from this size invert the key
 constexpr int kInvPerLane = 4;                // candidate keys per lane and step
 constexpr int32_t kCentWide = 256;            // rows longer than this take a wave each
 

@@ -367,12 +367,12 @@ def test_deep_trees_every_schedule(name):
 
 def test_tree_order_blocks_match_oracle_and_plain_path():
     # more than one pass on a graph whose main component has 10^5 vertices:
-    # the multi-tree path takes each block of up to 8,192 trees in its own
-    # order (by root distance to the core); 8,300 trees are two blocks.  Every
-    # tree's switch count equals the plain one-tree-at-a-time path's and, on
-    # sampled trees, the oracle's; the clouds agree
+    # the multi-tree path takes each block of up to 16,384 trees in its own
+    # order (by root distance to the core); 16,500 trees are two blocks.
+    # Every tree's switch count equals the plain one-tree-at-a-time path's
+    # and, on sampled trees, the oracle's; the clouds agree
     g = synth.chung_lu(100000, 500000, 2.3, 3, p_pos=0.85)
-    K, seed = 8300, 77
+    K, seed = 16500, 77
     G = _graph(g, cap=K)
     G.set_schedule(path=3, block=1024, batch=8)
     plain = G.sweep_range(0, K, seed, tree_switches=True).cpu().numpy().astype(np.uint64)
@@ -383,7 +383,7 @@ def test_tree_order_blocks_match_oracle_and_plain_path():
         sw = G.sweep_range(0, K, seed, tree_switches=True).cpu().numpy().astype(np.uint64)
         assert np.array_equal(sw, plain), s
         assert np.array_equal(G.cloud(), plain_cloud), s
-    for t in (0, 1, 127, 4000, 8191, 8192, 8299):
+    for t in (0, 1, 127, 8000, 16383, 16384, 16499):
         ref = oracle.sweep(g, seed, t, t + 1, checks=False)
         assert int(ref.trees[0, 0]) == int(plain[t]), t
     G.close()
