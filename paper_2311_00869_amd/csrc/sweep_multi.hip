@@ -59,6 +59,16 @@ constexpr int kCountBatch = 4;     // edges per lane in flight in the count
 // visited it; 64 bytes at W = 2).  A pull gathers, for every neighbour, the
 // previous parity's discovery words and the state words from one record.
 
+// A copy of a per-lane index that the compiler cannot move: addresses derived
+// from it are formed where they are used instead of at kernel entry, so they
+// do not stay live (and spill) across the pass and level loops.
+__device__ __forceinline__ int64_t fresh_index(int64_t x) {
+  uint32_t lo = (uint32_t)x, hi = (uint32_t)((uint64_t)x >> 32);
+  asm volatile("v_mov_b32 %0, %0" : "+v"(lo));
+  asm volatile("v_mov_b32 %0, %0" : "+v"(hi));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Control words; each group sits on its own 128-byte line.  r = level mod 4.
 //   F(r): the level's pull lists and frontier: small-row count, heavy
 //         (count << 32 | units), vertices reached, their degree sum,
@@ -331,14 +341,15 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
     }
 
     // ---- reset: records, bitmaps, control words
-    for (int64_t v = stid; v < (int64_t)n * W * kRecFields; v += sstride) A.S.nbw[0][v] = 0;
-    for (int64_t i = stid; i < nw; i += sstride) {
+    const int64_t ptid = fresh_index(stid);
+    for (int64_t v = ptid; v < (int64_t)n * W * kRecFields; v += sstride) A.S.nbw[0][v] = 0;
+    for (int64_t i = ptid; i < nw; i += sstride) {
       A.S.unf[i] = G.word_mask[i];
       A.S.cand[i] = 0;
     }
     // big components' root minima (read by several waves each, so cleared
     // here); the main component's come found already when oroot is given
-    for (int64_t i = stid; i < (int64_t)A.nbig * 64 * W; i += sstride) {
+    for (int64_t i = ptid; i < (int64_t)A.nbig * 64 * W; i += sstride) {
       uint64_t r = kUnvisited;
       if (A.oroot && i / (64 * W) == A.main_big) {
         const int t = (int)(i % (64 * W));
@@ -444,8 +455,9 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
         }
       }
       // medium and split rows set their reached bits with atomics
-      for (int64_t i = stid; i < A.rlstride; i += sstride) rmn[i] = 0;
-      for (int64_t i = stid; i < A.rhstride; i += sstride) rhn[i] = 0;
+      const int64_t ltid = fresh_index(stid);
+      for (int64_t i = ltid; i < A.rlstride; i += sstride) rmn[i] = 0;
+      for (int64_t i = ltid; i < A.rhstride; i += sstride) rhn[i] = 0;
 
       // ---- phase 1: the pull lists of level L
       if (push) {
