@@ -216,7 +216,10 @@ __device__ __forceinline__ void log_phase(const MArgs& A, uint32_t rank, uint32_
   if (A.plog && rank == 0 && threadIdx.x == 0) {
     const uint64_t i = atomicAdd((unsigned long long*)A.plog, 1ull);
     if ((int64_t)(2 + 2 * i + 1) < A.pcap) {
-      A.plog[2 + 2 * i] = ((uint64_t)phase << 32) | level;
+      // formed here: as constants hoisted to kernel entry they would be spilled
+      uint32_t hi = phase, lo = level;
+      asm volatile("" : "+v"(hi), "+v"(lo));
+      A.plog[2 + 2 * i] = ((uint64_t)hi << 32) | lo;
       A.plog[3 + 2 * i] = __builtin_amdgcn_s_memrealtime();
     }
   }
