@@ -497,9 +497,11 @@ __device__ __forceinline__ uint64_t pull_small_w(const DevGraph& G, const MState
       uint64_t rh = hits & in_row;
       hits &= ~in_row;
       cur = kr0 + (int)__popcll(starts & bits_upto(j0)) - 1;
-      if ((rh & (rh - 1)) == 0) {
+      if (W > 1 && (rh & (rh - 1)) == 0) {
         // one edge of the row hits: its trees are the row's new trees and
-        // their states are the ones it hands down, no key to compare
+        // their states are the ones it hands down, no key to compare (with
+        // one tree word the general walk is as short, and the batch kernel,
+        // which pulls one word, ran 2 % slower with this branch)
         TW<W> nbits, sbits;
 #pragma unroll
         for (int w = 0; w < W; ++w) {
