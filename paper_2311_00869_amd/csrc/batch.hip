@@ -494,6 +494,7 @@ __global__ void __launch_bounds__(NT) k_batch_multi(BatchMArgs B) {
   __shared__ int s_any[2];  // some vertex reached, by level parity
   __shared__ uint64_t s_acc[3][64];
   __shared__ mt::TW<1> s_pw[NW][4 * 64];  // per wave: short rows' wanted trees and outcomes, edge states
+  __shared__ uint64_t s_pe[NW][65];       // per wave: where the short rows' edges start a row
   char* slot = B.slots + (size_t)blockIdx.x * B.slot_stride;
   const size_t nm = (size_t)B.n_max;
   // vertex records of one word per field, then the unfinished-vertex bitmap
@@ -621,8 +622,8 @@ __global__ void __launch_bounds__(NT) k_batch_multi(BatchMArgs B) {
         if (ne) {
           const int src = mt::select_lane(small, lane < ne ? lane : 0);
           const int32_t vk = __shfl(v, src);
-          mt::pull_small_w<1>(G, S, vk, ne, pp, p, mt::TW<1>{{valid}}, &km, false, s_pw[wave], cnt,
-                              deg, fin);
+          mt::pull_small_w<1, 64>(G, S, vk, ne, pp, p, mt::TW<1>{{valid}}, &km, false, s_pw[wave],
+                                  s_pe[wave], cnt, deg, fin);
         }
         uint64_t big = bits & ~small;
         while (big) {

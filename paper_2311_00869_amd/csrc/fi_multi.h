@@ -377,12 +377,17 @@ __device__ __forceinline__ bool settle_w(const MState& A, int32_t v, const TW<W>
 // chunk's records are in flight (its adjacency was read while this chunk's
 // records arrived).  lw is the wave's LDS scratch of 4 x 64 entries: each
 // row's wanted trees, its newly reached trees and their states, and the
-// states each edge of the current chunk hands down.
-template <int W>
+// states each edge of the current chunk hands down.  ends is the wave's LDS
+// bitmap of DMAX + 1 words (rows have at most DMAX edges, so the 64 rows hold
+// at most 64 DMAX edges): bit e is set when an edge e > 0 of the concatenated
+// rows starts a row.
+template <int W, int DMAX>
 __device__ __forceinline__ uint64_t pull_small_w(const DevGraph& G, const MState& A, int32_t v,
                                                  int ne, int pp, int p, const TW<W>& valid,
                                                  const KeyMix* km, bool push, TW<W>* lw,
-                                                 uint64_t& cnt, uint64_t& deg, uint64_t& fin) {
+                                                 uint64_t* ends, uint64_t& cnt, uint64_t& deg,
+                                                 uint64_t& fin) {
+  static_assert(DMAX >= 1 && DMAX <= 64, "rows of at most 64 edges");
   const int lane = lane_id();
   const bool ok = lane < ne;
   int s = 0, d = 0;
@@ -395,14 +400,17 @@ __device__ __forceinline__ uint64_t pull_small_w(const DevGraph& G, const MState
   lw[lane] = want;
   lw[64 + lane] = TW<W>{};
   lw[128 + lane] = TW<W>{};
-  __builtin_amdgcn_wave_barrier();
-  int inc = d;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(inc, o);
-    if (lane >= o) inc += y;
-  }
+  if (lane <= DMAX) ends[lane] = 0;
+  if (DMAX == 64 && lane == 0) ends[64] = 0;
+  const int inc = wave_incl_sum_i32(d);
   const int excl = inc - d;
+  const int all = __builtin_amdgcn_readlane(inc, 63);
+  __builtin_amdgcn_wave_barrier();
+  // rows are never empty (a vertex without edges is its own tree's root), so
+  // the row ends inc are distinct; the last one starts no row
+  if (ok && inc < all) atomicOr((unsigned long long*)&ends[inc >> 6], 1ull << (inc & 63));
+  const int sx = s - excl;  // edge e of the concatenation is entry sx + e of its row's vertex
+  __builtin_amdgcn_wave_barrier();
   // the chunk that starts at row k0: lane i < total takes its edge i, of row kj
   struct Chunk {
     int k0, k1, total, kj;
@@ -412,17 +420,20 @@ __device__ __forceinline__ uint64_t pull_small_w(const DevGraph& G, const MState
   auto chunk_at = [&](int k0) {
     Chunk c;
     const int eb = __builtin_amdgcn_readlane(excl, k0);
+    const int q = eb >> 6, sh = eb & 63;
+    const uint64_t w0 = ends[q], w1 = ends[q + 1];
     const bool inr = ok && lane >= k0 && inc - eb <= 64;
     const uint64_t fit = __ballot(inr);
     c.k1 = k0 + (int)__popcll(fit);
     c.total = __builtin_amdgcn_readlane(inc, c.k1 - 1) - eb;
-    const int e = inc - eb;
-    const uint64_t starts = 1ull | wave_or64(inr && e < c.total ? (1ull << e) : 0ull);
+    const uint64_t win =
+        readlane64(sh ? (w0 >> sh) | (w1 << (64 - sh)) : w0, 0);
+    const uint64_t starts = 1ull | (c.total >= 64 ? win : win & ((1ull << c.total) - 1));
     const int r = (int)__popcll(starts & bits_upto(lane));
     c.kj = k0 + r - 1;
     c.k0 = k0;
     c.starts = starts;
-    c.pos = (int64_t)__shfl(s, c.kj) + (eb + lane - __shfl(excl, c.kj));
+    c.pos = (int64_t)__shfl(sx, c.kj) + eb + lane;
     return c;
   };
   // c0: the chunk being walked; c1: its records are in flight; the adjacency

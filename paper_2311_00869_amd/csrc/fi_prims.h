@@ -55,6 +55,18 @@ __device__ __forceinline__ T wave_reduce(T x, Op op) {
   }
 }
 
+// Inclusive prefix sum over the wave: row shifts by 1, 2, 4 and 8 lanes, then
+// the row broadcasts as above.  Every lane of the wave must be active.
+__device__ __forceinline__ int wave_incl_sum_i32(int x) {
+  x += (int)dpp32<0x111, 0xF>((uint32_t)x, 0u);
+  x += (int)dpp32<0x112, 0xF>((uint32_t)x, 0u);
+  x += (int)dpp32<0x114, 0xF>((uint32_t)x, 0u);
+  x += (int)dpp32<0x118, 0xF>((uint32_t)x, 0u);
+  x += (int)dpp32<0x142, 0xA>((uint32_t)x, 0u);
+  x += (int)dpp32<0x143, 0xC>((uint32_t)x, 0u);
+  return x;
+}
+
 __device__ __forceinline__ uint32_t wave_or_u32(uint32_t x) {
   return wave_reduce<false>(x, [](uint32_t a, uint32_t b) { return a | b; });
 }

@@ -140,6 +140,7 @@ struct MS {
   uint64_t hbest[64 * W];
   uint64_t tacc[3][64 * W];
   TW<W> pw[NT / 64][4 * 64];  // per wave: small rows' wanted trees and outcomes, edge states
+  uint64_t pe[NT / 64][kSmall + 1];  // per wave: where the small rows' edges start a row
 };
 
 // Move the LDS staging list into a global list (one reservation per block).
@@ -624,8 +625,8 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
           if (b * 64 >= nl) break;
           const int ne = (int)min<int64_t>(64, nl - b * 64);
           const uint64_t r =
-              pull_small_w<W>(G, A.S, b * 64 + lane < nl ? pln[b * 64 + lane] : 0, ne, pp, p, valid,
-                              km, push, sh.pw[wave], cnt, deg, fin);
+              pull_small_w<W, kSmall>(G, A.S, b * 64 + lane < nl ? pln[b * 64 + lane] : 0, ne, pp,
+                                      p, valid, km, push, sh.pw[wave], sh.pe[wave], cnt, deg, fin);
           if (lane == 0) rln[b] = r;
         }
         // medium rows: block b owns rows b, b + nb, ...; its waves draw them
