@@ -84,6 +84,39 @@ def load_traffic(workload: str):
     return d
 
 
+def gather_probe(fr, torch, g, reps=5):
+    """The neighbour gathers of one dense pull level alone (fi_probe_gather):
+    every CSR entry reads 32 bytes of its neighbour's 64-byte record, in CSR
+    order; then as many reads of uniform random records.  Median of reps
+    launches, timed with events on the launch stream."""
+    import numpy as np
+
+    n, nnz = int(g.n), int(g.col.shape[0])
+    rec = torch.empty(n * 16, dtype=torch.int32, device="cuda")  # 64 bytes per vertex
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    col = torch.from_numpy(np.ascontiguousarray(g.col, dtype=np.int32)).cuda()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(0)
+    uni = torch.randint(0, n, (nnz,), dtype=torch.int32, device="cuda", generator=gen)
+    s = torch.cuda.current_stream()
+    out = {"records": n, "record_bytes": 64, "bytes_per_gather": 32, "gathers": nnz}
+    for name, idx in (("csr_order", col), ("uniform", uni)):
+        fr.probe_gather(idx, rec, sink, stream=s)
+        ts = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            fr.probe_gather(idx, rec, sink, stream=s)
+            e1.record(s)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = sorted(ts)[reps // 2]
+        out[name] = {"ms": round(ms, 3), "G_gathers_per_s": round(nnz / ms / 1e6, 2)}
+    del rec, sink, col, uni
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -240,6 +273,9 @@ def main():
         "model_unbatched_GBps": round(mb["unbatched_bytes_per_launch"] / avg_launch_s / 1e9, 1),
         "avg_launch_ms": round(avg_launch_s * 1e3, 3), "launches": launches,
     }
+
+    if path_used in (4, 5):
+        roofline["gather_probe"] = gather_probe(fr, torch, g)
 
     sched_used = G.get_schedule()
     extra = {}

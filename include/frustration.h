@@ -486,6 +486,19 @@ int fi_prof_read(fi_graph* g, int kernel, double* out_ms, int64_t* out_launches)
  * and keys, 8 cloud insert.  NULL turns the log off. */
 int fi_prof_phases(fi_graph* g, uint64_t* d_log, int64_t cap);
 
+/* Measurement aid, not part of the method: the neighbour gathers of one
+ * dense pull level of the multi-tree sweep, alone.  For every e < count,
+ * reads the first 32 bytes (two 16-byte loads) of the 64-byte record
+ * min(d_idx[e] & 0x7FFFFFFF, n_records - 1) of d_records (device,
+ * 64 * n_records bytes, 16-byte aligned) and discards them; d_sink (device,
+ * one uint32) is written only with probability 2^-32, so that the loads are
+ * kept.  With a graph's adjacency (col, in CSR order) as d_idx it times what
+ * the memory system needs for one level's gathers; with uniform random
+ * indices, the random-access ceiling of such reads.  FI_EINVAL for count < 0,
+ * n_records outside 1 .. 2^31 or a missing pointer. */
+int fi_probe_gather(const uint32_t* d_idx, int64_t count, const void* d_records, int64_t n_records,
+                    uint32_t* d_sink, void* stream);
+
 const char* fi_strerror(int code);
 
 #ifdef __cplusplus

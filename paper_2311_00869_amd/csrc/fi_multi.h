@@ -68,6 +68,21 @@ __device__ __forceinline__ void take_min(uint64_t& best, uint32_t key, uint32_t 
   if (key <= (uint32_t)(best >> 32)) best = ((uint64_t)key << 32) | lo;
 }
 
+// One hit edge j of a row walk (the neighbour's key hash Hj, the candidate's
+// low half lo): every lane computes its tree's key and keeps it as in
+// take_min if its tree is in the edge's tree mask f_w.  The mask only selects,
+// so the execution mask never changes inside a walk.
+template <int W, class TWW>
+__device__ __forceinline__ void walk_edge(uint64_t* best, const TWW& F, int j, uint32_t Hj,
+                                          uint32_t lo, const KeyMix* km) {
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const uint32_t key = vkey_of(km[w], Hj);
+    const bool take = lane_bit(readlane64(F.w[w], j)) & (key <= (uint32_t)(best[w] >> 32));
+    best[w] = take ? (((uint64_t)key << 32) | lo) : best[w];
+  }
+}
+
 // A value every lane holds alike (a scalar), copied into a vector register
 // once, so that several selects under different execution masks share it.
 __device__ __forceinline__ uint32_t to_vgpr(uint32_t s) {
@@ -285,9 +300,7 @@ __device__ __forceinline__ void pull_edges_w(const uint32_t* adj, const uint64_t
       hits &= hits - 1;
       const uint32_t Hj = __builtin_amdgcn_readlane(H, j);
       const uint32_t lo = to_vgpr(kPending | (uint32_t)j);
-#pragma unroll
-      for (int w = 0; w < W; ++w)
-        if (lane_bit(readlane64(F.w[w], j))) take_min(best[w], vkey_of(km[w], Hj), lo);
+      walk_edge<W>(best, F, j, Hj, lo, km);
     }
     // minima found in this chunk take their state
 #pragma unroll
@@ -532,9 +545,7 @@ __device__ __forceinline__ uint64_t pull_small_w(const DevGraph& G, const MState
         rh &= rh - 1;
         const uint32_t Hj = __builtin_amdgcn_readlane(H, jj);
         const uint32_t lo = to_vgpr(kPending | (uint32_t)jj);
-#pragma unroll
-        for (int w = 0; w < W; ++w)
-          if (lane_bit(readlane64(F.w[w], jj))) take_min(best[w], vkey_of(km[w], Hj), lo);
+        walk_edge<W>(best, F, jj, Hj, lo, km);
       }
       keep();
     }

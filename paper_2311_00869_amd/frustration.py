@@ -35,7 +35,7 @@ SYMBOLS = (
     "fi_bcloud_min", "fi_bcloud_stats", "fi_edge_list", "fi_switch_list", "fi_sweep_stats",
     "fi_graphl_descend", "fi_graphl_aux_size", "fi_graphl_scales", "fi_set_sampler",
     "fi_get_sampler", "fi_clean_workspace_size", "fi_clean", "fi_clean_no_alloc",
-    "fi_batch_cloud_read", "fi_prof_phases",
+    "fi_batch_cloud_read", "fi_prof_phases", "fi_probe_gather",
 )
 CLEAN_NO_ALLOC_MAX_ENTRIES = 1_000_000  # FI_CLEAN_NO_ALLOC_MAX_ENTRIES
 
@@ -124,6 +124,7 @@ def load_library(path: str = LIB_PATH):
             "fi_clean_no_alloc": ([i32, i64, vp, vp, vp, vp, vp, vp, P(i64), vp], c.c_int),
             "fi_batch_cloud_read": ([vp, i32, vp, i64, P(i64), vp], c.c_int),
             "fi_prof_phases": ([vp, vp, i64], c.c_int),
+            "fi_probe_gather": ([vp, i64, vp, i64, vp, vp], c.c_int),
             "fi_get_sampler": ([vp, P(i32)], c.c_int),
         }
         for name, (args, res) in sig.items():
@@ -166,6 +167,21 @@ def nwords(n: int) -> int:
 def words_to_numpy(t) -> np.ndarray:
     """int64 device words -> numpy uint64."""
     return t.detach().cpu().numpy().view(np.uint64)
+
+
+def probe_gather(idx, records, sink, stream=None):
+    """Measurement aid (fi_probe_gather): read the first 32 bytes of the 64-byte
+    record idx[e] of records for every e, as one dense pull level gathers its
+    neighbours.  idx: int32 device tensor; records: a device tensor of
+    64 * n_records bytes; sink: a device tensor of at least 4 bytes."""
+    lib = load_library()
+    if idx.dtype != torch.int32 or not idx.is_contiguous():
+        raise ValueError("idx must be a contiguous int32 tensor")
+    nbytes = records.numel() * records.element_size()
+    if nbytes % 64 or not records.is_contiguous() or sink.numel() * sink.element_size() < 4:
+        raise ValueError("records must hold whole 64-byte records; sink at least 4 bytes")
+    _check(lib.fi_probe_gather(_ptr(idx), idx.numel(), _ptr(records), nbytes // 64, _ptr(sink),
+                               _stream_ptr(stream)), "probe_gather")
 
 
 def clean(n: int, src, dst, sign, device="cuda", stream=None, no_alloc: bool = False):

@@ -117,3 +117,16 @@ def test_clean_no_alloc_rejects_sizes_on_the_host():
     assert lib.fi_clean_no_alloc(10, 5, None, fake, fake, fake, fake, fake, counts, None) == -1
     hdr = open(HEADER).read()
     assert f"#define FI_CLEAN_NO_ALLOC_MAX_ENTRIES {fr.CLEAN_NO_ALLOC_MAX_ENTRIES}" in hdr
+
+
+def test_gather_probe_rejects_bad_arguments_on_the_host():
+    # the measurement aid checks its arguments before any device work, and an
+    # empty probe is a no-op
+    lib = fr.load_library()
+    fake = ctypes.c_void_p(256)
+    assert lib.fi_probe_gather(fake, -1, fake, 4, fake, None) == -1
+    assert lib.fi_probe_gather(fake, 8, fake, 0, fake, None) == -1
+    assert lib.fi_probe_gather(fake, 8, fake, 2**31 + 1, fake, None) == -1
+    assert lib.fi_probe_gather(None, 8, fake, 4, fake, None) == -1
+    assert lib.fi_probe_gather(fake, 8, fake, 4, None, None) == -1
+    assert lib.fi_probe_gather(None, 0, None, 4, fake, None) == 0

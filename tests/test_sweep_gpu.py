@@ -476,3 +476,21 @@ def test_phase_log_records_every_pass_and_changes_nothing():
     levels = {lv for p, lv, _ in recs if p == 5}
     assert min(levels) == 1 and max(levels) >= 3
     G.close()
+
+
+def test_gather_probe_runs_and_clamps_indices():
+    # the measurement aid reads records only: indices past the table are
+    # clamped to its last record, and the sink keeps its value (the loads'
+    # xor would have to equal one 32-bit constant to store)
+    from paper_2311_00869_amd import frustration as fr
+    g = synth.chung_lu(100000, 500000, 2.3, 0, p_pos=0.85)
+    col = torch.from_numpy(np.ascontiguousarray(g.col, dtype=np.int32)).cuda()
+    rec = torch.zeros(g.n * 16, dtype=torch.int32, device="cuda")
+    sink = torch.full((1,), 7, dtype=torch.int32, device="cuda")
+    fr.probe_gather(col, rec, sink)
+    far = torch.full((1000,), 0x7FFFFFFF, dtype=torch.int32, device="cuda")
+    small = torch.zeros(16 * 16, dtype=torch.int32, device="cuda")
+    fr.probe_gather(far, small, sink)
+    fr.probe_gather(col[:0], rec, sink)
+    torch.cuda.synchronize()
+    assert int(sink.item()) == 7
