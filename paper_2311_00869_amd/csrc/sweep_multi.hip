@@ -46,7 +46,12 @@ namespace {
 
 using namespace mt;
 
-constexpr int kStageM = 2048;      // LDS staging entries for light list appends
+constexpr int kStageM = 2048;      // LDS staging entries for list appends
+// Small-row staging entries: each flush is one global reservation, so
+// 1,024-thread workgroups (one per CU) stage three times as many; smaller
+// workgroups keep kStageM and two workgroups per CU.
+template <int NT>
+constexpr int stage_small() { return NT >= 1024 ? 3 * kStageM : kStageM; }
 constexpr int kPushCost = 32;      // push while kPushCost * frontier edges < unfinished edges
 constexpr int kSmall = 32;         // rows up to this many edges are pulled 64 vertices per wave
 constexpr int kMedChunk = 4;       // medium frontier rows per push unit (at most 8,192 edges)
@@ -126,7 +131,7 @@ struct MS {
   int start[NT];
   uint64_t base[NT * W];
   int scan[NT / 64 + 1];
-  int32_t q[kStageM];   // staging: small rows
+  int32_t q[stage_small<NT>()];  // staging: small rows
   int32_t q2[kStageM];  // staging: medium rows
   uint32_t qn, qn2;
   uint32_t bnext;       // next small-row batch of the block
@@ -560,7 +565,8 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
             }
             mlist(first, v, dv, sh, phn, rf);
             __syncthreads();
-            if (sh.qn > kStageM - NT || sh.qn2 > kStageM - NT) mflush<NT>(sh, pln, pmn, rf);
+            if (sh.qn > stage_small<NT>() - NT || sh.qn2 > kStageM - NT)
+              mflush<NT>(sh, pln, pmn, rf);
           }
           __syncthreads();
         }
@@ -588,7 +594,8 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
           const int32_t v = (int32_t)(w * 64 + lane);
           mlist(in, v, in ? r1 - r0 : 0, sh, phn, rf);
           __syncthreads();
-          if (sh.qn > kStageM - NT || sh.qn2 > kStageM - NT) mflush<NT>(sh, pln, pmn, rf);
+          if (sh.qn > stage_small<NT>() - NT || sh.qn2 > kStageM - NT)
+            mflush<NT>(sh, pln, pmn, rf);
           w += wstep;
           bits = bn;
           r0 = q0;
