@@ -70,8 +70,9 @@ __device__ __forceinline__ void take_min(uint64_t& best, uint32_t key, uint32_t 
 
 // One hit edge j of a row walk (the neighbour's key hash Hj, the candidate's
 // low half lo): every lane computes its tree's key and keeps it as in
-// take_min if its tree is in the edge's tree mask f_w.  The mask only selects,
-// so the execution mask never changes inside a walk.
+// take_min if its tree is in the edge's tree mask (word w of F held by lane
+// j).  The mask only selects, so the execution mask never changes inside a
+// walk.
 template <int W, class TWW>
 __device__ __forceinline__ void walk_edge(uint64_t* best, const TWW& F, int j, uint32_t Hj,
                                           uint32_t lo, const KeyMix* km) {
@@ -384,7 +385,7 @@ __device__ __forceinline__ bool settle_w(const MState& A, int32_t v, const TW<W>
 }
 
 // One wave pulls ne <= 64 vertices (lane k < ne holds vertex v; every row has
-// between 1 and 64 edges) and returns the entries some tree reached.
+// between 1 and DMAX edges) and returns the entries some tree reached.
 // The rows are walked in chunks of as many whole rows as fit in 64 lanes, in
 // a two-stage pipeline: while the edges of one chunk are walked, the next
 // chunk's records are in flight (its adjacency was read while this chunk's
