@@ -164,8 +164,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU: every box here has one MI355X, and the sweep shards "
-              "trees across GPUs only by design (see the multi-GPU notes); use --gpus 1.",
+        print("bench.py measures one GPU: sharding the trees of a sweep across GPUs is a "
+              "design (the multi-GPU notes), not a measured path; use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 

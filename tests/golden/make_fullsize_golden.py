@@ -2,7 +2,7 @@
 
 Runs only the CPU oracle (oracle/) on the seeded synthetic graphs, so that
 the GPU tests can check the HIP path at full size without running the oracle
-on the GPU machine.  Trees are independent, so each worker process sweeps one
+beside them.  Trees are independent, so each worker process sweeps one
 tree at a time (the graph is made once and shared by fork), and the cloud is
 joined from the per-tree rows by oracle.cloud_from_trees.
 
