@@ -9,7 +9,7 @@
 //
 // What it follows (Shebaro & Tesic, "Scaling Frustration Index and
 // Corresponding Balanced State Discovery for Real Signed Graphs"):
-//   * Alg. alg-index (graphBpp driver): per sampled tree, balance the graph,
+//   * Alg. alg-index (graphBpp, the outer loop): per sampled tree, balance the graph,
 //     count the sign differences, turn the balanced state into a key, and
 //     insert-or-increment it in the frustration cloud; return min S.
 //   * Alg. alg-balance (graphB+ balancing): for every non-tree edge, flip it
