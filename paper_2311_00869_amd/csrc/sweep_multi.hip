@@ -54,6 +54,7 @@ template <int NT>
 constexpr int stage_small() { return NT >= 1024 ? 3 * kStageM : kStageM; }
 constexpr int kPushCost = 32;      // push while kPushCost * frontier edges < unfinished edges
 constexpr int kSmall = 32;         // rows up to this many edges are pulled 64 vertices per wave
+static_assert(stage_small<1024>() / (kSmall + 1) <= kStageM, "sparse listing: medium rows");
 constexpr int kMedChunk = 4;       // medium frontier rows per push unit (at most 8,192 edges)
 constexpr int kPlanes = 8;         // bit-sliced counter planes (flushed before 255 edges)
 constexpr int kCountBatch = 4;     // edges per lane in flight in the count
@@ -140,7 +141,7 @@ struct MS {
   int hidx;
   int2 heavy;
   uint64_t cnt, deg, fin;
-  int mode, active;
+  int mode, active, sparse;
   uint32_t nl, nm, nh, hunits;
   uint64_t hbest[64 * W];
   uint64_t tacc[3][64 * W];
@@ -449,6 +450,8 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
         const uint64_t unf = load_agent(ctl + cUNF);
         sh.active = reached > 0;
         sh.mode = (uint64_t)kPushCost * fdeg < unf ? 1 : 2;
+        // every unfinished vertex has an edge, so unf bounds their number
+        sh.sparse = unf <= (uint64_t)stage_small<NT>();
       }
       __syncthreads();
       if (!uni(sh.active)) break;
@@ -569,6 +572,27 @@ __global__ void __launch_bounds__(NT) k_sweep_multi(DevGraph G, MArgs A) {
               mflush<NT>(sh, pln, pmn, rf);
           }
           __syncthreads();
+        }
+      } else if (uni(sh.sparse)) {
+        // every vertex some tree has not visited yet, when they are at most as
+        // many as a workgroup's small-row staging holds (medium rows, of more
+        // than kSmall edges, are then fewer than its medium-row staging holds),
+        // so that no workgroup's staging can overflow: each wave reads 64
+        // bitmap words at once and lists the vertices of the nonzero ones,
+        // with no barrier between words
+        const int64_t wstep = (int64_t)nb * NW;
+        for (int64_t x0 = (int64_t)rank * NW + wave; x0 < nw; x0 += 64 * wstep) {
+          const int64_t x = x0 + (int64_t)lane * wstep;
+          const uint64_t bx = x < nw ? A.S.unf[x] : 0ull;
+          uint64_t nz = __ballot(bx != 0ull);
+          while (nz) {
+            const int k = __builtin_ctzll(nz);
+            nz &= nz - 1;
+            const uint64_t bits = readlane64(bx, k);
+            const int64_t vx = (x0 + (int64_t)k * wstep) * 64 + lane;
+            const bool in = (bits >> lane) & 1;
+            mlist(in, (int32_t)vx, in ? rp[vx + 1] - rp[vx] : 0, sh, phn, rf);
+          }
         }
       } else {
         // every vertex some tree has not visited yet; the bitmap word and the
